@@ -1,0 +1,382 @@
+"""Triple-tree (multi-tree) Axilrod-Teller potential on the CPU - oracle side.
+
+TEST INFRASTRUCTURE ONLY.
+
+This is the paper's algorithm written out in its own order, for n = 3:
+
+  1. bottom-up: BuildKdTree (Algorithm 1, ``oracle.kdtree``); at expansion
+     order p = 0 a node's moment is its point count (Section 4);
+  2. approximation: MTPotentialCanonical over node triples (Algorithm 2),
+     started at (root, root, root).  For each canonical triple, in order:
+       a. deterministic prune (Section 4 and Section 4.1, the hybrid rule of
+          the deterministic-prune equation): Summarize adds T_i * phi(c1,c2,c3)
+          to node P_i and raises the running lower bound by
+          delta^l_i = T_i * phi_lo;
+       b. Monte Carlo prune (Algorithms 3 and 4 with the relative-error
+          termination rule, committed by Algorithm 5);
+       c. if all three nodes are leaves: the exhaustive base case
+          MTPotentialBase;
+       d. otherwise: split and recurse on the canonical children;
+  3. top-down: node accumulators are pushed to their points (Section 3).
+
+Readings taken where the paper is silent, garbled or does not fit the
+Axilrod-Teller potential:
+  * Canonical triples.  A triple (P1, P2, P3) is kept in depth-first order
+    with every two nodes equal or disjoint; its case is (a) all equal,
+    (b) P1 = P2 < P3, (c) P1 < P2 = P3, (d) all distinct (the four-case
+    figure of Section 3).  The redundancy rule of Section 3 is printed with
+    the inequality reversed; triples that it is meant to discard are never
+    generated here, because children are emitted only in canonical order.
+  * Splitting.  Every non-leaf node of the triple is split at once and the
+    children are emitted in canonical order ((a) -> LLL, LLR, LRR, RRR;
+    (b) -> {LL, LR, RR} x {B_L, B_R}; ...).  This partitions the particle
+    triples exactly, as the proofs of Section 5 assume (up to 8 sub-calls).
+  * T_i (tuples through a fixed point of P_i, Section 4.1):
+        (a) C(n-1, 2);
+        (b) x in A: (n_A - 1) n_B, x in B: C(n_A, 2);
+        (c) x in A: C(n_B, 2), x in B: n_A (n_B - 1);
+        (d) the product of the other two counts;
+    T_root = C(N - 1, 2).
+  * Bounds for Axilrod-Teller.  The paper's bound assumes a monotone
+    potential; Axilrod-Teller is sign-indefinite.  Its angular factor
+    1 + 3 cos cos cos lies in [-2, 11/8] (collinear, equilateral), so with
+    R^u = 1 / (d^l_12 d^l_13 d^l_23)^3 every phi of the triple, and phi at
+    the centroids, lies in [-2 R^u, 11/8 R^u]: span = 27/8 R^u and
+    phi_lo = -2 R^u.  Only case (d) with all d^l > 0 can be pruned this way.
+  * Running lower bound Phi^l.  LB(x) accumulates the lower bounds of
+    everything already credited to x (exact base-case values, delta^l of
+    deterministic prunes, T_i (mu - z sigma_mu) of Monte Carlo prunes);
+    Phi^l(P) = min over x in P of LB(x).  For a sign-indefinite potential
+    this is the paper's running sum, not a bound on the final total.
+  * Monte Carlo termination (relative form): stop once m >= m_min and
+        z sigma_mu <= (eps (Phi^l(P_i) + T_i (mu - z sigma_mu)) + tau) / T_root,
+    i.e. the per-tuple error allowance of the deterministic rule; the
+    printed equation drops T_i from the eps term while the proof of
+    Theorem 5.2 keeps it.  A point passes iff this holds with m >= m_min
+    samples, m <= m_limit.  MC is tried only if alpha > 0 and
+    zeta * m_limit <= min_i T_i.  Defaults: m_limit = 128, zeta = 4,
+    m_min = 30 (the rule of thumb quoted after Theorem 4.1).
+  * z = z_{alpha/2}, the two-sided normal quantile; beta = alpha in
+    Algorithm 5.
+  * Samples are i.i.d. with replacement, each uniform over the T_i tuples of
+    the node triple that contain x, drawn from Philox4x32-10 with
+    counter (x, s, p1, p2) and key (p3, seed ^ seed >> 32), where x is the
+    depth-first rank of the point, s the sample number and p1..p3 the node
+    numbers.  A 64-bit uniform integer r is (w1 << 32 | w0); an index in
+    [0, M) is floor(r * M / 2^64).
+  * Test order: deterministic, then Monte Carlo, then base case or split.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from statistics import NormalDist
+
+import numpy as np
+
+from .kdtree import KdTree, box_min_dist, build_kdtree
+from .philox import philox4x32_10_np
+
+
+def comb2(n):
+    return n * (n - 1) // 2
+
+
+def at_phi_np(xi: np.ndarray, xj: np.ndarray, xk: np.ndarray) -> np.ndarray:
+    """Vectorized Axilrod-Teller phi (Section 1), cosines from dot products."""
+    dij = xj - xi
+    dik = xk - xi
+    djk = xk - xj
+    rij = np.sqrt(np.einsum("...d,...d->...", dij, dij))
+    rik = np.sqrt(np.einsum("...d,...d->...", dik, dik))
+    rjk = np.sqrt(np.einsum("...d,...d->...", djk, djk))
+    ci = np.einsum("...d,...d->...", dij, dik) / (rij * rik)
+    cj = -np.einsum("...d,...d->...", dij, djk) / (rij * rjk)
+    ck = np.einsum("...d,...d->...", dik, djk) / (rik * rjk)
+    r3 = (rij * rik * rjk) ** 3
+    return (1.0 + 3.0 * ci * cj * ck) / r3
+
+
+def canonical_case(p1: int, p2: int, p3: int) -> str:
+    if p1 == p2 == p3:
+        return "a"
+    if p1 == p2:
+        return "b"
+    if p2 == p3:
+        return "c"
+    return "d"
+
+
+def distinct_roles(p: tuple[int, int, int], n: tuple[int, int, int]) -> list[tuple[int, int, int]]:
+    """(node, T_i, slot) for each distinct node of a canonical triple, in order.
+
+    ``slot`` is the first position (0, 1, 2) the node takes in the triple.
+    """
+    p1, p2, p3 = p
+    n1, n2, n3 = n
+    case = canonical_case(p1, p2, p3)
+    if case == "a":
+        return [(p1, comb2(n1 - 1), 0)]
+    if case == "b":
+        return [(p1, (n1 - 1) * n3, 0), (p3, comb2(n1), 2)]
+    if case == "c":
+        return [(p1, comb2(n2), 0), (p2, n1 * (n2 - 1), 1)]
+    return [(p1, n2 * n3, 0), (p2, n1 * n3, 1), (p3, n1 * n2, 2)]
+
+
+def triple_index_arrays(case: str, r1: np.ndarray, r2: np.ndarray, r3: np.ndarray):
+    """All canonical particle triples (i, j, k) of a node triple, as rank arrays."""
+    if case == "a":
+        a = r1
+        if a.size < 3:
+            e = np.zeros(0, dtype=np.int64)
+            return e, e, e
+        ii, jj, kk = np.meshgrid(a, a, a, indexing="ij")
+        m = (ii < jj) & (jj < kk)
+        return ii[m], jj[m], kk[m]
+    if case == "b":
+        ii, jj, kk = np.meshgrid(r1, r1, r3, indexing="ij")
+        m = ii < jj
+        return ii[m], jj[m], kk[m]
+    if case == "c":
+        ii, jj, kk = np.meshgrid(r1, r2, r2, indexing="ij")
+        m = jj < kk
+        return ii[m], jj[m], kk[m]
+    ii, jj, kk = np.meshgrid(r1, r2, r3, indexing="ij")
+    return ii.ravel(), jj.ravel(), kk.ravel()
+
+
+def canonical_children(tree: KdTree, p: tuple[int, int, int]) -> list[tuple[int, int, int]]:
+    """Split every non-leaf node; children in canonical (depth-first) order."""
+    opts = []
+    for node in p:
+        opts.append([node] if tree.is_leaf(node) else [int(tree.left[node]), int(tree.right[node])])
+    seen = set()
+    out = []
+    for a in opts[0]:
+        for b in opts[1]:
+            for c in opts[2]:
+                t = tuple(sorted((a, b, c), key=lambda v: (tree.begin[v], v)))
+                if t in seen:
+                    continue
+                seen.add(t)
+                out.append(t)
+    out.sort(key=lambda t: (tree.begin[t[0]], tree.begin[t[1]], tree.begin[t[2]]))
+    return out
+
+
+def mc_draw(seed: int, p: tuple[int, int, int], x_rank: int, s: np.ndarray) -> np.ndarray:
+    """64-bit uniform integers for samples s of point x in node triple p."""
+    m = s.shape[0]
+    ctr = np.zeros((m, 4), dtype=np.uint64)
+    ctr[:, 0] = x_rank
+    ctr[:, 1] = s
+    ctr[:, 2] = p[0]
+    ctr[:, 3] = p[1]
+    key = np.zeros((m, 2), dtype=np.uint64)
+    key[:, 0] = p[2]
+    key[:, 1] = (seed ^ (seed >> 32)) & 0xFFFFFFFF
+    w = philox4x32_10_np(ctr, key).astype(np.uint64)
+    return (w[:, 1] << np.uint64(32)) | w[:, 0]
+
+
+def uniform_index(r: np.ndarray, m: int) -> np.ndarray:
+    """floor(r * m / 2^64) for 64-bit r and 0 < m < 2^63 (the high word of r * m)."""
+    mask = np.uint64(0xFFFFFFFF)
+    sh = np.uint64(32)
+    r = r.astype(np.uint64)
+    rh, rl = r >> sh, r & mask
+    mh, ml = np.uint64(m) >> sh, np.uint64(m) & mask
+    t = (rl * ml) >> sh
+    t1 = rh * ml + t
+    t2 = rl * mh + (t1 & mask)
+    return (rh * mh + (t1 >> sh) + (t2 >> sh)).astype(np.int64)
+
+
+def pair_from_index(t: np.ndarray, m: int) -> tuple[np.ndarray, np.ndarray]:
+    """Unordered pair (u < v) of [0, m) from its index t in [0, C(m, 2)), v-major."""
+    v = np.floor((1.0 + np.sqrt(1.0 + 8.0 * t.astype(np.float64))) / 2.0).astype(np.int64)
+    v = np.where(v * (v - 1) // 2 > t, v - 1, v)
+    v = np.where((v + 1) * v // 2 <= t, v + 1, v)
+    u = t - v * (v - 1) // 2
+    return u, v
+
+
+def sample_partners(case: str, slot: int, x_local: np.ndarray, n: tuple[int, int, int],
+                    r: np.ndarray) -> tuple[np.ndarray, np.ndarray, int, int]:
+    """Map uniform integers to the two partners of x (uniform over the T_i tuples).
+
+    ``slot`` is the triple position of x's node, ``x_local`` the offset of x
+    inside it (broadcast against ``r``).  Returns the partners' offsets
+    inside their nodes and the triple positions of those nodes.
+    """
+    n1, n2, n3 = n
+    if case == "a":  # a pair of distinct points of A minus x
+        u, v = pair_from_index(uniform_index(r, comb2(n1 - 1)), n1 - 1)
+        return u + (u >= x_local), v + (v >= x_local), 0, 0
+    if case == "b":
+        if slot == 0:  # x in A: one partner in A minus x, one in B
+            t = uniform_index(r, (n1 - 1) * n3)
+            u, v = t // n3, t % n3
+            return u + (u >= x_local), v, 0, 2
+        u, v = pair_from_index(uniform_index(r, comb2(n1)), n1)  # x in B: a pair in A
+        return u, v, 0, 0
+    if case == "c":
+        if slot == 0:  # x in A: a pair in B
+            u, v = pair_from_index(uniform_index(r, comb2(n2)), n2)
+            return u, v, 1, 1
+        t = uniform_index(r, n1 * (n2 - 1))  # x in B: one partner in A, one in B minus x
+        u, v = t // (n2 - 1), t % (n2 - 1)
+        return u, v + (v >= x_local), 0, 1
+    others = [s_ for s_ in (0, 1, 2) if s_ != slot]
+    nb = n[others[1]]
+    t = uniform_index(r, n[others[0]] * nb)
+    return t // nb, t % nb, others[0], others[1]
+
+
+@dataclass
+class MTResult:
+    phi: np.ndarray                # estimate, input order
+    lower: np.ndarray              # running lower bound LB(x), input order
+    coverage: np.ndarray           # tuples credited per point, input order (int64)
+    tree: KdTree
+    stats: dict = field(default_factory=dict)
+
+
+def multitree(x, eps: float, alpha: float, leaf_size: int, tau: float = 0.0, seed: int = 0,
+              m_limit: int = 128, zeta: float = 4.0, m_min: int = 30) -> MTResult:
+    x = np.asarray(x, dtype=np.float64)
+    n = x.shape[0]
+    if eps < 0 or tau < 0 or not (0.0 <= alpha < 1.0) or leaf_size < 1:
+        raise ValueError("bad multitree parameters")
+    tree = build_kdtree(x, leaf_size)
+    xs = x[tree.perm]  # depth-first order
+    t_root = comb2(n - 1) if n >= 1 else 0
+    z = NormalDist().inv_cdf(1.0 - alpha / 2.0) if alpha > 0 else math.inf
+    est = np.zeros(n)
+    lb = np.zeros(n)
+    cov = np.zeros(n, dtype=np.int64)
+    node_acc = np.zeros(tree.n_nodes)
+    st = dict(visited=0, det_prunes=0, mc_prunes=0, mc_failed=0, base_cases=0, base_triples=0,
+              mc_samples=0)
+    if n < 3:
+        return MTResult(np.zeros(n), np.zeros(n), cov, tree, st)
+
+    def pts(node):
+        return slice(int(tree.begin[node]), int(tree.end[node]))
+
+    def phi_l(node) -> float:
+        return float(lb[pts(node)].min())
+
+    stack = [(0, 0, 0)]
+    while stack:
+        p = stack.pop()
+        st["visited"] += 1
+        p1, p2, p3 = p
+        case = canonical_case(p1, p2, p3)
+        cnt = (int(tree.count[p1]), int(tree.count[p2]), int(tree.count[p3]))
+        roles = distinct_roles(p, cnt)
+
+        # (a) deterministic prune, case (d) only
+        if case == "d":
+            d12 = box_min_dist(tree.lo[p1], tree.hi[p1], tree.lo[p2], tree.hi[p2])
+            d13 = box_min_dist(tree.lo[p1], tree.hi[p1], tree.lo[p3], tree.hi[p3])
+            d23 = box_min_dist(tree.lo[p2], tree.hi[p2], tree.lo[p3], tree.hi[p3])
+            if d12 > 0 and d13 > 0 and d23 > 0:
+                ru = 1.0 / (d12 * d13 * d23) ** 3
+                phi_lo = -2.0 * ru
+                span = 3.375 * ru
+                allow = min(phi_l(node) + t * phi_lo for node, t, _ in roles)
+                if span <= (eps * allow + tau) / t_root:
+                    phic = float(at_phi_np(tree.centroid[p1], tree.centroid[p2], tree.centroid[p3]))
+                    for node, t, _ in roles:
+                        node_acc[node] += t * phic
+                        lb[pts(node)] += t * phi_lo
+                        cov[pts(node)] += t
+                    st["det_prunes"] += 1
+                    continue
+
+        # (b) Monte Carlo prune (Algorithm 3 over the distinct nodes, Algorithm 4 per point)
+        if alpha > 0 and zeta * m_limit <= min(t for _, t, _ in roles):
+            ok = True
+            commits = []
+            for node, t, slot in roles:
+                base = int(tree.begin[node])
+                npts = cnt[slot]
+                plo = phi_l(node)
+                xl = np.arange(npts, dtype=np.int64)[:, None]
+                xr = base + xl
+                r = np.stack([mc_draw(seed, p, int(base + q), np.arange(m_limit, dtype=np.uint64))
+                              for q in range(npts)])
+                u, v, su, sv = sample_partners(case, slot, xl, cnt, r)
+                f = at_phi_np(xs[xr], xs[tree.begin[p[su]] + u], xs[tree.begin[p[sv]] + v])
+                # Welford running mean and unbiased variance, sample by sample
+                mean = np.zeros(npts)
+                m2 = np.zeros(npts)
+                stop_m = np.full(npts, -1, dtype=np.int64)
+                mu_s = np.zeros(npts)
+                sg_s = np.zeros(npts)
+                passed = np.zeros(npts, dtype=bool)
+                for k in range(m_limit):
+                    m = k + 1
+                    d = f[:, k] - mean
+                    mean = mean + d / m
+                    m2 = m2 + d * (f[:, k] - mean)
+                    if m < 2:
+                        continue
+                    sig_mu = np.sqrt(m2 / (m - 1) / m)
+                    cond = z * sig_mu <= (eps * (plo + t * (mean - z * sig_mu)) + tau) / t_root
+                    fresh = (stop_m < 0) & ((cond & (m >= m_min)) | (m == m_limit))
+                    stop_m[fresh] = m
+                    mu_s[fresh] = mean[fresh]
+                    sg_s[fresh] = sig_mu[fresh]
+                    passed[fresh] = cond[fresh] & (m >= m_min)
+                # Algorithm 3 scans points in order and stops at the first failure
+                fail = np.nonzero(~passed)[0]
+                used = stop_m if fail.size == 0 else stop_m[: fail[0] + 1]
+                st["mc_samples"] += int(used.sum())
+                if fail.size:
+                    ok = False
+                    break
+                commits.append((base, t, mu_s, sg_s))
+            if ok:
+                for base, t, mu_s, sg_s in commits:
+                    sl = slice(base, base + mu_s.shape[0])
+                    est[sl] += t * mu_s
+                    lb[sl] += t * (mu_s - z * sg_s)
+                    cov[sl] += t
+                st["mc_prunes"] += 1
+                continue
+            st["mc_failed"] += 1
+
+        # (c) base case
+        if tree.is_leaf(p1) and tree.is_leaf(p2) and tree.is_leaf(p3):
+            ri, rj, rk = triple_index_arrays(case, np.arange(*pts(p1).indices(n)),
+                                             np.arange(*pts(p2).indices(n)),
+                                             np.arange(*pts(p3).indices(n)))
+            if ri.size:
+                f = at_phi_np(xs[ri], xs[rj], xs[rk])
+                for r_ in (ri, rj, rk):
+                    np.add.at(est, r_, f)
+                    np.add.at(lb, r_, f)
+                    np.add.at(cov, r_, 1)
+            st["base_cases"] += 1
+            st["base_triples"] += int(ri.size)
+            continue
+
+        # (d) split: push children so that the first canonical child is processed first
+        kids = canonical_children(tree, p)
+        for c in reversed(kids):
+            stack.append(c)
+
+    # top-down: node accumulators to their points
+    for node in range(tree.n_nodes):
+        if node_acc[node] != 0.0:
+            est[pts(node)] += node_acc[node]
+    out = np.empty(n)
+    out[tree.perm] = est
+    low = np.empty(n)
+    low[tree.perm] = lb
+    cv = np.empty(n, dtype=np.int64)
+    cv[tree.perm] = cov
+    return MTResult(out, low, cv, tree, st)

@@ -1,0 +1,39 @@
+"""Write the stored oracle values used by the GPU parity tests.
+
+Calls only ``workloads`` (seeded inputs) and ``oracle`` (CPU reference).
+Run from the repository root:  python tests/golden/make_golden.py
+"""
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+from oracle import direct  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def c2_samples():
+    """Direct Phi at 64 sampled particles of the 32^3 jittered lattice."""
+    x = workloads.jittered_lattice(32768, seed=2)
+    idx = workloads.sample_indices(32768, 64, seed=1002)
+    t = time.time()
+    phi = direct.phi(x, idx)
+    out = {
+        "workload": "jittered lattice 32^3, spacing 1.0, jitter 0.25, seed 2",
+        "n": 32768,
+        "sample_seed": 1002,
+        "indices": idx.tolist(),
+        "phi": [repr(float(v)) for v in phi],
+        "oracle_seconds": time.time() - t,
+    }
+    with open(os.path.join(HERE, "c2_direct_samples.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    c2_samples()
