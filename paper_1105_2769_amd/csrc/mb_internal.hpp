@@ -1,0 +1,76 @@
+// Host-side helpers shared by the library's translation units: error state,
+// HIP error mapping and stream-ordered scratch allocation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/mb.h"
+
+namespace mb {
+
+// Record a message for mb_last_error() and return the status.
+mb_status fail(mb_status st, const std::string &msg);
+void clear_error();
+
+// Map a HIP error to MB_ERR_DEVICE (or MB_ERR_OOM for allocation failures).
+mb_status hip_fail(hipError_t e, const char *what);
+
+#define MB_HIP(call)                                                 \
+    do {                                                             \
+        hipError_t mb_e_ = (call);                                   \
+        if (mb_e_ != hipSuccess) return ::mb::hip_fail(mb_e_, #call); \
+    } while (0)
+
+// Stream-ordered device scratch that frees itself on scope exit.
+struct Scratch {
+    void *ptr = nullptr;
+    hipStream_t stream = nullptr;
+    Scratch() = default;
+    Scratch(const Scratch &) = delete;
+    Scratch &operator=(const Scratch &) = delete;
+    ~Scratch() {
+        if (ptr) (void)hipFreeAsync(ptr, stream);
+    }
+    mb_status alloc(size_t bytes, hipStream_t s) {
+        stream = s;
+        hipError_t e = hipMallocAsync(&ptr, bytes ? bytes : 1, s);
+        if (e != hipSuccess) {
+            ptr = nullptr;
+            return hip_fail(e, "hipMallocAsync");
+        }
+        return MB_OK;
+    }
+    template <typename T>
+    T *as() const {
+        return static_cast<T *>(ptr);
+    }
+};
+
+// Result of the validation pass (device layout mirrors this struct).
+struct ValidateOut {
+    unsigned long long min_d2_bits;  // bit pattern of min |xi-xj|^2 (non-negative double)
+    int32_t nonfinite;               // nonzero if any coordinate is NaN or Inf
+    int32_t pad;
+    unsigned long long lo_key[3];    // order-preserving keys of the bounding box
+    unsigned long long hi_key[3];
+    // filled on the host after the copy back
+    double lo[3];
+    double hi[3];
+};
+
+// Enqueue validation and wait for it.  n >= 0.
+mb_status validate_points(const double *x, int64_t n, hipStream_t s, ValidateOut *out);
+
+// Enqueue phi[0:n] = 0.
+mb_status zero_doubles(double *p, int64_t n, hipStream_t s);
+
+// Direct (exhaustive) evaluation, no validation; phi is zeroed and
+// accumulated.  `scale` is a power of two applied to all coordinate
+// differences (the result is rescaled exactly).
+mb_status direct_launch(const double *x, int64_t n, int prec, double scale, double *phi,
+                        hipStream_t s);
+
+}  // namespace mb
