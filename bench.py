@@ -51,6 +51,9 @@ def main() -> int:
                     help="particles for the CPU-oracle leg (0: two per host thread)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prec", choices=["fp64", "fp32c", "both"], default="both")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (the "
+                         "reference kernel for scaling HBM byte counters), then exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -65,6 +68,15 @@ def main() -> int:
     import workloads
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration_mib:
+        nbytes = args.copy_calibration_mib << 20
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 3}), flush=True)
+        return 0
     n = args.n
     x_np = workloads.jittered_lattice(n, seed=2)
     x = torch.from_numpy(x_np).to(dev)

@@ -3,7 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "mb_internal.hpp"
@@ -27,6 +29,31 @@ mb_status hip_fail(hipError_t e, const char *what) {
     std::string msg = std::string(what) + ": " + hipGetErrorString(e);
     if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return fail(MB_ERR_OOM, msg);
     return fail(MB_ERR_DEVICE, msg);
+}
+
+size_t table_budget_bytes() {
+    static const size_t v = [] {
+        const char *e = std::getenv("MB_TABLE_BUDGET_MB");
+        long mb = e ? std::atol(e) : 2048;
+        if (mb < 1) mb = 1;
+        return (size_t)mb << 20;
+    }();
+    return v;
+}
+
+void device_pool_setup() {
+    static std::mutex mu;
+    static bool done[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+    std::lock_guard<std::mutex> lock(mu);
+    if (done[dev]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    done[dev] = true;
 }
 
 // Ratio limit between the bounding-box diagonal and the closest pair above

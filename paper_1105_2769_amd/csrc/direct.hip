@@ -1,55 +1,69 @@
 // Exhaustive per-particle Axilrod-Teller sum on gfx950 (the naive algorithm
 // of Section 6, definition in Section 1), plus input validation.
 //
-// Work decomposition.  Points are cut into blocks of 64 (I and J roles) and
-// tiles of 128 (K role).  A work unit is (I, J, K) with I <= J and the K tile
-// reaching past J; together the units cover every unordered triple i < j < k
-// exactly once, the global-index masks i < j, j < k, i < k inside a unit
-// removing the rest.  One 512-thread workgroup (8 wave64s) runs one unit:
+// Work decomposition.  A work unit is a block triple (I, J, K): an I block of
+// 8 * IPW points, a J block of 64 and a K tile of 256.  Units are enumerated
+// so that together they hold every unordered triple i < j < k exactly once;
+// inside a unit the global-index masks i < j < k < n drop the rest.  One
+// 512-thread workgroup (8 wave64s) runs one unit:
 //
-//   * lane l of every wave owns the two points k = K0 + l and K0 + 64 + l;
-//   * wave w owns the eight points i = I0 + 8w .. I0 + 8w + 7 and keeps the
-//     pair terms (i, k) of its 16 (i, k) combinations in registers;
-//   * j runs over the J block in chunks of 16: the workgroup stages the
-//     pair terms (i, j) (same for all lanes: LDS broadcast reads) and
-//     (j, k) (one per lane) of the chunk in LDS.
+//   * lane l owns the four points k = K0 + l + 64 m, m = 0..3;
+//   * wave w owns IPW points i and keeps the (i, k) pair terms of its
+//     4 * IPW combinations in registers for the whole unit;
+//   * the (i, j) pair terms do not depend on the lane.  A table kernel writes
+//     them to HBM per (I, J) block pair, and the triple kernel reads them
+//     with scalar loads into SGPRs, issued one j ahead of their use;
+//   * the (j, k) terms (one per lane) are staged in LDS per chunk of 16 j
+//     and also read one j ahead into registers.
 //
 // Inner step for one triple, with (a, qa, wa) the (i, j) terms, (g, qg, wg)
 // the (i, k) terms and (b, qb, ob = 3/8 / b) the (j, k) terms:
 //
 //   phi = qb * psi,   psi = qa qg + ob (wa wg) (a + g - b)(b^2 - (a - g)^2)
 //
-// Per-particle sums: Phi_k += qb * sum_i psi (register), Phi_i += qb * psi
-// (register array), Phi_j += sum over lanes and waves of qb * sum_i psi
-// (LDS atomics into a per-(j, k) slot, reduced once per chunk).  The three
-// sums are pushed to Phi with FP64 atomics once per unit.
+// which is 11 VALU operations per triple including the sums
+// Phi_k += qb * sum_i psi (register), Phi_i += qb * psi (register array) and
+// Phi_j += sum over lanes, waves of sum_k qb * sum_i psi (one LDS atomic per
+// lane and j into a per-(j, lane) slot, reduced once per chunk).  Unit sums
+// go to Phi with FP64 atomics.
 #include "at_device.hpp"
 #include "mb_internal.hpp"
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 namespace mb {
 namespace {
 
-constexpr int kB = 64;           // points per I and J block
-constexpr int kKT = 128;         // points per K tile (two per lane)
-constexpr int kNW = 8;           // waves per workgroup
-constexpr int kIPW = kB / kNW;   // i points per wave
-constexpr int kJC = 16;          // j points per LDS chunk
+constexpr int kNW = 8;              // waves per workgroup
 constexpr int kThreads = kNW * 64;
-constexpr int kXS = kB + kB + kKT;
+constexpr int kB = 64;              // points per J block
+constexpr int kKT = 256;            // points per K tile (four per lane)
+constexpr int kKR = kKT / 64;       // k points per lane
+constexpr int kJC = 16;             // j points per LDS chunk
+
+// Tile shape per arithmetic type: i points per wave.
+template <typename T> struct DirectShape;
+template <> struct DirectShape<double> { static constexpr int IPW = 4; };
+template <> struct DirectShape<float> { static constexpr int IPW = 8; };
 
 template <typename T>
 struct DirectLds {
-    double xs[3][kXS];            // coordinates of the I block, J block and K tile
-    T ua[kJC][kB], uq[kJC][kB], uw[kJC][kB];      // (i, j) terms of the chunk
-    T cb[kJC][kKT], cq[kJC][kKT], co[kJC][kKT];   // (j, k) terms of the chunk
-    double pj[kJC][kKT];          // Phi_j partials per (j, k), summed over waves
-    double pjacc[kB];             // Phi_j of the unit
-    double kacc[kKT];             // Phi_k of the unit
+    static constexpr int IB = kNW * DirectShape<T>::IPW;
+    static constexpr int XS = IB + kB + kKT;
+    double xs[3][XS];                              // coordinates of the I, J blocks and K tile
+    T cb[kJC][kKT], cq[kJC][kKT], co[kJC][kKT];    // (j, k) terms of the chunk
+    double pj[kJC][64];                            // Phi_j partials per (j, lane), all waves
+    double pjacc[kB];                              // Phi_j of the unit
+    double kacc[kKT];                              // Phi_k of the unit
 };
+
+// Units of J block b: a in [0, na_b) times t in [b / 4, nt).
+__host__ __device__ __forceinline__ int units_a(int b, int ib, int na) {
+    return min(na, (64 * b + 62) / ib + 1);
+}
 
 __device__ __forceinline__ void decode_unit(int64_t u, const int64_t *__restrict__ off, int nb,
                                             int nt, int &a, int &b, int &t) {
@@ -59,11 +73,21 @@ __device__ __forceinline__ void decode_unit(int64_t u, const int64_t *__restrict
         if (off[mid] <= u) lo = mid; else hi = mid;
     }
     b = lo;
-    int64_t rem = u - off[b];
-    int tc = nt - (b >> 1);
+    const int64_t rem = u - off[b];
+    const int tc = nt - (b >> 2);
     a = (int)(rem / tc);
-    t = (b >> 1) + (int)(rem % tc);
+    t = (b >> 2) + (int)(rem % tc);
 }
+
+// s_waitcnt lgkmcnt(0) (vmcnt and expcnt left at their maxima), with
+// scheduling barriers so no memory operation moves across it.
+__device__ __forceinline__ void lgkm_wait_all() {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+__device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -71,46 +95,86 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// (i, j) pair-term table for J blocks b0 <= b < b0 + gridDim.y: block (a, b)
+// holds (a_ij, q_ij, w_ij) at [jl][il][3] for i = IB a + il, j = 64 b + jl,
+// masked unless i < j < n.
+template <typename T>
+__global__ __launch_bounds__(256) void pair_table_kernel(const double *__restrict__ x, int n,
+                                                         int na, int b0, double scale,
+                                                         T *__restrict__ tab) {
+    constexpr int IB = DirectLds<T>::IB;
+    const int a = blockIdx.x, b = b0 + blockIdx.y;
+    if (a >= units_a(b, IB, na)) return;
+    __shared__ double xa[3][IB], xb[3][kB];
+    const int tid = threadIdx.x;
+    if (tid < IB) {
+        const int i = a * IB + tid;
+        for (int c = 0; c < 3; ++c) xa[c][tid] = i < n ? x[3 * (int64_t)i + c] * scale : 0.0;
+    } else if (tid < IB + kB) {
+        const int j = b * kB + tid - IB;
+        for (int c = 0; c < 3; ++c) xb[c][tid - IB] = j < n ? x[3 * (int64_t)j + c] * scale : 0.0;
+    }
+    __syncthreads();
+    T *out = tab + ((int64_t)blockIdx.y * na + a) * (IB * kB * 3);
+    for (int e = tid; e < IB * kB; e += 256) {
+        const int jl = e / IB, il = e % IB;
+        const int i = a * IB + il, j = b * kB + jl;
+        double pa, pq, pw, pia;
+        pair_terms(xb[0][jl] - xa[0][il], xb[1][jl] - xa[1][il], xb[2][jl] - xa[2][il],
+                   (i < j) && (j < n), pa, pq, pw, pia);
+        out[3 * e + 0] = (T)pa;
+        out[3 * e + 1] = (T)pq;
+        out[3 * e + 2] = (T)pw;
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads, 1) void direct_kernel(
-    const double *__restrict__ x, int n, int nb, int nt, const int64_t *__restrict__ unit_off,
-    int64_t n_units, double scale, double out_scale, double *__restrict__ phi) {
+    const double *__restrict__ x, int n, int na, int nb, int nt,
+    const int64_t *__restrict__ unit_off, int64_t u_begin, int64_t u_end, int b0,
+    const T *__restrict__ utab, double scale, double out_scale, double *__restrict__ phi) {
+    constexpr int IPW = DirectShape<T>::IPW;
+    constexpr int IB = DirectLds<T>::IB;
     __shared__ DirectLds<T> s;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    constexpr int XI = 0, XJ = IB, XK = IB + kB;
 
-    for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+    for (int64_t u = u_begin + blockIdx.x; u < u_end; u += gridDim.x) {
         int a, b, t;
         decode_unit(u, unit_off, nb, nt, a, b, t);
-        const int I0 = a * kB, J0 = b * kB, K0 = t * kKT;
+        const int I0 = a * IB, J0 = b * kB, K0 = t * kKT;
+        const T *__restrict__ up =
+            utab + ((int64_t)(b - b0) * na + a) * (IB * kB * 3) + wave * (IPW * 3);
 
         __syncthreads();  // the previous unit is done with the LDS
-        if (tid < kXS) {
-            int p = tid < kB ? I0 + tid : (tid < 2 * kB ? J0 + tid - kB : K0 + tid - 2 * kB);
-            bool ok = p < n;
-            s.xs[0][tid] = ok ? x[3 * (int64_t)p + 0] * scale : 0.0;
-            s.xs[1][tid] = ok ? x[3 * (int64_t)p + 1] * scale : 0.0;
-            s.xs[2][tid] = ok ? x[3 * (int64_t)p + 2] * scale : 0.0;
+        for (int p = tid; p < DirectLds<T>::XS; p += kThreads) {
+            const int g = p < XJ ? I0 + p : (p < XK ? J0 + p - XJ : K0 + p - XK);
+            const bool ok = g < n;
+            s.xs[0][p] = ok ? x[3 * (int64_t)g + 0] * scale : 0.0;
+            s.xs[1][p] = ok ? x[3 * (int64_t)g + 1] * scale : 0.0;
+            s.xs[2][p] = ok ? x[3 * (int64_t)g + 2] * scale : 0.0;
         }
         if (tid < kKT) s.kacc[tid] = 0.0;
         __syncthreads();
 
-        // (i, k) pair terms of this wave, kept in registers for the whole unit
-        T ag[kIPW][2], aq[kIPW][2], aw[kIPW][2];
-        T acc_i[kIPW];
-        double acc_i64[kIPW];
+        // (i, k) pair terms of this wave, in registers for the whole unit
+        T ag[IPW][kKR], aq[IPW][kKR], aw[IPW][kKR];
+        T acc_i[IPW];
+        double acc_i64[IPW];
 #pragma unroll
-        for (int ii = 0; ii < kIPW; ++ii) {
-            const int il = wave * kIPW + ii;
+        for (int ii = 0; ii < IPW; ++ii) {
+            const int il = wave * IPW + ii;
             const int i = I0 + il;
 #pragma unroll
-            for (int kk = 0; kk < 2; ++kk) {
+            for (int kk = 0; kk < kKR; ++kk) {
                 const int kl = lane + 64 * kk;
                 const int k = K0 + kl;
                 double pa, pq, pw, pia;
-                pair_terms(s.xs[0][2 * kB + kl] - s.xs[0][il], s.xs[1][2 * kB + kl] - s.xs[1][il],
-                           s.xs[2][2 * kB + kl] - s.xs[2][il], (i < k) && (k < n), pa, pq, pw, pia);
+                pair_terms(s.xs[0][XK + kl] - s.xs[0][XI + il], s.xs[1][XK + kl] - s.xs[1][XI + il],
+                           s.xs[2][XK + kl] - s.xs[2][XI + il], (i < k) && (k < n), pa, pq, pw,
+                           pia);
                 ag[ii][kk] = (T)pa;
                 aq[ii][kk] = (T)pq;
                 aw[ii][kk] = (T)pw;
@@ -118,88 +182,108 @@ __global__ __launch_bounds__(kThreads, 1) void direct_kernel(
             acc_i[ii] = T(0);
             acc_i64[ii] = 0.0;
         }
-        double acck0 = 0.0, acck1 = 0.0;
+        double acck[kKR];
+#pragma unroll
+        for (int kk = 0; kk < kKR; ++kk) acck[kk] = 0.0;
 
         for (int jc = 0; jc < kB / kJC; ++jc) {
             __syncthreads();  // previous chunk's readers are done
-            for (int e = tid; e < kJC * kB; e += kThreads) {
-                const int jj = e / kB, il = e % kB;
-                const int jl = jc * kJC + jj;
-                const int i = I0 + il, j = J0 + jl;
-                double pa, pq, pw, pia;
-                pair_terms(s.xs[0][kB + jl] - s.xs[0][il], s.xs[1][kB + jl] - s.xs[1][il],
-                           s.xs[2][kB + jl] - s.xs[2][il], (i < j) && (j < n), pa, pq, pw, pia);
-                s.ua[jj][il] = (T)pa;
-                s.uq[jj][il] = (T)pq;
-                s.uw[jj][il] = (T)pw;
-            }
             for (int e = tid; e < kJC * kKT; e += kThreads) {
                 const int jj = e / kKT, kl = e % kKT;
                 const int jl = jc * kJC + jj;
                 const int j = J0 + jl, k = K0 + kl;
                 double pa, pq, pw, pia;
-                pair_terms(s.xs[0][2 * kB + kl] - s.xs[0][kB + jl],
-                           s.xs[1][2 * kB + kl] - s.xs[1][kB + jl],
-                           s.xs[2][2 * kB + kl] - s.xs[2][kB + jl], (j < k) && (k < n), pa, pq, pw,
+                pair_terms(s.xs[0][XK + kl] - s.xs[0][XJ + jl], s.xs[1][XK + kl] - s.xs[1][XJ + jl],
+                           s.xs[2][XK + kl] - s.xs[2][XJ + jl], (j < k) && (k < n), pa, pq, pw,
                            pia);
                 s.cb[jj][kl] = (T)pa;
                 s.cq[jj][kl] = (T)pq;
                 s.co[jj][kl] = (T)(0.375 * pia);
-                s.pj[jj][kl] = 0.0;
             }
+            for (int e = tid; e < kJC * 64; e += kThreads) s.pj[e / 64][e % 64] = 0.0;
             __syncthreads();
 
-            for (int jj = 0; jj < kJC; ++jj) {
-                const T b1 = s.cb[jj][lane], q1 = s.cq[jj][lane], o1 = s.co[jj][lane];
-                const T b2 = s.cb[jj][lane + 64], q2 = s.cq[jj][lane + 64], o2 = s.co[jj][lane + 64];
-                const T bb1 = b1 * b1, bb2 = b2 * b2;
-                T s1 = T(0), s2 = T(0);
+            const T *__restrict__ uc = up + (jc * kJC) * (IB * 3);
+            // Operands of one j step: the (i, j) terms of the wave's IPW points
+            // (uniform, SGPRs) and the (j, k) terms of the lane's four k.
+            struct Ops {
+                T u[IPW * 3];
+                T cb[kKR], cq[kKR], co[kKR];
+            };
+            auto load = [&](int jj, Ops &o) {
+                const T *__restrict__ p = uc + jj * (IB * 3);
 #pragma unroll
-                for (int ii = 0; ii < kIPW; ++ii) {
-                    const int il = wave * kIPW + ii;
-                    const T al = s.ua[jj][il], qa = s.uq[jj][il], wa = s.uw[jj][il];
-                    {
-                        const T g = ag[ii][0];
+                for (int e = 0; e < IPW * 3; ++e) o.u[e] = p[e];
+#pragma unroll
+                for (int kk = 0; kk < kKR; ++kk) {
+                    o.cb[kk] = s.cb[jj][lane + 64 * kk];
+                    o.cq[kk] = s.cq[jj][lane + 64 * kk];
+                    o.co[kk] = s.co[jj][lane + 64 * kk];
+                }
+            };
+            // One j step: 4 * IPW triples per lane.
+            auto step = [&](int jj, const Ops &o) {
+                T bb[kKR], sk[kKR];
+#pragma unroll
+                for (int kk = 0; kk < kKR; ++kk) bb[kk] = o.cb[kk] * o.cb[kk];
+#pragma unroll
+                for (int ii = 0; ii < IPW; ++ii) {
+                    const T al = o.u[3 * ii], qa = o.u[3 * ii + 1], wa = o.u[3 * ii + 2];
+#pragma unroll
+                    for (int kk = 0; kk < kKR; ++kk) {
+                        const T g = ag[ii][kk];
                         const T d = al - g;
-                        const T tt = (al + g) - b1;
-                        const T m = fma(-d, d, bb1);
+                        const T tt = (al + g) - o.cb[kk];
+                        const T m = fma(-d, d, bb[kk]);
+                        const T X = qa * aq[ii][kk];
+                        const T W = wa * aw[ii][kk];
                         const T P = tt * m;
-                        const T X = qa * aq[ii][0];
-                        const T Y = (wa * aw[ii][0]) * P;
-                        const T psi = fma(o1, Y, X);
-                        s1 += psi;
-                        acc_i[ii] = fma(q1, psi, acc_i[ii]);
-                    }
-                    {
-                        const T g = ag[ii][1];
-                        const T d = al - g;
-                        const T tt = (al + g) - b2;
-                        const T m = fma(-d, d, bb2);
-                        const T P = tt * m;
-                        const T X = qa * aq[ii][1];
-                        const T Y = (wa * aw[ii][1]) * P;
-                        const T psi = fma(o2, Y, X);
-                        s2 += psi;
-                        acc_i[ii] = fma(q2, psi, acc_i[ii]);
+                        const T Y = W * P;
+                        const T psi = fma(o.co[kk], Y, X);
+                        sk[kk] = ii ? sk[kk] + psi : psi;
+                        acc_i[ii] = fma(o.cq[kk], psi, acc_i[ii]);
                     }
                 }
-                const T p1 = q1 * s1, p2 = q2 * s2;
-                acck0 += (double)p1;
-                acck1 += (double)p2;
-                atomicAdd(&s.pj[jj][lane], (double)p1);
-                atomicAdd(&s.pj[jj][lane + 64], (double)p2);
-            }
-            // fold the short binary32 partial sums into binary64
+                double pjv = 0.0;
 #pragma unroll
-            for (int ii = 0; ii < kIPW; ++ii) {
-                acc_i64[ii] += (double)acc_i[ii];
-                acc_i[ii] = T(0);
+                for (int kk = 0; kk < kKR; ++kk) {
+                    const double v = (double)(o.cq[kk] * sk[kk]);
+                    acck[kk] += v;
+                    pjv += v;
+                }
+                atomicAdd(&s.pj[jj][lane], pjv);
+            };
+            // Two operand sets: everything step jj + 1 reads is loaded while
+            // step jj computes, so one wait per step covers loads issued a
+            // whole step earlier (LDS and scalar loads share one counter).
+            // The explicit wait + scheduling barriers keep the compiler from
+            // hoisting the next set's loads above the wait for this set.
+            Ops A, B;
+            load(0, A);
+#pragma unroll 1
+            for (int jj = 0; jj < kJC; jj += 2) {
+                lgkm_wait_all();
+                load(jj + 1, B);
+                sched_fence();
+                step(jj, A);
+                lgkm_wait_all();
+                if (jj + 2 < kJC) load(jj + 2, A);
+                sched_fence();
+                step(jj + 1, B);
+            }
+            // fold the short binary32 partial sums of Phi_i into binary64
+            if constexpr (sizeof(T) == 4) {
+#pragma unroll
+                for (int ii = 0; ii < IPW; ++ii) {
+                    acc_i64[ii] += (double)acc_i[ii];
+                    acc_i[ii] = T(0);
+                }
             }
             __syncthreads();
             {
-                // Phi_j of the chunk: sum the (j, k) slots over k
+                // Phi_j of the chunk: 16 rows of 64 slots, 32 threads per row
                 const int row = tid >> 5, c = tid & 31;
-                double v = s.pj[row][c] + s.pj[row][c + 32] + s.pj[row][c + 64] + s.pj[row][c + 96];
+                double v = s.pj[row][c] + s.pj[row][c + 32];
 #pragma unroll
                 for (int m = 16; m >= 1; m >>= 1) v += __shfl_xor(v, m);
                 if (c == 0) s.pjacc[jc * kJC + row] = v;
@@ -207,13 +291,13 @@ __global__ __launch_bounds__(kThreads, 1) void direct_kernel(
         }
 
 #pragma unroll
-        for (int ii = 0; ii < kIPW; ++ii) {
-            const double v = wave_sum(acc_i64[ii]);
-            const int i = I0 + wave * kIPW + ii;
+        for (int ii = 0; ii < IPW; ++ii) {
+            const double v = wave_sum(sizeof(T) == 4 ? acc_i64[ii] : (double)acc_i[ii]);
+            const int i = I0 + wave * IPW + ii;
             if (lane == 0 && i < n) atomicAdd(&phi[i], v * out_scale);
         }
-        atomicAdd(&s.kacc[lane], acck0);
-        atomicAdd(&s.kacc[lane + 64], acck1);
+#pragma unroll
+        for (int kk = 0; kk < kKR; ++kk) atomicAdd(&s.kacc[lane + 64 * kk], acck[kk]);
         __syncthreads();
         if (tid < kKT) {
             const int k = K0 + tid;
@@ -225,13 +309,13 @@ __global__ __launch_bounds__(kThreads, 1) void direct_kernel(
     }
 }
 
-// Prefix offsets of the unit list: units with J block b number (b + 1) * (nt - b / 2).
-__global__ void unit_offsets_kernel(int nb, int nt, int64_t *__restrict__ off) {
+// Prefix offsets of the unit list, units of J block b: units_a(b) * (nt - b / 4).
+__global__ void unit_offsets_kernel(int nb, int nt, int ib, int na, int64_t *__restrict__ off) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int64_t acc = 0;
     off[0] = 0;
     for (int b = 0; b < nb; ++b) {
-        acc += (int64_t)(b + 1) * (nt - (b >> 1));
+        acc += (int64_t)units_a(b, ib, na) * (nt - (b >> 2));
         off[b + 1] = acc;
     }
 }
@@ -306,6 +390,44 @@ double key_to_double(unsigned long long k) {
     return d;
 }
 
+template <typename T>
+mb_status direct_launch_t(const double *x, int64_t n, double scale, double *phi, hipStream_t s) {
+    constexpr int IB = DirectLds<T>::IB;
+    const int na = (int)((n + IB - 1) / IB);
+    const int nb = (int)((n + kB - 1) / kB);
+    const int nt = (int)((n + kKT - 1) / kKT);
+    std::vector<int64_t> off(nb + 1, 0);
+    for (int b = 0; b < nb; ++b)
+        off[b + 1] = off[b] + (int64_t)units_a(b, IB, na) * (nt - (b >> 2));
+    mb_status st;
+    Scratch unit_tab;
+    if ((st = unit_tab.alloc(sizeof(int64_t) * (nb + 1), s)) != MB_OK) return st;
+    unit_offsets_kernel<<<1, 1, 0, s>>>(nb, nt, IB, na, unit_tab.as<int64_t>());
+    MB_HIP(hipGetLastError());
+
+    // the (i, j) table is built for a stripe of J blocks at a time
+    const size_t per_b = (size_t)na * IB * kB * 3 * sizeof(T);
+    int stripe = (int)std::max<size_t>(1, table_budget_bytes() / per_b);
+    stripe = std::min(stripe, nb);
+    Scratch pair_tab;
+    if ((st = pair_tab.alloc(per_b * stripe, s)) != MB_OK) return st;
+
+    const double s2 = scale * scale;
+    const double out_scale = s2 * s2 * s2 * s2 * scale;  // scale^9, exact for a power of two
+    for (int b0 = 0; b0 < nb; b0 += stripe) {
+        const int b1 = std::min(nb, b0 + stripe);
+        const int64_t u0 = off[b0], u1 = off[b1];
+        pair_table_kernel<T><<<dim3((unsigned)na, (unsigned)(b1 - b0)), 256, 0, s>>>(
+            x, (int)n, na, b0, scale, pair_tab.as<T>());
+        const unsigned grid = (unsigned)std::min<int64_t>(u1 - u0, (int64_t)1 << 30);
+        direct_kernel<T><<<grid, kThreads, 0, s>>>(x, (int)n, na, nb, nt, unit_tab.as<int64_t>(),
+                                                   u0, u1, b0, pair_tab.as<T>(), scale,
+                                                   out_scale, phi);
+        MB_HIP(hipGetLastError());
+    }
+    return MB_OK;
+}
+
 }  // namespace
 
 mb_status zero_doubles(double *p, int64_t n, hipStream_t s) {
@@ -344,25 +466,8 @@ mb_status direct_launch(const double *x, int64_t n, int prec, double scale, doub
     mb_status st = zero_doubles(phi, n, s);
     if (st != MB_OK) return st;
     if (n < 3) return MB_OK;
-    const int nb = (int)((n + kB - 1) / kB);
-    const int nt = (int)((n + kKT - 1) / kKT);
-    int64_t n_units = 0;
-    for (int b = 0; b < nb; ++b) n_units += (int64_t)(b + 1) * (nt - (b >> 1));
-    Scratch tab;
-    if ((st = tab.alloc(sizeof(int64_t) * (nb + 1), s)) != MB_OK) return st;
-    unit_offsets_kernel<<<1, 1, 0, s>>>(nb, nt, tab.as<int64_t>());
-    MB_HIP(hipGetLastError());
-    const unsigned grid = (unsigned)std::min<int64_t>(n_units, (int64_t)1 << 30);
-    const double s2 = scale * scale;
-    const double out_scale = s2 * s2 * s2 * s2 * scale;  // scale^9, exact for a power of two
-    if (prec == MB_FP64)
-        direct_kernel<double><<<grid, kThreads, 0, s>>>(x, (int)n, nb, nt, tab.as<int64_t>(),
-                                                        n_units, scale, out_scale, phi);
-    else
-        direct_kernel<float><<<grid, kThreads, 0, s>>>(x, (int)n, nb, nt, tab.as<int64_t>(),
-                                                       n_units, scale, out_scale, phi);
-    MB_HIP(hipGetLastError());
-    return MB_OK;
+    return prec == MB_FP64 ? direct_launch_t<double>(x, n, scale, phi, s)
+                           : direct_launch_t<float>(x, n, scale, phi, s);
 }
 
 }  // namespace mb

@@ -24,6 +24,10 @@ mb_status hip_fail(hipError_t e, const char *what);
         if (mb_e_ != hipSuccess) return ::mb::hip_fail(mb_e_, #call); \
     } while (0)
 
+// Keep freed stream-ordered memory in the current device's pool instead of
+// returning it to the driver at every synchronization (once per device).
+void device_pool_setup();
+
 // Stream-ordered device scratch that frees itself on scope exit.
 struct Scratch {
     void *ptr = nullptr;
@@ -36,6 +40,7 @@ struct Scratch {
     }
     mb_status alloc(size_t bytes, hipStream_t s) {
         stream = s;
+        device_pool_setup();
         hipError_t e = hipMallocAsync(&ptr, bytes ? bytes : 1, s);
         if (e != hipSuccess) {
             ptr = nullptr;
@@ -66,6 +71,10 @@ mb_status validate_points(const double *x, int64_t n, hipStream_t s, ValidateOut
 
 // Enqueue phi[0:n] = 0.
 mb_status zero_doubles(double *p, int64_t n, hipStream_t s);
+
+// Upper bound on the bytes of the (i, j) pair-term table the exhaustive sum
+// keeps per launch stripe (MB_TABLE_BUDGET_MB overrides, default 2048 MiB).
+size_t table_budget_bytes();
 
 // Direct (exhaustive) evaluation, no validation; phi is zeroed and
 // accumulated.  `scale` is a power of two applied to all coordinate
