@@ -98,6 +98,112 @@ mb_status mb_eval_direct_unchecked(const double *x, int64_t n, int32_t prec, dou
 mb_status mb_validate(const double *x, int64_t n, double *min_d2, int32_t *finite, double *bbox,
                       void *stream);
 
+/* ------------------------------------------------------------------------
+ * kd-tree (BuildKdTree, Algorithm 1) and triple-tree traversal
+ * (MTPotentialCanonical, Algorithm 2; approximation rules of Section 4)
+ * ---------------------------------------------------------------------- */
+
+/* Opaque device-resident kd-tree.  Immutable after build; may be shared by
+ * calls on any stream of the device it was built on. */
+typedef struct mb_tree_s *mb_tree;
+
+/*
+ * Build the kd-tree of the N points (Algorithm 1): a node holding more than
+ * leaf_size points is split along the widest dimension of its tight
+ * bounding box (ties to the lowest dimension) at the median by count: the
+ * left child takes the floor(n/2) points first in the order (coordinate,
+ * original index).  Points are kept in depth-first order; a node owns the
+ * depth-first ranks [begin, end).  Nodes are numbered in pre-order (root 0,
+ * left child = node + 1).
+ *   leaf_size : 1 .. 32 (MB_ERR_UNSUPPORTED above 32, MB_ERR_INVALID below 1)
+ *   out       : receives the tree; release with mb_free_kdtree.
+ * Coordinates must be finite (MB_ERR_INVALID otherwise).  Waits on stream.
+ */
+mb_status mb_build_kdtree(const double *x, int64_t n, int32_t leaf_size, void *stream,
+                          mb_tree *out);
+
+/* Release a tree (NULL is accepted). */
+mb_status mb_free_kdtree(mb_tree t);
+
+/* Sizes of a tree: points, nodes, depth of the deepest node, build time. */
+mb_status mb_kdtree_info(mb_tree t, int64_t *n_points, int32_t *n_nodes, int32_t *max_depth,
+                         double *build_ms);
+
+/*
+ * Copy a tree to host arrays (each pointer may be NULL):
+ *   perm     [N]     original index of the point at each depth-first rank
+ *   ranges   [2M]    begin, end of node v at 2v, 2v+1
+ *   children [2M]    left, right of node v (-1, -1 for a leaf)
+ *   bbox     [6M]    lower corner then upper corner of node v at 6v
+ *   centroid [3M]    mean of node v's points
+ */
+mb_status mb_kdtree_export(mb_tree t, int32_t *perm, int32_t *ranges, int32_t *children,
+                           double *bbox, double *centroid);
+
+/* Parameters of the traversal (error criteria of Definitions 2.1-2.3). */
+typedef struct {
+    double eps_rel;    /* epsilon: relative error bound (Definition 2.2), >= 0         */
+    double tau_abs;    /* tau: absolute error bound (Definition 2.1), >= 0             */
+    double alpha;      /* 1 - alpha: probability level (Definition 2.3), 0 <= alpha < 1;
+                          0 disables Monte Carlo (deterministic guarantee only)        */
+    int32_t m_limit;   /* samples per point before Monte Carlo gives up (Algorithm 4)  */
+    int32_t m_min;     /* samples required before the normal approximation is used    */
+    double zeta;       /* Monte Carlo is tried only if zeta * m_limit <= min_i T_i     */
+    uint64_t seed;     /* seed of the counter-based sampler                            */
+    int32_t base_prec; /* arithmetic of the exhaustive base cases: MB_FP64 or MB_FP32C */
+    int32_t chunk;     /* node triples processed per round of the device stack         */
+} mb_mt_params;
+
+/* Defaults: eps 1e-2, tau 0, alpha 0.05, m_limit 128, m_min 30, zeta 4,
+ * seed 0, base_prec MB_FP32C, chunk 32768. */
+void mb_mt_params_default(mb_mt_params *p);
+
+typedef struct {
+    int64_t visited;      /* node triples examined                                   */
+    int64_t det_prunes;   /* triples summarized by the deterministic bound           */
+    int64_t mc_prunes;    /* triples summarized by Monte Carlo                       */
+    int64_t mc_failed;    /* Monte Carlo attempts that did not meet the bound        */
+    int64_t base_cases;   /* leaf triples summed exhaustively                        */
+    int64_t base_triples; /* particle triples in those base cases                    */
+    int64_t mc_samples;   /* phi evaluations drawn by Monte Carlo                    */
+    int64_t max_stack;    /* largest device stack (node triples)                     */
+    int64_t rounds;       /* rounds of the device stack                              */
+    double build_ms;      /* tree build (0 if a tree was passed in)                  */
+    double traverse_ms;   /* traversal incl. top-down pass                           */
+} mb_mt_stats;
+
+/*
+ * Approximate Phi(x) for all points by the triple-tree traversal
+ * (Algorithm 2 with CanSummarize / Summarize of Section 4 and Algorithms
+ * 3-5), guaranteeing |Phi~ - Phi| <= eps |Phi| + tau per point in the sense
+ * of Definition 2.3 (with alpha = 0, Theorem 5.1's deterministic form).
+ * For the sign-indefinite Axilrod-Teller potential the deterministic bound
+ * uses phi in [-2 R, 11/8 R], R = (product of the three box distances)^-3,
+ * and the running lower bound of the paper is a heuristic (the sum of
+ * lower bounds of what has been credited so far).
+ *   tree     : a tree of the same points built with the same leaf_size, or
+ *              NULL to build one internally (then leaf_size is used).
+ *   params   : host pointer (NULL = defaults).
+ *   phi      : device, N doubles, input order.
+ *   coverage : device, N int64 or NULL; receives the number of particle
+ *              triples credited to each point (C(N-1, 2) when the traversal
+ *              partitions the tuples exactly, which it does by construction).
+ *   stats    : host, nullable.
+ * Validation as for mb_eval_direct.  eps < 0, tau < 0, alpha outside [0,1),
+ * m_limit < 2, m_min < 2, zeta < 0, or a tree built for other points ->
+ * MB_ERR_INVALID.  Waits on stream (the host drives the device stack).
+ */
+mb_status mb_eval_multitree(const double *x, int64_t n, int32_t leaf_size,
+                            const mb_mt_params *params, mb_tree tree, double *phi,
+                            int64_t *coverage, mb_mt_stats *stats, void *stream);
+
+/*
+ * z such that P(Z > z) = alpha_half for a standard normal Z: the quantile
+ * z_{alpha/2} of the Monte Carlo stop rule is mb_normal_quantile(alpha / 2).
+ * Host only; returns 0 for alpha_half outside (0, 0.5).
+ */
+double mb_normal_quantile(double alpha_half);
+
 #ifdef __cplusplus
 }
 #endif

@@ -4,6 +4,8 @@ The compute path is libmb.so (hand-written HIP, C ABI in include/mb.h);
 this package is its thin Python binding.  Torch tensors provide device
 memory and streams only.
 """
-from ._lib import MBError, eval_direct, lib, validate  # noqa: F401
+from ._lib import (KdTree, MBError, eval_direct, eval_multitree, lib, mt_params,  # noqa: F401
+                   normal_quantile, validate)
 
-__all__ = ["MBError", "eval_direct", "validate", "lib"]
+__all__ = ["MBError", "KdTree", "eval_direct", "eval_multitree", "mt_params", "normal_quantile",
+           "validate", "lib"]

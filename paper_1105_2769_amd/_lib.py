@@ -39,6 +39,24 @@ _c_i64 = ctypes.c_int64
 _c_dbl = ctypes.c_double
 _c_vp = ctypes.c_void_p
 
+class MtParams(ctypes.Structure):
+    _fields_ = [("eps_rel", ctypes.c_double), ("tau_abs", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("m_limit", ctypes.c_int32),
+                ("m_min", ctypes.c_int32), ("zeta", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("base_prec", ctypes.c_int32),
+                ("chunk", ctypes.c_int32)]
+
+
+class MtStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in
+                ("visited", "det_prunes", "mc_prunes", "mc_failed", "base_cases", "base_triples",
+                 "mc_samples", "max_stack", "rounds")] + \
+               [("build_ms", ctypes.c_double), ("traverse_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "mb_last_error": (ctypes.c_char_p, []),
@@ -47,6 +65,15 @@ SIGNATURES = {
                              ctypes.POINTER(_c_dbl), _c_vp]),
     "mb_eval_direct": (_c_i32, [_c_vp, _c_i64, _c_i32, _c_vp, _c_vp]),
     "mb_eval_direct_unchecked": (_c_i32, [_c_vp, _c_i64, _c_i32, _c_vp, _c_vp]),
+    "mb_build_kdtree": (_c_i32, [_c_vp, _c_i64, _c_i32, _c_vp, ctypes.POINTER(_c_vp)]),
+    "mb_free_kdtree": (_c_i32, [_c_vp]),
+    "mb_kdtree_info": (_c_i32, [_c_vp, ctypes.POINTER(_c_i64), ctypes.POINTER(_c_i32),
+                                ctypes.POINTER(_c_i32), ctypes.POINTER(_c_dbl)]),
+    "mb_kdtree_export": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, _c_vp, _c_vp]),
+    "mb_mt_params_default": (None, [ctypes.POINTER(MtParams)]),
+    "mb_eval_multitree": (_c_i32, [_c_vp, _c_i64, _c_i32, ctypes.POINTER(MtParams), _c_vp, _c_vp,
+                                   _c_vp, ctypes.POINTER(MtStats), _c_vp]),
+    "mb_normal_quantile": (_c_dbl, [_c_dbl]),
 }
 
 
@@ -111,3 +138,79 @@ def eval_direct(x, prec: str = "fp64", out=None, checked: bool = True):
     fn = lib().mb_eval_direct if checked else lib().mb_eval_direct_unchecked
     check(fn(_c_vp(x.data_ptr()), n, PREC[prec], _c_vp(phi.data_ptr()), stream_of(x)))
     return phi
+
+
+class KdTree:
+    """A device-resident kd-tree (mb_build_kdtree); freed with the object."""
+
+    def __init__(self, x, leaf_size: int = 32):
+        x = _points(x)
+        self._x = x
+        handle = _c_vp()
+        check(lib().mb_build_kdtree(_c_vp(x.data_ptr()), x.shape[0], int(leaf_size), stream_of(x),
+                                    ctypes.byref(handle)))
+        self.handle = handle
+        self.leaf_size = int(leaf_size)
+        n = _c_i64()
+        m = _c_i32()
+        d = _c_i32()
+        ms = _c_dbl()
+        check(lib().mb_kdtree_info(handle, ctypes.byref(n), ctypes.byref(m), ctypes.byref(d),
+                                   ctypes.byref(ms)))
+        self.n, self.n_nodes, self.max_depth, self.build_ms = n.value, m.value, d.value, ms.value
+
+    def export(self) -> dict:
+        import numpy as np
+
+        m = self.n_nodes
+        perm = np.zeros(self.n, dtype=np.int32)
+        ranges = np.zeros(2 * m, dtype=np.int32)
+        children = np.zeros(2 * m, dtype=np.int32)
+        bbox = np.zeros(6 * m, dtype=np.float64)
+        cen = np.zeros(3 * m, dtype=np.float64)
+        ptr = lambda a: _c_vp(a.ctypes.data)  # noqa: E731
+        check(lib().mb_kdtree_export(self.handle, ptr(perm), ptr(ranges), ptr(children), ptr(bbox),
+                                     ptr(cen)))
+        return dict(perm=perm, begin=ranges[0::2], end=ranges[1::2], left=children[0::2],
+                    right=children[1::2], lo=bbox.reshape(m, 6)[:, :3], hi=bbox.reshape(m, 6)[:, 3:],
+                    centroid=cen.reshape(m, 3))
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib().mb_free_kdtree(h)
+            self.handle = None
+
+
+def mt_params(**kw) -> MtParams:
+    p = MtParams()
+    lib().mb_mt_params_default(ctypes.byref(p))
+    for key, val in kw.items():
+        if key == "base_prec" and isinstance(val, str):
+            val = PREC[val]
+        setattr(p, key, val)
+    return p
+
+
+def eval_multitree(x, eps: float = 1e-2, alpha: float = 0.05, leaf_size: int = 32,
+                   tree: KdTree | None = None, coverage: bool = False, **kw):
+    """Triple-tree Phi (mb_eval_multitree).  Returns (phi, stats[, coverage])."""
+    import torch
+
+    x = _points(x)
+    n = x.shape[0]
+    p = mt_params(eps_rel=eps, alpha=alpha, **kw)
+    phi = torch.empty(n, dtype=torch.float64, device=x.device)
+    cov = torch.zeros(n, dtype=torch.int64, device=x.device) if coverage else None
+    st = MtStats()
+    check(lib().mb_eval_multitree(_c_vp(x.data_ptr()), n, int(leaf_size), ctypes.byref(p),
+                                  tree.handle if tree is not None else None, _c_vp(phi.data_ptr()),
+                                  _c_vp(cov.data_ptr()) if cov is not None else None,
+                                  ctypes.byref(st), stream_of(x)))
+    if coverage:
+        return phi, st.as_dict(), cov
+    return phi, st.as_dict()
+
+
+def normal_quantile(alpha_half: float) -> float:
+    return float(lib().mb_normal_quantile(float(alpha_half)))

@@ -7,8 +7,11 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "mb_internal.hpp"
+#include "multitree.hpp"
+#include "tree.hpp"
 
 namespace mb {
 
@@ -145,5 +148,147 @@ mb_status mb_eval_direct_unchecked(const double *x, int64_t n, int32_t prec, dou
     if (n == 0) return MB_OK;
     return direct_launch(x, n, prec, 1.0, phi, (hipStream_t)stream);
 }
+
+mb_status mb_build_kdtree(const double *x, int64_t n, int32_t leaf_size, void *stream,
+                          mb_tree *out) {
+    clear_error();
+    if (!out) return fail(MB_ERR_INVALID, "null output");
+    *out = nullptr;
+    if (n < 0 || (n > 0 && !x)) return fail(MB_ERR_INVALID, "bad points");
+    if (leaf_size < 1) return fail(MB_ERR_INVALID, "leaf_size < 1");
+    if (leaf_size > 32) return fail(MB_ERR_UNSUPPORTED, "leaf_size > 32");
+    if (n >= ((int64_t)1 << 31)) return fail(MB_ERR_UNSUPPORTED, "n must be < 2^31");
+    hipStream_t s = (hipStream_t)stream;
+    ValidateOut v{};
+    mb_status st = validate_points(x, n, s, &v);
+    if (st != MB_OK) return st;
+    if (v.nonfinite) return fail(MB_ERR_INVALID, "non-finite coordinate");
+    DeviceTree *t = nullptr;
+    if ((st = tree_build(x, n, leaf_size, s, &t)) != MB_OK) return st;
+    *out = reinterpret_cast<mb_tree>(t);
+    return MB_OK;
+}
+
+mb_status mb_free_kdtree(mb_tree t) {
+    tree_free(reinterpret_cast<DeviceTree *>(t));
+    return MB_OK;
+}
+
+mb_status mb_kdtree_info(mb_tree tt, int64_t *n_points, int32_t *n_nodes, int32_t *max_depth,
+                         double *build_ms) {
+    clear_error();
+    const DeviceTree *t = reinterpret_cast<const DeviceTree *>(tt);
+    if (!t) return fail(MB_ERR_INVALID, "null tree");
+    if (n_points) *n_points = t->h.n;
+    if (n_nodes) *n_nodes = t->h.n_nodes;
+    if (max_depth) *max_depth = t->h.max_depth;
+    if (build_ms) *build_ms = t->build_ms;
+    return MB_OK;
+}
+
+mb_status mb_kdtree_export(mb_tree tt, int32_t *perm, int32_t *ranges, int32_t *children,
+                           double *bbox, double *centroid) {
+    clear_error();
+    const DeviceTree *t = reinterpret_cast<const DeviceTree *>(tt);
+    if (!t) return fail(MB_ERR_INVALID, "null tree");
+    const int M = t->h.n_nodes;
+    if (perm && t->h.n > 0)
+        MB_HIP(hipMemcpy(perm, t->perm, sizeof(int32_t) * t->h.n, hipMemcpyDeviceToHost));
+    if (ranges)
+        for (int v = 0; v < M; ++v) {
+            ranges[2 * v] = t->h.begin[v];
+            ranges[2 * v + 1] = t->h.end[v];
+        }
+    if (children)
+        for (int v = 0; v < M; ++v) {
+            children[2 * v] = t->h.left[v];
+            children[2 * v + 1] = t->h.right[v];
+        }
+    if (bbox) {
+        std::vector<double> lo(3 * (size_t)M), hi(3 * (size_t)M);
+        MB_HIP(hipMemcpy(lo.data(), t->lo, sizeof(double) * 3 * M, hipMemcpyDeviceToHost));
+        MB_HIP(hipMemcpy(hi.data(), t->hi, sizeof(double) * 3 * M, hipMemcpyDeviceToHost));
+        for (int v = 0; v < M; ++v)
+            for (int c = 0; c < 3; ++c) {
+                bbox[6 * v + c] = lo[3 * v + c];
+                bbox[6 * v + 3 + c] = hi[3 * v + c];
+            }
+    }
+    if (centroid && M > 0)
+        MB_HIP(hipMemcpy(centroid, t->centroid, sizeof(double) * 3 * M, hipMemcpyDeviceToHost));
+    return MB_OK;
+}
+
+void mb_mt_params_default(mb_mt_params *p) {
+    if (!p) return;
+    p->eps_rel = 1e-2;
+    p->tau_abs = 0.0;
+    p->alpha = 0.05;
+    p->m_limit = 128;
+    p->m_min = 30;
+    p->zeta = 4.0;
+    p->seed = 0;
+    p->base_prec = MB_FP32C;
+    p->chunk = 32768;
+}
+
+mb_status mb_eval_multitree(const double *x, int64_t n, int32_t leaf_size,
+                            const mb_mt_params *params, mb_tree tree, double *phi,
+                            int64_t *coverage, mb_mt_stats *stats, void *stream) {
+    clear_error();
+    mb_mt_params p;
+    if (params) p = *params; else mb_mt_params_default(&p);
+    if (n < 0 || (n > 0 && (!x || !phi))) return fail(MB_ERR_INVALID, "bad points or output");
+    if (!(p.eps_rel >= 0.0) || !(p.tau_abs >= 0.0) || !(p.alpha >= 0.0 && p.alpha < 1.0) ||
+        p.m_limit < 2 || p.m_min < 2 || !(p.zeta >= 0.0) || p.chunk < 1 ||
+        (p.base_prec != MB_FP64 && p.base_prec != MB_FP32C))
+        return fail(MB_ERR_INVALID, "bad traversal parameters");
+    if (n >= ((int64_t)1 << 31)) return fail(MB_ERR_UNSUPPORTED, "n must be < 2^31");
+    hipStream_t s = (hipStream_t)stream;
+    if (stats) *stats = mb_mt_stats{};
+    if (n == 0) return MB_OK;
+    ValidateOut v{};
+    mb_status st = check_points(x, n, s, &v);
+    if (st != MB_OK) return st;
+    DeviceTree *t = reinterpret_cast<DeviceTree *>(tree);
+    DeviceTree *own = nullptr;
+    if (t) {
+        if (t->h.n != n) return fail(MB_ERR_INVALID, "tree built for a different point count");
+    } else {
+        if (leaf_size < 1) return fail(MB_ERR_INVALID, "leaf_size < 1");
+        if (leaf_size > 32) return fail(MB_ERR_UNSUPPORTED, "leaf_size > 32");
+        if ((st = tree_build(x, n, leaf_size, s, &own)) != MB_OK) return st;
+        t = own;
+    }
+    MtParams mp;
+    mp.eps = p.eps_rel;
+    mp.tau = p.tau_abs;
+    mp.alpha = p.alpha;
+    mp.m_limit = p.m_limit;
+    mp.m_min = p.m_min;
+    mp.zeta = p.zeta;
+    mp.seed = p.seed;
+    mp.base_prec = p.base_prec;
+    mp.chunk = p.chunk;
+    MtStats ms;
+    st = multitree_run(t, mp, phi, coverage, &ms, s);
+    if (st == MB_OK && stats) {
+        stats->visited = ms.visited;
+        stats->det_prunes = ms.det_prunes;
+        stats->mc_prunes = ms.mc_prunes;
+        stats->mc_failed = ms.mc_failed;
+        stats->base_cases = ms.base_cases;
+        stats->base_triples = ms.base_triples;
+        stats->mc_samples = ms.mc_samples;
+        stats->max_stack = ms.max_stack;
+        stats->rounds = ms.rounds;
+        stats->build_ms = own ? own->build_ms : 0.0;
+        stats->traverse_ms = ms.traverse_ms;
+    }
+    if (own) tree_free(own);
+    return st;
+}
+
+double mb_normal_quantile(double alpha_half) { return normal_quantile_upper(alpha_half); }
 
 }  // extern "C"

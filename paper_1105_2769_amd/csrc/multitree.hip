@@ -1,0 +1,890 @@
+// Triple-tree (multi-tree) traversal for the Axilrod-Teller potential on
+// gfx950: MTPotentialCanonical (Algorithm 2) with the deterministic
+// monopole prune (Section 4, Section 4.1) and the Monte Carlo prune
+// (Algorithms 3-5), then the top-down pass (Section 3).
+//
+// The recursion becomes a device-resident LIFO stack of canonical node
+// triples, processed in rounds: the host pops the top `chunk` triples and
+// enqueues
+//   1. classify   - one thread per triple: canonical case, T_i, distance
+//                   bounds, deterministic test (a prune is applied at once
+//                   with FP64 atomics on node accumulators), Monte Carlo
+//                   eligibility, base case or split;
+//   2. mc         - one workgroup per eligible triple: per-point sampling
+//                   until the termination rule, commit if every point passes;
+//                   a failed triple falls through to base case or split;
+//   3. base       - one workgroup per leaf triple: exact sum through the
+//                   pair-term tiles also used by the exhaustive kernel;
+//   4. children   - the canonical children of split triples are compacted in
+//                   order onto the stack where the popped triples were;
+//   5. refresh    - the node summary statistic Phi^l(P) = min over x in P of
+//                   the running lower bound of x is recomputed.
+// Popping from the top processes the most recently split triples first, so
+// the traversal is depth first across rounds, as the paper's recursion.
+// Triples generated early (far apart, high in the tree) wait on the stack
+// while the lower bounds of their points grow, which is what lets them be
+// pruned when their turn comes.
+//
+// Readings for the Axilrod-Teller potential (sign-indefinite, not monotone):
+// phi lies in [-2 R^u, 11/8 R^u], R^u = (d^l_12 d^l_13 d^l_23)^-3, so the
+// deterministic test uses span = 27/8 R^u and delta^l_i = T_i (-2 R^u); the
+// Monte Carlo stop rule is z sigma_mu <= (eps (Phi^l + T_i (mu - z sigma_mu))
+// + tau) / T_root with at least m_min samples.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "at_device.hpp"
+#include "mb_internal.hpp"
+#include "multitree.hpp"
+#include "tree.hpp"
+
+namespace mb {
+namespace {
+
+struct Item {
+    int32_t p1, p2, p3, slot;  // canonical node triple; slot = index in the popped chunk
+};
+
+struct MtCounters {
+    unsigned long long n_base, n_mc;
+    unsigned long long visited, det_prunes, mc_prunes, mc_failed, base_cases, base_triples,
+        mc_samples;
+};
+
+struct MtConst {
+    int n;
+    double eps, tau, z, t_root;
+    int m_limit, m_min;
+    double zeta;
+    uint32_t seed32;
+    int use_mc;
+    int want_cov;
+};
+
+struct NodeView {
+    const int32_t *begin, *end, *left, *right;
+    const double *lo, *hi, *centroid;
+};
+
+__device__ __forceinline__ int64_t comb2(int64_t n) { return n * (n - 1) / 2; }
+
+__device__ __forceinline__ double box_min_dist(const double *lo1, const double *hi1,
+                                               const double *lo2, const double *hi2) {
+    double s2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double g = fmax(0.0, fmax(lo1[c] - hi2[c], lo2[c] - hi1[c]));
+        s2 = fma(g, g, s2);
+    }
+    return sqrt(s2);
+}
+
+// phi of three points from binary64 coordinates (law-of-cosines form).
+__device__ __forceinline__ double phi3(const double *a, const double *b, const double *c) {
+    double ab, qab, wab, iab, ac, qac, wac, iac, bc, qbc, wbc, ibc;
+    pair_terms(b[0] - a[0], b[1] - a[1], b[2] - a[2], true, ab, qab, wab, iab);
+    pair_terms(c[0] - a[0], c[1] - a[1], c[2] - a[2], true, ac, qac, wac, iac);
+    pair_terms(c[0] - b[0], c[1] - b[1], c[2] - b[2], true, bc, qbc, wbc, ibc);
+    return phi_from_pairs<double>(ab, qab, wab, ac, qac, wac, bc, qbc, wbc);
+}
+
+// Distinct nodes of a canonical triple, each with its T_i and its first slot.
+struct Roles {
+    int n_roles;
+    int node[3];
+    int slot[3];
+    int64_t t[3];
+};
+
+__device__ __forceinline__ char canonical_case(int p1, int p2, int p3) {
+    if (p1 == p2 && p2 == p3) return 'a';
+    if (p1 == p2) return 'b';
+    if (p2 == p3) return 'c';
+    return 'd';
+}
+
+__device__ __forceinline__ Roles roles_of(int p1, int p2, int p3, int64_t n1, int64_t n2,
+                                          int64_t n3) {
+    Roles r;
+    const char cs = canonical_case(p1, p2, p3);
+    if (cs == 'a') {
+        r.n_roles = 1;
+        r.node[0] = p1; r.slot[0] = 0; r.t[0] = comb2(n1 - 1);
+    } else if (cs == 'b') {
+        r.n_roles = 2;
+        r.node[0] = p1; r.slot[0] = 0; r.t[0] = (n1 - 1) * n3;
+        r.node[1] = p3; r.slot[1] = 2; r.t[1] = comb2(n1);
+    } else if (cs == 'c') {
+        r.n_roles = 2;
+        r.node[0] = p1; r.slot[0] = 0; r.t[0] = comb2(n2);
+        r.node[1] = p2; r.slot[1] = 1; r.t[1] = n1 * (n2 - 1);
+    } else {
+        r.n_roles = 3;
+        r.node[0] = p1; r.slot[0] = 0; r.t[0] = n2 * n3;
+        r.node[1] = p2; r.slot[1] = 1; r.t[1] = n1 * n3;
+        r.node[2] = p3; r.slot[2] = 2; r.t[2] = n1 * n2;
+    }
+    return r;
+}
+
+// Canonical children (every non-leaf node split, one copy per pair of equal
+// nodes): written to out[0..count), returns count (<= 8).
+__device__ int canonical_children(const NodeView &nv, int p1, int p2, int p3, Item *out) {
+    auto opts = [&](int v, int *o) -> int {
+        if (nv.left[v] < 0) {
+            o[0] = v;
+            return 1;
+        }
+        o[0] = nv.left[v];
+        o[1] = nv.right[v];
+        return 2;
+    };
+    const char cs = canonical_case(p1, p2, p3);
+    int cnt = 0;
+    int oa[2], ob[2];
+    if (cs == 'a') {
+        const int na = opts(p1, oa);
+        for (int x = 0; x < na; ++x)
+            for (int y = x; y < na; ++y)
+                for (int z = y; z < na; ++z) out[cnt++] = Item{oa[x], oa[y], oa[z], 0};
+    } else if (cs == 'b') {
+        const int na = opts(p1, oa), nb = opts(p3, ob);
+        for (int x = 0; x < na; ++x)
+            for (int y = x; y < na; ++y)
+                for (int z = 0; z < nb; ++z) out[cnt++] = Item{oa[x], oa[y], ob[z], 0};
+    } else if (cs == 'c') {
+        const int na = opts(p1, oa), nb = opts(p2, ob);
+        for (int x = 0; x < na; ++x)
+            for (int y = 0; y < nb; ++y)
+                for (int z = y; z < nb; ++z) out[cnt++] = Item{oa[x], ob[y], ob[z], 0};
+    } else {
+        int oc[2];
+        const int na = opts(p1, oa), nb = opts(p2, ob), nc = opts(p3, oc);
+        for (int x = 0; x < na; ++x)
+            for (int y = 0; y < nb; ++y)
+                for (int z = 0; z < nc; ++z) out[cnt++] = Item{oa[x], ob[y], oc[z], 0};
+    }
+    return cnt;
+}
+
+__device__ __forceinline__ void emit_children(const NodeView &nv, const Item &it, int slot,
+                                              Item *__restrict__ child_buf,
+                                              uint8_t *__restrict__ child_flag) {
+    Item ch[8];
+    const int c = canonical_children(nv, it.p1, it.p2, it.p3, ch);
+    for (int q = 0; q < 8; ++q) {
+        if (q < c) child_buf[8 * slot + q] = ch[q];
+        child_flag[8 * slot + q] = q < c ? 1 : 0;
+    }
+}
+
+// 1. classification of the popped triples
+__global__ __launch_bounds__(256) void classify_kernel(
+    const Item *__restrict__ items, int n_items, NodeView nv, const double *__restrict__ node_phil,
+    double *__restrict__ node_acc, double *__restrict__ node_lo,
+    unsigned long long *__restrict__ node_cov, MtConst k, MtCounters *__restrict__ ctr,
+    Item *__restrict__ mc_list, Item *__restrict__ base_list, Item *__restrict__ child_buf,
+    uint8_t *__restrict__ child_flag, int defer_far, Item *__restrict__ defer_buf,
+    uint8_t *__restrict__ defer_flag) {
+    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= n_items) return;
+    Item it = items[slot];
+    it.slot = slot;
+    for (int q = 0; q < 8; ++q) child_flag[8 * slot + q] = 0;
+    defer_flag[slot] = 0;
+    const int p1 = it.p1, p2 = it.p2, p3 = it.p3;
+    const int64_t n1 = nv.end[p1] - nv.begin[p1], n2 = nv.end[p2] - nv.begin[p2],
+                  n3 = nv.end[p3] - nv.begin[p3];
+    const Roles r = roles_of(p1, p2, p3, n1, n2, n3);
+
+    // deterministic prune: case (d) with all three boxes apart
+    if (r.n_roles == 3) {
+        const double d12 = box_min_dist(nv.lo + 3 * p1, nv.hi + 3 * p1, nv.lo + 3 * p2, nv.hi + 3 * p2);
+        const double d13 = box_min_dist(nv.lo + 3 * p1, nv.hi + 3 * p1, nv.lo + 3 * p3, nv.hi + 3 * p3);
+        const double d23 = box_min_dist(nv.lo + 3 * p2, nv.hi + 3 * p2, nv.lo + 3 * p3, nv.hi + 3 * p3);
+        if (d12 > 0.0 && d13 > 0.0 && d23 > 0.0 && defer_far) {
+            // far triple met while near-field work remains: examined later
+            defer_buf[slot] = it;
+            defer_flag[slot] = 1;
+            return;
+        }
+        atomicAdd(&ctr->visited, 1ull);
+        if (d12 > 0.0 && d13 > 0.0 && d23 > 0.0) {
+            const double prod = d12 * d13 * d23;
+            const double ru = 1.0 / (prod * prod * prod);
+            const double phi_lo = -2.0 * ru;
+            const double span = 3.375 * ru;
+            double allow = INFINITY;
+            for (int q = 0; q < 3; ++q)
+                allow = fmin(allow, node_phil[r.node[q]] + (double)r.t[q] * phi_lo);
+            if (span <= (k.eps * allow + k.tau) / k.t_root) {
+                const double phic = phi3(nv.centroid + 3 * p1, nv.centroid + 3 * p2,
+                                         nv.centroid + 3 * p3);
+                for (int q = 0; q < 3; ++q) {
+                    atomicAdd(&node_acc[r.node[q]], (double)r.t[q] * phic);
+                    atomicAdd(&node_lo[r.node[q]], (double)r.t[q] * phi_lo);
+                    if (k.want_cov) atomicAdd(&node_cov[r.node[q]], (unsigned long long)r.t[q]);
+                }
+                atomicAdd(&ctr->det_prunes, 1ull);
+                return;
+            }
+        }
+    } else {
+        atomicAdd(&ctr->visited, 1ull);
+    }
+    // Monte Carlo candidate
+    if (k.use_mc) {
+        int64_t tmin = r.t[0];
+        for (int q = 1; q < r.n_roles; ++q) tmin = min(tmin, r.t[q]);
+        if (tmin > 0 && k.zeta * (double)k.m_limit <= (double)tmin) {
+            const unsigned long long pos = atomicAdd(&ctr->n_mc, 1ull);
+            mc_list[pos] = it;
+            return;
+        }
+    }
+    const bool all_leaves = nv.left[p1] < 0 && nv.left[p2] < 0 && nv.left[p3] < 0;
+    if (all_leaves) {
+        const unsigned long long pos = atomicAdd(&ctr->n_base, 1ull);
+        base_list[pos] = it;
+        return;
+    }
+    emit_children(nv, it, slot, child_buf, child_flag);
+}
+
+// Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32 -> 64-bit
+// multiplications with key bumps by the Weyl constants in between.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        c[1] = (uint32_t)p1;
+        c[3] = (uint32_t)p0;
+        c[0] = n0;
+        c[2] = n2;
+    }
+}
+
+// Unordered pair (u < v) of [0, m) from its index t in [0, C(m, 2)), v-major.
+__device__ __forceinline__ void pair_from_index(uint64_t t, int64_t &u, int64_t &v) {
+    int64_t vv = (int64_t)floor((1.0 + sqrt(1.0 + 8.0 * (double)t)) * 0.5);
+    while (vv * (vv - 1) / 2 > (int64_t)t) --vv;
+    while ((vv + 1) * vv / 2 <= (int64_t)t) ++vv;
+    v = vv;
+    u = (int64_t)t - vv * (vv - 1) / 2;
+}
+
+// The two partners of point x (offset xl inside the node at slot `slot`) for
+// one uniform 64-bit integer r: offsets inside their nodes and their slots.
+__device__ __forceinline__ void sample_partners(char cs, int slot, int64_t xl, int64_t n1,
+                                                int64_t n2, int64_t n3, uint64_t r, int64_t &u,
+                                                int64_t &v, int &su, int &sv) {
+    if (cs == 'a') {
+        pair_from_index(__umul64hi(r, (uint64_t)comb2(n1 - 1)), u, v);
+        u += u >= xl;
+        v += v >= xl;
+        su = sv = 0;
+    } else if (cs == 'b') {
+        if (slot == 0) {
+            const uint64_t t = __umul64hi(r, (uint64_t)((n1 - 1) * n3));
+            u = (int64_t)(t / (uint64_t)n3);
+            v = (int64_t)(t % (uint64_t)n3);
+            u += u >= xl;
+            su = 0;
+            sv = 2;
+        } else {
+            pair_from_index(__umul64hi(r, (uint64_t)comb2(n1)), u, v);
+            su = sv = 0;
+        }
+    } else if (cs == 'c') {
+        if (slot == 0) {
+            pair_from_index(__umul64hi(r, (uint64_t)comb2(n2)), u, v);
+            su = sv = 1;
+        } else {
+            const uint64_t t = __umul64hi(r, (uint64_t)(n1 * (n2 - 1)));
+            u = (int64_t)(t / (uint64_t)(n2 - 1));
+            v = (int64_t)(t % (uint64_t)(n2 - 1));
+            v += v >= xl;
+            su = 0;
+            sv = 1;
+        }
+    } else {
+        const int o0 = slot == 0 ? 1 : 0;
+        const int o1 = slot == 2 ? 1 : 2;
+        const int64_t na = o0 == 0 ? n1 : n2;
+        const int64_t nb = o1 == 1 ? n2 : n3;
+        const uint64_t t = __umul64hi(r, (uint64_t)(na * nb));
+        u = (int64_t)(t / (uint64_t)nb);
+        v = (int64_t)(t % (uint64_t)nb);
+        su = o0;
+        sv = o1;
+    }
+}
+
+constexpr int kMcThreads = 256;
+constexpr int kMcCache = 2048;  // points whose (mu, lower bound) stay in LDS between passes
+
+// Draws samples for point xr (offset off in the node at slot `slot`) until
+// the termination rule holds or m_limit samples are taken; returns pass.
+__device__ __forceinline__ bool mc_point(const Item &it, char cs, int slot, int64_t off, int64_t xr,
+                                         int64_t n1, int64_t n2, int64_t n3, const int *pn,
+                                         const NodeView &nv, const double *__restrict__ xs,
+                                         double t, double plo, const MtConst &k,
+                                         const volatile int *failed, double &mean, double &sig,
+                                         int &m_used) {
+    const double *xp = xs + 3 * xr;
+    double m2 = 0.0;
+    mean = 0.0;
+    sig = 0.0;
+    int m = 0;
+    bool pass = false;
+    while (m < k.m_limit) {
+        if (failed && *failed) break;
+        uint32_t c[4] = {(uint32_t)xr, (uint32_t)m, (uint32_t)it.p1, (uint32_t)it.p2};
+        philox4x32_10(c, (uint32_t)it.p3, k.seed32);
+        const uint64_t rr = ((uint64_t)c[1] << 32) | c[0];
+        int64_t u, v;
+        int su, sv;
+        sample_partners(cs, slot, off, n1, n2, n3, rr, u, v, su, sv);
+        const double f = phi3(xp, xs + 3 * ((int64_t)nv.begin[pn[su]] + u),
+                              xs + 3 * ((int64_t)nv.begin[pn[sv]] + v));
+        ++m;
+        const double d = f - mean;
+        mean += d / (double)m;
+        m2 += d * (f - mean);
+        if (m < 2) continue;
+        sig = sqrt(m2 / (double)(m - 1) / (double)m);
+        const bool cond = k.z * sig <= (k.eps * (plo + t * (mean - k.z * sig)) + k.tau) / k.t_root;
+        if ((cond && m >= k.m_min) || m == k.m_limit) {
+            pass = cond && m >= k.m_min;
+            break;
+        }
+    }
+    m_used = m;
+    return pass;
+}
+
+// 2. Monte Carlo test and commit (Algorithms 3-5), one workgroup per triple.
+// Pass 1 samples every point of the distinct nodes (stopping early once a
+// point has failed); the triple is summarized only if all points pass, in
+// which case pass 2 commits T_i mu and T_i (mu - z sigma_mu) per point.
+__global__ __launch_bounds__(kMcThreads) void mc_kernel(
+    const Item *__restrict__ mc_list, NodeView nv, const double *__restrict__ xs,
+    const double *__restrict__ node_phil, double *__restrict__ est, double *__restrict__ lb,
+    unsigned long long *__restrict__ node_cov, MtConst k, MtCounters *__restrict__ ctr,
+    Item *__restrict__ base_list, Item *__restrict__ child_buf, uint8_t *__restrict__ child_flag) {
+    __shared__ int failed;
+    __shared__ double c_mean[kMcCache], c_low[kMcCache];
+    const unsigned long long n_mc = ctr->n_mc;
+    for (unsigned long long w = blockIdx.x; w < n_mc; w += gridDim.x) {
+        const Item it = mc_list[w];
+        const int pn[3] = {it.p1, it.p2, it.p3};
+        const int64_t n1 = nv.end[it.p1] - nv.begin[it.p1], n2 = nv.end[it.p2] - nv.begin[it.p2],
+                      n3 = nv.end[it.p3] - nv.begin[it.p3];
+        const Roles r = roles_of(it.p1, it.p2, it.p3, n1, n2, n3);
+        const char cs = canonical_case(it.p1, it.p2, it.p3);
+        int64_t sz[3] = {0, 0, 0}, total = 0;
+        for (int q = 0; q < r.n_roles; ++q) {
+            sz[q] = nv.end[r.node[q]] - nv.begin[r.node[q]];
+            total += sz[q];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) failed = 0;
+        __syncthreads();
+        unsigned long long drawn = 0;
+        for (int64_t e = threadIdx.x; e < total; e += kMcThreads) {
+            int q = 0;
+            int64_t off = e;
+            while (off >= sz[q]) off -= sz[q++];
+            const int64_t xr = nv.begin[r.node[q]] + off;
+            double mean, sig;
+            int m;
+            const bool ok = mc_point(it, cs, r.slot[q], off, xr, n1, n2, n3, pn, nv, xs,
+                                     (double)r.t[q], node_phil[r.node[q]], k, &failed, mean, sig, m);
+            drawn += m;
+            if (!ok) {
+                failed = 1;
+                break;
+            }
+            if (e < kMcCache) {
+                c_mean[e] = mean;
+                c_low[e] = mean - k.z * sig;
+            }
+        }
+        atomicAdd(&ctr->mc_samples, drawn);
+        __syncthreads();
+        if (failed) {
+            if (threadIdx.x == 0) {
+                atomicAdd(&ctr->mc_failed, 1ull);
+                if (nv.left[it.p1] < 0 && nv.left[it.p2] < 0 && nv.left[it.p3] < 0)
+                    base_list[atomicAdd(&ctr->n_base, 1ull)] = it;
+                else
+                    emit_children(nv, it, it.slot, child_buf, child_flag);
+            }
+            continue;
+        }
+        for (int64_t e = threadIdx.x; e < total; e += kMcThreads) {
+            int q = 0;
+            int64_t off = e;
+            while (off >= sz[q]) off -= sz[q++];
+            const int64_t xr = nv.begin[r.node[q]] + off;
+            const double t = (double)r.t[q];
+            double mean, low;
+            if (e < kMcCache) {
+                mean = c_mean[e];
+                low = c_low[e];
+            } else {
+                double sig;
+                int m;
+                mc_point(it, cs, r.slot[q], off, xr, n1, n2, n3, pn, nv, xs, t,
+                         node_phil[r.node[q]], k, nullptr, mean, sig, m);
+                low = mean - k.z * sig;
+            }
+            atomicAdd(&est[xr], t * mean);
+            atomicAdd(&lb[xr], t * low);
+        }
+        if (threadIdx.x == 0) {
+            atomicAdd(&ctr->mc_prunes, 1ull);
+            if (k.want_cov)
+                for (int q = 0; q < r.n_roles; ++q)
+                    atomicAdd(&node_cov[r.node[q]], (unsigned long long)r.t[q]);
+        }
+    }
+}
+
+// 3. Exhaustive base case over a triple of leaves (MTPotentialBase): all
+// (i, j, k) in P1 x P2 x P3 with depth-first ranks i < j < k.  One
+// workgroup per leaf triple; leaves hold at most kLeafMax points.
+constexpr int kLeafMax = 32;
+constexpr int kBaseThreads = 256;
+
+template <typename T>
+struct BaseLds {
+    double x[3][3][kLeafMax];                    // coordinates of P1, P2, P3
+    T ua[kLeafMax][kLeafMax], uq[kLeafMax][kLeafMax], uw[kLeafMax][kLeafMax];  // (i, j)
+    T cb[kLeafMax][kLeafMax], cq[kLeafMax][kLeafMax], co[kLeafMax][kLeafMax];  // (j, k)
+    double pj[kLeafMax][8];                      // Phi_j partials
+    double pk[kLeafMax];                         // Phi_k partials
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBaseThreads) void base_kernel(
+    const Item *__restrict__ base_list, NodeView nv, const double *__restrict__ xs,
+    double *__restrict__ est, double *__restrict__ lb, unsigned long long *__restrict__ node_cov,
+    MtConst k, MtCounters *__restrict__ ctr) {
+    __shared__ BaseLds<T> s;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int kl = lane & 31, ih = lane >> 5;  // this lane's k and its half of the i points
+    const unsigned long long n_base = ctr->n_base;
+    for (unsigned long long w = blockIdx.x; w < n_base; w += gridDim.x) {
+        const Item it = base_list[w];
+        const int b1 = nv.begin[it.p1], b2 = nv.begin[it.p2], b3 = nv.begin[it.p3];
+        const int n1 = nv.end[it.p1] - b1, n2 = nv.end[it.p2] - b2, n3 = nv.end[it.p3] - b3;
+        __syncthreads();
+        if (tid < 3 * kLeafMax) {
+            const int set = tid / kLeafMax, o = tid % kLeafMax;
+            const int b = set == 0 ? b1 : (set == 1 ? b2 : b3);
+            const int cnt = set == 0 ? n1 : (set == 1 ? n2 : n3);
+            for (int c = 0; c < 3; ++c) s.x[set][c][o] = o < cnt ? xs[3 * (int64_t)(b + o) + c] : 0.0;
+        }
+        if (tid < kLeafMax) s.pk[tid] = 0.0;
+        for (int e = tid; e < kLeafMax * 8; e += kBaseThreads) s.pj[e / 8][e % 8] = 0.0;
+        __syncthreads();
+        // pair tables: (i, j) and (j, k), masked by rank order and size
+        for (int e = tid; e < kLeafMax * kLeafMax; e += kBaseThreads) {
+            const int a = e / kLeafMax, c = e % kLeafMax;
+            double pa, pq, pw, pia;
+            // (i = a, j = c)
+            pair_terms(s.x[1][0][c] - s.x[0][0][a], s.x[1][1][c] - s.x[0][1][a],
+                       s.x[1][2][c] - s.x[0][2][a], a < n1 && c < n2 && b1 + a < b2 + c, pa, pq, pw,
+                       pia);
+            s.ua[a][c] = (T)pa;
+            s.uq[a][c] = (T)pq;
+            s.uw[a][c] = (T)pw;
+            // (j = a, k = c)
+            pair_terms(s.x[2][0][c] - s.x[1][0][a], s.x[2][1][c] - s.x[1][1][a],
+                       s.x[2][2][c] - s.x[1][2][a], a < n2 && c < n3 && b2 + a < b3 + c, pa, pq, pw,
+                       pia);
+            s.cb[a][c] = (T)pa;
+            s.cq[a][c] = (T)pq;
+            s.co[a][c] = (T)(0.375 * pia);
+        }
+        // (i, k) terms of this lane: i = 8 m + 2 wave + ih, m = 0..3
+        T ag[4], aq[4], aw[4], acc_i[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int il = 8 * m + 2 * wave + ih;
+            double pa, pq, pw, pia;
+            pair_terms(s.x[2][0][kl] - s.x[0][0][il], s.x[2][1][kl] - s.x[0][1][il],
+                       s.x[2][2][kl] - s.x[0][2][il], il < n1 && kl < n3 && b1 + il < b3 + kl, pa,
+                       pq, pw, pia);
+            ag[m] = (T)pa;
+            aq[m] = (T)pq;
+            aw[m] = (T)pw;
+            acc_i[m] = T(0);
+        }
+        __syncthreads();
+        double acck = 0.0;
+        for (int j = 0; j < n2; ++j) {
+            const T bj = s.cb[j][kl], qj = s.cq[j][kl], oj = s.co[j][kl];
+            const T bb = bj * bj;
+            T sk = T(0);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int il = 8 * m + 2 * wave + ih;
+                const T al = s.ua[il][j], qa = s.uq[il][j], wa = s.uw[il][j];
+                const T d = al - ag[m];
+                const T tt = (al + ag[m]) - bj;
+                const T mm = fma(-d, d, bb);
+                const T X = qa * aq[m];
+                const T Y = (wa * aw[m]) * (tt * mm);
+                const T psi = fma(oj, Y, X);
+                sk += psi;
+                acc_i[m] = fma(qj, psi, acc_i[m]);
+            }
+            const double v = (double)(qj * sk);
+            acck += v;
+            atomicAdd(&s.pj[j][lane & 7], v);
+        }
+        // Phi_i: sum over the 32 k lanes of each half-wave
+        double vi[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            double v = (double)acc_i[m];
+#pragma unroll
+            for (int sh = 16; sh >= 1; sh >>= 1) v += __shfl_xor(v, sh);
+            vi[m] = v;
+        }
+        if (kl == 0) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int il = 8 * m + 2 * wave + ih;
+                if (il < n1) {
+                    atomicAdd(&est[b1 + il], vi[m]);
+                    atomicAdd(&lb[b1 + il], vi[m]);
+                }
+            }
+        }
+        atomicAdd(&s.pk[kl], acck);
+        __syncthreads();
+        if (tid < kLeafMax) {
+            if (tid < n3) {
+                atomicAdd(&est[b3 + tid], s.pk[tid]);
+                atomicAdd(&lb[b3 + tid], s.pk[tid]);
+            }
+        } else if (tid < 2 * kLeafMax) {
+            const int j = tid - kLeafMax;
+            if (j < n2) {
+                double v = 0.0;
+                for (int q = 0; q < 8; ++q) v += s.pj[j][q];
+                atomicAdd(&est[b2 + j], v);
+                atomicAdd(&lb[b2 + j], v);
+            }
+        } else if (tid == 2 * kLeafMax) {
+            atomicAdd(&ctr->base_cases, 1ull);
+            const Roles r = roles_of(it.p1, it.p2, it.p3, n1, n2, n3);
+            unsigned long long tri = 0;
+            const char cs = canonical_case(it.p1, it.p2, it.p3);
+            if (cs == 'a') tri = (unsigned long long)(n1 * (int64_t)(n1 - 1) * (n1 - 2) / 6);
+            else if (cs == 'b') tri = (unsigned long long)(comb2(n1) * n3);
+            else if (cs == 'c') tri = (unsigned long long)(n1 * comb2(n2));
+            else tri = (unsigned long long)n1 * n2 * n3;
+            atomicAdd(&ctr->base_triples, tri);
+            if (k.want_cov)
+                for (int q = 0; q < r.n_roles; ++q)
+                    atomicAdd(&node_cov[r.node[q]], (unsigned long long)r.t[q]);
+        }
+    }
+}
+
+__global__ void reset_round_kernel(MtCounters *ctr) {
+    ctr->n_base = 0;
+    ctr->n_mc = 0;
+}
+
+__global__ void zero_u64_kernel(unsigned long long *__restrict__ p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+__global__ void zero_counters_kernel(MtCounters *ctr) {
+    ctr->n_base = ctr->n_mc = ctr->visited = ctr->det_prunes = ctr->mc_prunes = 0;
+    ctr->mc_failed = ctr->base_cases = ctr->base_triples = ctr->mc_samples = 0;
+}
+
+// 5. Phi^l(P) = min over x in P of LB(x), LB(x) = lb[x] + sum of the node
+// lower-bound increments of x's leaf and its ancestors.  Top-down sums and
+// bottom-up minima run in one workgroup, depth by depth.
+__global__ __launch_bounds__(1024) void refresh_down_kernel(const int32_t *__restrict__ depth_nodes,
+                                                            const int *__restrict__ depth_off,
+                                                            int n_depths,
+                                                            const int32_t *__restrict__ parent,
+                                                            const double *__restrict__ node_lo,
+                                                            double *__restrict__ cum) {
+    for (int d = 0; d < n_depths; ++d) {
+        for (int e = depth_off[d] + threadIdx.x; e < depth_off[d + 1]; e += blockDim.x) {
+            const int v = depth_nodes[e];
+            cum[v] = node_lo[v] + (parent[v] >= 0 ? cum[parent[v]] : 0.0);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void refresh_leaf_kernel(const int32_t *__restrict__ leaves, int n_leaves,
+                                    const int32_t *__restrict__ begin,
+                                    const int32_t *__restrict__ end, const double *__restrict__ lb,
+                                    const double *__restrict__ cum, double *__restrict__ phil) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_leaves) return;
+    const int v = leaves[e];
+    double mn = INFINITY;
+    for (int r = begin[v]; r < end[v]; ++r) mn = fmin(mn, lb[r]);
+    phil[v] = mn + cum[v];
+}
+
+__global__ __launch_bounds__(1024) void refresh_up_kernel(const int32_t *__restrict__ depth_nodes,
+                                                          const int *__restrict__ depth_off,
+                                                          int n_depths,
+                                                          const int32_t *__restrict__ left,
+                                                          const int32_t *__restrict__ right,
+                                                          double *__restrict__ phil) {
+    for (int d = n_depths - 1; d >= 0; --d) {
+        for (int e = depth_off[d] + threadIdx.x; e < depth_off[d + 1]; e += blockDim.x) {
+            const int v = depth_nodes[e];
+            if (left[v] >= 0) phil[v] = fmin(phil[left[v]], phil[right[v]]);
+        }
+        __syncthreads();
+    }
+}
+
+// 6. Top-down (Section 3): node accumulators to points, back to input order.
+__global__ void topdown_kernel(int n, const int32_t *__restrict__ leaf_of,
+                               const int32_t *__restrict__ parent, const int32_t *__restrict__ perm,
+                               const double *__restrict__ est, const double *__restrict__ node_acc,
+                               const unsigned long long *__restrict__ node_cov,
+                               double *__restrict__ phi, int64_t *__restrict__ coverage) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    double acc = est[r];
+    unsigned long long cv = 0;
+    for (int v = leaf_of[r]; v >= 0; v = parent[v]) {
+        acc += node_acc[v];
+        if (coverage) cv += node_cov[v];
+    }
+    phi[perm[r]] = acc;
+    if (coverage) coverage[perm[r]] = (int64_t)cv;
+}
+
+template <typename T>
+mb_status dalloc(Scratch &sc, T **p, size_t count, hipStream_t s) {
+    mb_status st = sc.alloc(sizeof(T) * (count ? count : 1), s);
+    *p = sc.as<T>();
+    return st;
+}
+
+}  // namespace
+
+double normal_quantile_upper(double alpha_half) {
+    // z with P(Z > z) = alpha_half, by Newton's method on erfc
+    if (!(alpha_half > 0.0 && alpha_half < 0.5)) return 0.0;
+    double z = 1.0;
+    for (int it = 0; it < 100; ++it) {
+        const double f = 0.5 * std::erfc(z / std::sqrt(2.0)) - alpha_half;
+        const double df = -std::exp(-0.5 * z * z) / std::sqrt(2.0 * M_PI);
+        const double step = f / df;
+        z -= step;
+        if (std::fabs(step) < 1e-16 * std::fabs(z)) break;
+    }
+    return z;
+}
+
+mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, int64_t *coverage,
+                        MtStats *stats, hipStream_t s) {
+    const int n = (int)t->h.n;
+    const int M = t->h.n_nodes;
+    mb_status st;
+    auto t0 = std::chrono::steady_clock::now();
+    if (n < 3) {
+        if ((st = zero_doubles(phi, n, s)) != MB_OK) return st;
+        if (coverage && n > 0) MB_HIP(hipMemsetAsync(coverage, 0, sizeof(int64_t) * n, s));
+        MB_HIP(hipStreamSynchronize(s));
+        return MB_OK;
+    }
+    // host lists: leaves, depth offsets
+    std::vector<int32_t> leaves;
+    for (int v = 0; v < M; ++v)
+        if (t->h.left[v] < 0) leaves.push_back(v);
+    const int n_depths = t->h.max_depth + 1;
+
+    Scratch s_est, s_lb, s_acc, s_lo, s_cov, s_phil, s_cum, s_ctr, s_leaves, s_doff;
+    double *est, *lb, *node_acc, *node_lo, *node_phil, *cum;
+    unsigned long long *node_cov;
+    MtCounters *ctr;
+    int32_t *d_leaves;
+    int *d_doff;
+    if ((st = dalloc(s_est, &est, n, s)) || (st = dalloc(s_lb, &lb, n, s)) ||
+        (st = dalloc(s_acc, &node_acc, M, s)) || (st = dalloc(s_lo, &node_lo, M, s)) ||
+        (st = dalloc(s_cov, &node_cov, M, s)) || (st = dalloc(s_phil, &node_phil, M, s)) ||
+        (st = dalloc(s_cum, &cum, M, s)) || (st = dalloc(s_ctr, &ctr, 1, s)) ||
+        (st = dalloc(s_leaves, &d_leaves, leaves.size(), s)) ||
+        (st = dalloc(s_doff, &d_doff, t->depth_off.size(), s)))
+        return st;
+    MB_HIP(hipMemcpyAsync(d_leaves, leaves.data(), sizeof(int32_t) * leaves.size(),
+                          hipMemcpyHostToDevice, s));
+    MB_HIP(hipMemcpyAsync(d_doff, t->depth_off.data(), sizeof(int) * t->depth_off.size(),
+                          hipMemcpyHostToDevice, s));
+    for (double *p : {est, lb}) zero_doubles(p, n, s);
+    for (double *p : {node_acc, node_lo, node_phil, cum}) zero_doubles(p, M, s);
+    zero_u64_kernel<<<(M + 255) / 256, 256, 0, s>>>(node_cov, M);
+    zero_counters_kernel<<<1, 1, 0, s>>>(ctr);
+
+    const int chunk = std::max(1, prm.chunk);
+    // two LIFO stacks: the near stack is drained first; triples whose three
+    // boxes are pairwise apart are deferred to the far stack meanwhile
+    int64_t cap = std::max<int64_t>(16 * (int64_t)chunk, 1 << 16);
+    int64_t fcap = cap;
+    Scratch s_stack, s_far, s_mc, s_base, s_child, s_flag, s_dbuf, s_dflag, s_num, s_tmp;
+    Item *stack, *far, *mc_list, *base_list, *child_buf, *defer_buf;
+    uint8_t *child_flag, *defer_flag;
+    int *d_num;
+    if ((st = dalloc(s_stack, &stack, cap, s)) || (st = dalloc(s_far, &far, fcap, s)) ||
+        (st = dalloc(s_mc, &mc_list, chunk, s)) || (st = dalloc(s_base, &base_list, chunk, s)) ||
+        (st = dalloc(s_child, &child_buf, 8 * (size_t)chunk, s)) ||
+        (st = dalloc(s_flag, &child_flag, 8 * (size_t)chunk, s)) ||
+        (st = dalloc(s_dbuf, &defer_buf, chunk, s)) || (st = dalloc(s_dflag, &defer_flag, chunk, s)) ||
+        (st = dalloc(s_num, &d_num, 2, s)))
+        return st;
+    size_t tmp_bytes = 0;
+    MB_HIP(hipcub::DeviceSelect::Flagged(nullptr, tmp_bytes, child_buf, child_flag, stack, d_num,
+                                         8 * chunk, s));
+    if ((st = s_tmp.alloc(tmp_bytes, s)) != MB_OK) return st;
+
+    const Item root{0, 0, 0, 0};
+    MB_HIP(hipMemcpyAsync(stack, &root, sizeof(Item), hipMemcpyHostToDevice, s));
+    int64_t top = 1, far_top = 0;
+    int phase = 0;  // 0: near stack (far triples deferred), 1: far stack
+
+    NodeView nv{t->begin, t->end, t->left, t->right, t->lo, t->hi, t->centroid};
+    MtConst k;
+    k.n = n;
+    k.eps = prm.eps;
+    k.tau = prm.tau;
+    k.z = prm.alpha > 0.0 ? normal_quantile_upper(prm.alpha / 2.0) : 0.0;
+    k.t_root = (double)(n - 1) * (double)(n - 2) / 2.0;
+    k.m_limit = prm.m_limit;
+    k.m_min = prm.m_min;
+    k.zeta = prm.zeta;
+    k.seed32 = (uint32_t)(prm.seed ^ (prm.seed >> 32));
+    k.use_mc = prm.alpha > 0.0 ? 1 : 0;
+    k.want_cov = coverage ? 1 : 0;
+
+    auto grow = [&](Scratch &sc, Item *&buf, int64_t &c, int64_t keep, int64_t need) -> mb_status {
+        if (need <= c) return MB_OK;
+        const int64_t nc = std::max<int64_t>(2 * c, need);
+        Scratch s2;
+        Item *b2;
+        mb_status e = dalloc(s2, &b2, nc, s);
+        if (e != MB_OK) return e;
+        if (keep > 0) {
+            hipError_t he = hipMemcpyAsync(b2, buf, sizeof(Item) * keep, hipMemcpyDeviceToDevice, s);
+            if (he != hipSuccess) return hip_fail(he, "stack copy");
+        }
+        std::swap(sc.ptr, s2.ptr);
+        buf = b2;
+        c = nc;
+        return MB_OK;
+    };
+
+    int64_t max_stack = 1, rounds = 0;
+    for (;;) {
+        if (top == 0) {
+            if (phase == 1 || far_top == 0) break;
+            // near field done: the deferred far triples become the stack
+            phase = 1;
+            std::swap(s_stack.ptr, s_far.ptr);
+            std::swap(stack, far);
+            std::swap(cap, fcap);
+            top = far_top;
+            far_top = 0;
+            continue;
+        }
+        const int B = (int)std::min<int64_t>(top, chunk);
+        Item *items = stack + (top - B);
+        reset_round_kernel<<<1, 1, 0, s>>>(ctr);
+        classify_kernel<<<(B + 255) / 256, 256, 0, s>>>(items, B, nv, node_phil, node_acc, node_lo,
+                                                       node_cov, k, ctr, mc_list, base_list,
+                                                       child_buf, child_flag, phase == 0 ? 1 : 0,
+                                                       defer_buf, defer_flag);
+        if (k.use_mc)
+            mc_kernel<<<std::min(B, 4096), kMcThreads, 0, s>>>(mc_list, nv, t->xs, node_phil, est,
+                                                               lb, node_cov, k, ctr, base_list,
+                                                               child_buf, child_flag);
+        if (prm.base_prec == MB_FP64)
+            base_kernel<double><<<std::min(B, 8192), kBaseThreads, 0, s>>>(
+                base_list, nv, t->xs, est, lb, node_cov, k, ctr);
+        else
+            base_kernel<float><<<std::min(B, 8192), kBaseThreads, 0, s>>>(
+                base_list, nv, t->xs, est, lb, node_cov, k, ctr);
+        MB_HIP(hipGetLastError());
+        // children of split triples, in order, onto the stack where the chunk was;
+        // deferred far triples, in order, onto the far stack
+        if ((st = grow(s_stack, stack, cap, top - B, top - B + 8 * (int64_t)B)) != MB_OK) return st;
+        MB_HIP(hipcub::DeviceSelect::Flagged(s_tmp.ptr, tmp_bytes, child_buf, child_flag,
+                                             stack + (top - B), d_num, 8 * B, s));
+        if (phase == 0) {
+            if ((st = grow(s_far, far, fcap, far_top, far_top + B)) != MB_OK) return st;
+            MB_HIP(hipcub::DeviceSelect::Flagged(s_tmp.ptr, tmp_bytes, defer_buf, defer_flag,
+                                                 far + far_top, d_num + 1, B, s));
+        }
+        int num[2] = {0, 0};
+        MB_HIP(hipMemcpyAsync(num, d_num, sizeof(num), hipMemcpyDeviceToHost, s));
+        // Phi^l refresh for the next round
+        refresh_down_kernel<<<1, 1024, 0, s>>>(t->depth_nodes, d_doff, n_depths, t->parent,
+                                               node_lo, cum);
+        refresh_leaf_kernel<<<((int)leaves.size() + 255) / 256, 256, 0, s>>>(
+            d_leaves, (int)leaves.size(), t->begin, t->end, lb, cum, node_phil);
+        refresh_up_kernel<<<1, 1024, 0, s>>>(t->depth_nodes, d_doff, n_depths, t->left, t->right,
+                                             node_phil);
+        MB_HIP(hipGetLastError());
+        MB_HIP(hipStreamSynchronize(s));
+        top = top - B + num[0];
+        if (phase == 0) far_top += num[1];
+        max_stack = std::max(max_stack, top + far_top);
+        ++rounds;
+    }
+    topdown_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, t->leaf_of, t->parent, t->perm, est, node_acc,
+                                                   node_cov, phi, coverage);
+    MB_HIP(hipGetLastError());
+    MtCounters hc;
+    MB_HIP(hipMemcpyAsync(&hc, ctr, sizeof hc, hipMemcpyDeviceToHost, s));
+    MB_HIP(hipStreamSynchronize(s));
+    if (stats) {
+        stats->visited = (int64_t)hc.visited;
+        stats->det_prunes = (int64_t)hc.det_prunes;
+        stats->mc_prunes = (int64_t)hc.mc_prunes;
+        stats->mc_failed = (int64_t)hc.mc_failed;
+        stats->base_cases = (int64_t)hc.base_cases;
+        stats->base_triples = (int64_t)hc.base_triples;
+        stats->mc_samples = (int64_t)hc.mc_samples;
+        stats->max_stack = max_stack;
+        stats->rounds = rounds;
+        stats->traverse_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return MB_OK;
+}
+
+}  // namespace mb

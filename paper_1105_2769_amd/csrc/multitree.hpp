@@ -1,0 +1,35 @@
+// Host interface of the triple-tree traversal.
+#pragma once
+
+#include <cstdint>
+
+#include "mb_internal.hpp"
+#include "tree.hpp"
+
+namespace mb {
+
+struct MtParams {
+    double eps = 0.0, tau = 0.0, alpha = 0.0;
+    int m_limit = 128, m_min = 30;
+    double zeta = 4.0;
+    uint64_t seed = 0;
+    int base_prec = MB_FP32C;
+    int chunk = 32768;
+};
+
+struct MtStats {
+    int64_t visited = 0, det_prunes = 0, mc_prunes = 0, mc_failed = 0, base_cases = 0,
+            base_triples = 0, mc_samples = 0, max_stack = 0, rounds = 0;
+    double traverse_ms = 0.0;
+};
+
+// z with P(Z > z) = alpha_half for a standard normal Z (0 if out of range).
+double normal_quantile_upper(double alpha_half);
+
+// Runs the traversal over a built tree; phi (device, input order) receives
+// the estimate, coverage (device, nullable) the number of tuples credited
+// to each point.
+mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, int64_t *coverage,
+                        MtStats *stats, hipStream_t s);
+
+}  // namespace mb

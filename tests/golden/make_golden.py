@@ -35,5 +35,28 @@ def c2_samples():
         json.dump(out, f, indent=1)
 
 
+def c3_samples(threads: int = 0):
+    """Direct Phi at 64 sampled particles of the 262144-point saturated mixture."""
+    x = workloads.saturated_gaussian_mixture(262144, seed=3)
+    idx = workloads.sample_indices(262144, 64, seed=1003)
+    t = time.time()
+    phi = direct.phi(x, idx, threads=threads)
+    out = {
+        "workload": "saturated Gaussian mixture: 32 components, means U[0,100]^3, sigma 2.0, "
+                    "min separation 0.3, seed 3",
+        "n": 262144,
+        "sample_seed": 1003,
+        "indices": idx.tolist(),
+        "phi": [repr(float(v)) for v in phi],
+        "oracle_seconds": time.time() - t,
+    }
+    with open(os.path.join(HERE, "c3_direct_samples.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 if __name__ == "__main__":
-    c2_samples()
+    which = sys.argv[1] if len(sys.argv) > 1 else "c2"
+    if which == "c2":
+        c2_samples()
+    elif which == "c3":
+        c3_samples(int(sys.argv[2]) if len(sys.argv) > 2 else 0)

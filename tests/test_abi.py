@@ -41,3 +41,33 @@ def test_invalid_arguments_no_device():
     assert b"precision" in lib.mb_last_error() or b"null" in lib.mb_last_error()
     assert lib.mb_eval_direct(None, 0, 0, None, None) == 0
     assert lib.mb_version() >= 100
+
+
+def test_normal_quantile_matches_python():
+    # z_{alpha/2} of the Monte Carlo stop rule (host code, no device needed)
+    from statistics import NormalDist
+
+    import paper_1105_2769_amd as mb
+
+    for a in (0.5, 0.2, 0.1, 0.05, 0.01, 0.001):
+        assert mb.normal_quantile(a / 2) == pytest.approx(NormalDist().inv_cdf(1 - a / 2), rel=1e-12)
+    assert mb.normal_quantile(0.0) == 0.0
+
+
+def test_multitree_bad_params_no_device():
+    import ctypes
+
+    lib = _lib.lib()
+    p = _lib.MtParams()
+    lib.mb_mt_params_default(ctypes.byref(p))
+    assert p.m_limit == 128 and p.m_min == 30 and p.zeta == 4.0
+    for field, bad in (("eps_rel", -1.0), ("alpha", 1.0), ("alpha", -0.1), ("m_limit", 1),
+                       ("base_prec", 9), ("chunk", 0)):
+        q = _lib.MtParams()
+        lib.mb_mt_params_default(ctypes.byref(q))
+        setattr(q, field, bad)
+        assert lib.mb_eval_multitree(None, 10, 8, ctypes.byref(q), None, None, None, None,
+                                     None) == 1, field
+    out = ctypes.c_void_p()
+    assert lib.mb_build_kdtree(None, 10, 0, None, ctypes.byref(out)) == 1
+    assert lib.mb_build_kdtree(None, 10, 64, None, ctypes.byref(out)) in (1, 5)

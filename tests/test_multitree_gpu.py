@@ -1,0 +1,148 @@
+"""The HIP kd-tree and triple-tree traversal against the CPU oracle.
+
+Tree: bit-exact permutation, node ranges and boxes (index and min/max
+work), centroids to rounding.  Traversal: with eps = 0 and alpha = 0 it
+reduces to the exhaustive sum; every point is credited exactly C(N-1, 2)
+tuples; with alpha = 0 every point meets eps (Theorem 5.1); with alpha > 0
+at least a 1 - alpha fraction does (Theorem 5.2)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import direct as oracle_direct
+from oracle import kdtree as oracle_kdtree
+
+pytestmark = pytest.mark.gpu
+
+
+def dev(x, cuda):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x)).to(cuda)
+
+
+def clustered(n_per, centers, seed, spread=1.0):
+    """Jittered-lattice blobs (spacing 1.0) translated to the given centers."""
+    parts = [workloads.jittered_lattice(n_per, seed=seed + q) * spread + np.asarray(c)
+             for q, c in enumerate(centers)]
+    return np.concatenate(parts)
+
+
+CENTERS8 = [(0, 0, 0), (40, 0, 0), (0, 40, 0), (0, 0, 40), (40, 40, 0), (40, 0, 40), (0, 40, 40),
+            (40, 40, 40)]
+
+
+@pytest.mark.parametrize("case", ["lattice1000_32", "mixture3000_32", "uniform777_8", "lattice64_32",
+                                  "tiny5_1", "lattice300_7"])
+def test_tree_matches_oracle(case, cuda):
+    import paper_1105_2769_amd as mb
+
+    x = {"lattice1000_32": lambda: workloads.jittered_lattice(1000, 3),
+         "mixture3000_32": lambda: workloads.saturated_gaussian_mixture(3000, 5, components=6,
+                                                                         box=40.0),
+         "uniform777_8": lambda: workloads.uniform_cube(777, 4),
+         "lattice64_32": lambda: workloads.jittered_lattice(64, 5),
+         "tiny5_1": lambda: workloads.uniform_cube(5, 6),
+         "lattice300_7": lambda: workloads.jittered_lattice(300, 7)}[case]()
+    leaf = int(case.split("_")[1])
+    print(f"tree {case}", flush=True)
+    t = mb.KdTree(dev(x, cuda), leaf)
+    g = t.export()
+    o = oracle_kdtree.build_kdtree(x, leaf)
+    assert t.n_nodes == o.n_nodes
+    np.testing.assert_array_equal(g["perm"], o.perm)
+    np.testing.assert_array_equal(g["begin"], o.begin)
+    np.testing.assert_array_equal(g["end"], o.end)
+    np.testing.assert_array_equal(g["left"], o.left)
+    np.testing.assert_array_equal(g["right"], o.right)
+    np.testing.assert_array_equal(g["lo"], o.lo)
+    np.testing.assert_array_equal(g["hi"], o.hi)
+    np.testing.assert_allclose(g["centroid"], o.centroid, rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("n,leaf", [(3, 32), (20, 32), (130, 8), (513, 32), (700, 16)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32c", 1e-5)])
+def test_eps0_is_exhaustive(n, leaf, prec, tol, cuda):
+    import paper_1105_2769_amd as mb
+
+    x = workloads.jittered_lattice(n, seed=20 + n)
+    ref = oracle_direct.phi(x)
+    print(f"eps0 n={n} leaf={leaf} {prec}", flush=True)
+    phi, st, cov = mb.eval_multitree(dev(x, cuda), eps=0.0, alpha=0.0, leaf_size=leaf,
+                                     coverage=True, base_prec=prec)
+    got = phi.cpu().numpy()
+    np.testing.assert_allclose(got, ref, rtol=tol, atol=tol * np.abs(ref).max())
+    assert np.all(cov.cpu().numpy() == (n - 1) * (n - 2) // 2)
+    assert st["det_prunes"] == 0 and st["mc_prunes"] == 0
+
+
+def test_small_n(cuda):
+    import paper_1105_2769_amd as mb
+
+    for n in (1, 2):
+        phi, st = mb.eval_multitree(dev(workloads.uniform_cube(n, 1), cuda), leaf_size=8)
+        assert np.all(phi.cpu().numpy() == 0.0)
+
+
+def test_deterministic_guarantee(cuda):
+    # eight separated blobs: far triples of blobs are pruned by the bound
+    import paper_1105_2769_amd as mb
+
+    x = clustered(216, CENTERS8, seed=30)
+    n = x.shape[0]
+    idx = workloads.sample_indices(n, 96, seed=31)
+    ref = oracle_direct.phi(x, idx)
+    for eps in (0.1, 1e-2):
+        print(f"deterministic eps={eps}", flush=True)
+        phi, st, cov = mb.eval_multitree(dev(x, cuda), eps=eps, alpha=0.0, leaf_size=16,
+                                         coverage=True, base_prec="fp64")
+        rel = np.abs(phi.cpu().numpy()[idx] - ref) / np.abs(ref)
+        print(eps, st, rel.max())
+        assert st["det_prunes"] > 0
+        assert rel.max() <= eps
+        assert np.all(cov.cpu().numpy() == (n - 1) * (n - 2) // 2)
+
+
+def test_monte_carlo_guarantee(cuda):
+    import paper_1105_2769_amd as mb
+
+    x = clustered(512, CENTERS8[:6], seed=40, spread=1.0)
+    n = x.shape[0]
+    idx = workloads.sample_indices(n, 128, seed=41)
+    ref = oracle_direct.phi(x, idx)
+    eps, alpha = 1e-2, 0.05
+    phi, st, cov = mb.eval_multitree(dev(x, cuda), eps=eps, alpha=alpha, leaf_size=32,
+                                     coverage=True, seed=7)
+    rel = np.abs(phi.cpu().numpy()[idx] - ref) / np.abs(ref)
+    frac = float(np.mean(rel <= eps))
+    print("mc", st, "fraction within eps", frac, "max", rel.max())
+    assert st["mc_prunes"] > 0
+    assert frac >= 1 - alpha
+    assert np.all(cov.cpu().numpy() == (n - 1) * (n - 2) // 2)
+
+
+def test_tree_reuse_same_result(cuda):
+    import paper_1105_2769_amd as mb
+
+    x = clustered(125, CENTERS8[:4], seed=50)
+    xt = dev(x, cuda)
+    t = mb.KdTree(xt, 16)
+    a, _ = mb.eval_multitree(xt, eps=1e-2, alpha=0.0, leaf_size=16, tree=t, base_prec="fp64")
+    b, _ = mb.eval_multitree(xt, eps=1e-2, alpha=0.0, leaf_size=16, base_prec="fp64")
+    np.testing.assert_allclose(a.cpu().numpy(), b.cpu().numpy(), rtol=1e-12)
+
+
+def test_errors(cuda):
+    import paper_1105_2769_amd as mb
+
+    x = workloads.jittered_lattice(100, 1)
+    d = x.copy()
+    d[7] = d[3]
+    with pytest.raises(mb.MBError) as e:
+        mb.eval_multitree(dev(d, cuda), leaf_size=8)
+    assert e.value.status == 2
+    t = mb.KdTree(dev(x, cuda), 8)
+    with pytest.raises(mb.MBError):
+        mb.eval_multitree(dev(workloads.jittered_lattice(50, 1), cuda), tree=t)
