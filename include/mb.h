@@ -155,7 +155,7 @@ typedef struct {
 } mb_mt_params;
 
 /* Defaults: eps 1e-2, tau 0, alpha 0.05, m_limit 128, m_min 30, zeta 4,
- * seed 0, base_prec MB_FP32C, chunk 32768. */
+ * seed 0, base_prec MB_FP32C, chunk 65536. */
 void mb_mt_params_default(mb_mt_params *p);
 
 typedef struct {

@@ -229,7 +229,7 @@ void mb_mt_params_default(mb_mt_params *p) {
     p->zeta = 4.0;
     p->seed = 0;
     p->base_prec = MB_FP32C;
-    p->chunk = 32768;
+    p->chunk = 65536;
 }
 
 mb_status mb_eval_multitree(const double *x, int64_t n, int32_t leaf_size,
@@ -270,6 +270,13 @@ mb_status mb_eval_multitree(const double *x, int64_t n, int32_t leaf_size,
     mp.seed = p.seed;
     mp.base_prec = p.base_prec;
     mp.chunk = p.chunk;
+    {
+        double md2;
+        std::memcpy(&md2, &v.min_d2_bits, sizeof md2);
+        mp.r_min = n >= 2 ? std::sqrt(md2) : 0.0;
+    }
+    // spread bands in units of the mean leaf-box diagonal
+    mp.spread_unit = tree_mean_leaf_diagonal(t, s);
     MtStats ms;
     st = multitree_run(t, mp, phi, coverage, &ms, s);
     if (st == MB_OK && stats) {

@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cstring>
+#include <cmath>
 #include <functional>
 
 #include "tree.hpp"
@@ -331,6 +332,27 @@ mb_status tree_build(const double *x, int64_t n64, int leaf_size, hipStream_t s,
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = t;
     return MB_OK;
+}
+
+double tree_mean_leaf_diagonal(const DeviceTree *t, hipStream_t s) {
+    const int M = t->h.n_nodes;
+    std::vector<double> lo(3 * (size_t)M), hi(3 * (size_t)M);
+    if (hipMemcpyAsync(lo.data(), t->lo, sizeof(double) * 3 * M, hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(hi.data(), t->hi, sizeof(double) * 3 * M, hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return 0.0;
+    double sum = 0.0;
+    int cnt = 0;
+    for (int v = 0; v < M; ++v)
+        if (t->h.left[v] < 0) {
+            double d2 = 0.0;
+            for (int c = 0; c < 3; ++c) d2 += (hi[3 * v + c] - lo[3 * v + c]) * (hi[3 * v + c] - lo[3 * v + c]);
+            sum += std::sqrt(d2);
+            ++cnt;
+        }
+    return cnt ? sum / cnt : 0.0;
 }
 
 }  // namespace mb

@@ -35,6 +35,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -59,6 +61,7 @@ struct MtCounters {
 struct MtConst {
     int n;
     double eps, tau, z, t_root;
+    double r_min;  // closest pair distance of the point set: a floor for every d^l
     int m_limit, m_min;
     double zeta;
     uint32_t seed32;
@@ -189,7 +192,7 @@ __global__ __launch_bounds__(256) void classify_kernel(
     double *__restrict__ node_acc, double *__restrict__ node_lo,
     unsigned long long *__restrict__ node_cov, MtConst k, MtCounters *__restrict__ ctr,
     Item *__restrict__ mc_list, Item *__restrict__ base_list, Item *__restrict__ child_buf,
-    uint8_t *__restrict__ child_flag, int defer_far, Item *__restrict__ defer_buf,
+    uint8_t *__restrict__ child_flag, double spread_limit, Item *__restrict__ defer_buf,
     uint8_t *__restrict__ defer_flag) {
     const int slot = blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= n_items) return;
@@ -201,30 +204,45 @@ __global__ __launch_bounds__(256) void classify_kernel(
     const int64_t n1 = nv.end[p1] - nv.begin[p1], n2 = nv.end[p2] - nv.begin[p2],
                   n3 = nv.end[p3] - nv.begin[p3];
     const Roles r = roles_of(p1, p2, p3, n1, n2, n3);
-
-    // deterministic prune: case (d) with all three boxes apart
+    const double *lo = nv.lo, *hi = nv.hi;
+    // box distances of the distinct node pairs
+    double d12 = 0.0, d13 = 0.0, d23 = 0.0;
     if (r.n_roles == 3) {
-        const double d12 = box_min_dist(nv.lo + 3 * p1, nv.hi + 3 * p1, nv.lo + 3 * p2, nv.hi + 3 * p2);
-        const double d13 = box_min_dist(nv.lo + 3 * p1, nv.hi + 3 * p1, nv.lo + 3 * p3, nv.hi + 3 * p3);
-        const double d23 = box_min_dist(nv.lo + 3 * p2, nv.hi + 3 * p2, nv.lo + 3 * p3, nv.hi + 3 * p3);
-        if (d12 > 0.0 && d13 > 0.0 && d23 > 0.0 && defer_far) {
-            // far triple met while near-field work remains: examined later
-            defer_buf[slot] = it;
-            defer_flag[slot] = 1;
-            return;
-        }
-        atomicAdd(&ctr->visited, 1ull);
-        if (d12 > 0.0 && d13 > 0.0 && d23 > 0.0) {
-            const double prod = d12 * d13 * d23;
+        d12 = box_min_dist(lo + 3 * p1, hi + 3 * p1, lo + 3 * p2, hi + 3 * p2);
+        d13 = box_min_dist(lo + 3 * p1, hi + 3 * p1, lo + 3 * p3, hi + 3 * p3);
+        d23 = box_min_dist(lo + 3 * p2, hi + 3 * p2, lo + 3 * p3, hi + 3 * p3);
+    } else if (r.n_roles == 2) {
+        d12 = box_min_dist(lo + 3 * r.node[0], hi + 3 * r.node[0], lo + 3 * r.node[1],
+                           hi + 3 * r.node[1]);
+    }
+    // spread: the largest box distance between two nodes of the triple; it
+    // never decreases when a triple is split, so triples can be taken in
+    // bands of increasing spread
+    if (fmax(d12, fmax(d13, d23)) > spread_limit) {
+        defer_buf[slot] = it;
+        defer_flag[slot] = 1;
+        return;
+    }
+    atomicAdd(&ctr->visited, 1ull);
+
+    // deterministic prune (three distinct nodes): every pair of points is at
+    // least max(d^l, r_min) apart, so each phi of the triple lies in
+    // [-2 R, 11/8 R] with R = (product of those distances)^-3
+    if (r.n_roles == 3) {
+        const double e12 = fmax(d12, k.r_min), e13 = fmax(d13, k.r_min), e23 = fmax(d23, k.r_min);
+        if (e12 > 0.0 && e13 > 0.0 && e23 > 0.0) {
+            const double prod = e12 * e13 * e23;
             const double ru = 1.0 / (prod * prod * prod);
-            const double phi_lo = -2.0 * ru;
+            const double phi_lo = -2.0 * ru, phi_hi = 1.375 * ru;
             const double span = 3.375 * ru;
             double allow = INFINITY;
             for (int q = 0; q < 3; ++q)
                 allow = fmin(allow, node_phil[r.node[q]] + (double)r.t[q] * phi_lo);
             if (span <= (k.eps * allow + k.tau) / k.t_root) {
-                const double phic = phi3(nv.centroid + 3 * p1, nv.centroid + 3 * p2,
-                                         nv.centroid + 3 * p3);
+                // monopole estimate at the centroids, kept inside the bound interval
+                double phic = phi3(nv.centroid + 3 * p1, nv.centroid + 3 * p2,
+                                   nv.centroid + 3 * p3);
+                phic = isfinite(phic) ? fmin(fmax(phic, phi_lo), phi_hi) : 0.0;
                 for (int q = 0; q < 3; ++q) {
                     atomicAdd(&node_acc[r.node[q]], (double)r.t[q] * phic);
                     atomicAdd(&node_lo[r.node[q]], (double)r.t[q] * phi_lo);
@@ -234,8 +252,6 @@ __global__ __launch_bounds__(256) void classify_kernel(
                 return;
             }
         }
-    } else {
-        atomicAdd(&ctr->visited, 1ull);
     }
     // Monte Carlo candidate
     if (k.use_mc) {
@@ -333,52 +349,90 @@ __device__ __forceinline__ void sample_partners(char cs, int slot, int64_t xl, i
 }
 
 constexpr int kMcThreads = 256;
+constexpr int kMcWaves = kMcThreads / 64;
 constexpr int kMcCache = 2048;  // points whose (mu, lower bound) stay in LDS between passes
 
-// Draws samples for point xr (offset off in the node at slot `slot`) until
-// the termination rule holds or m_limit samples are taken; returns pass.
-__device__ __forceinline__ bool mc_point(const Item &it, char cs, int slot, int64_t off, int64_t xr,
-                                         int64_t n1, int64_t n2, int64_t n3, const int *pn,
-                                         const NodeView &nv, const double *__restrict__ xs,
-                                         double t, double plo, const MtConst &k,
-                                         const volatile int *failed, double &mean, double &sig,
-                                         int &m_used) {
-    const double *xp = xs + 3 * xr;
-    double m2 = 0.0;
-    mean = 0.0;
-    sig = 0.0;
-    int m = 0;
-    bool pass = false;
-    while (m < k.m_limit) {
-        if (failed && *failed) break;
-        uint32_t c[4] = {(uint32_t)xr, (uint32_t)m, (uint32_t)it.p1, (uint32_t)it.p2};
-        philox4x32_10(c, (uint32_t)it.p3, k.seed32);
-        const uint64_t rr = ((uint64_t)c[1] << 32) | c[0];
-        int64_t u, v;
-        int su, sv;
-        sample_partners(cs, slot, off, n1, n2, n3, rr, u, v, su, sv);
-        const double f = phi3(xp, xs + 3 * ((int64_t)nv.begin[pn[su]] + u),
-                              xs + 3 * ((int64_t)nv.begin[pn[sv]] + v));
-        ++m;
-        const double d = f - mean;
-        mean += d / (double)m;
-        m2 += d * (f - mean);
-        if (m < 2) continue;
-        sig = sqrt(m2 / (double)(m - 1) / (double)m);
-        const bool cond = k.z * sig <= (k.eps * (plo + t * (mean - k.z * sig)) + k.tau) / k.t_root;
-        if ((cond && m >= k.m_min) || m == k.m_limit) {
-            pass = cond && m >= k.m_min;
-            break;
-        }
+struct McPoint {
+    bool pass;
+    double mean, sig;
+    int drawn;
+};
+
+__device__ __forceinline__ double wave_incl_scan(double v, int lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double u = __shfl_up(v, d);
+        if (lane >= d) v += u;
     }
-    m_used = m;
-    return pass;
+    return v;
+}
+
+// Algorithm 4 for one point, by one wave: samples are drawn 64 at a time
+// (sample s by lane s mod 64); prefix sums give the running mean and
+// unbiased variance after every sample, and the first sample count m at
+// which the sequential loop would stop - the termination rule holding with
+// m >= m_min, or m = m_limit - is found with a ballot.  Every lane returns
+// the same result.  `failed` (nullable) aborts between batches.
+__device__ McPoint mc_point_wave(const Item &it, char cs, int slot, int64_t off, int64_t xr,
+                                 int64_t n1, int64_t n2, int64_t n3, const int *pn,
+                                 const NodeView &nv, const double *__restrict__ xs, double t,
+                                 double plo, const MtConst &k, const volatile int *failed,
+                                 int lane) {
+    const double *xp = xs + 3 * xr;
+    double f0 = 0.0, s1 = 0.0, s2 = 0.0;
+    int drawn = 0;
+    for (int base = 0; base < k.m_limit; base += 64) {
+        if (failed && *failed) break;
+        const int sidx = base + lane;
+        const bool valid = sidx < k.m_limit;
+        double f = 0.0;
+        if (valid) {
+            uint32_t c[4] = {(uint32_t)xr, (uint32_t)sidx, (uint32_t)it.p1, (uint32_t)it.p2};
+            philox4x32_10(c, (uint32_t)it.p3, k.seed32);
+            const uint64_t rr = ((uint64_t)c[1] << 32) | c[0];
+            int64_t u, v;
+            int su, sv;
+            sample_partners(cs, slot, off, n1, n2, n3, rr, u, v, su, sv);
+            f = phi3(xp, xs + 3 * ((int64_t)nv.begin[pn[su]] + u),
+                     xs + 3 * ((int64_t)nv.begin[pn[sv]] + v));
+        }
+        if (base == 0) f0 = __shfl(f, 0);  // shift for numerically stable sums
+        const double g = valid ? f - f0 : 0.0;
+        const double p1 = wave_incl_scan(g, lane), p2 = wave_incl_scan(g * g, lane);
+        const double t1 = s1 + p1, t2 = s2 + p2;
+        const double m = (double)(sidx + 1);
+        const double mean = f0 + t1 / m;
+        const double var = sidx >= 1 ? fmax(t2 - t1 * t1 / m, 0.0) / (m - 1.0) : 0.0;
+        const double sig = sqrt(var / m);
+        const bool cond =
+            valid && sidx >= 1 && k.z * sig <= (k.eps * (plo + t * (mean - k.z * sig)) + k.tau) / k.t_root;
+        const bool ok = cond && sidx + 1 >= k.m_min;
+        const bool stop = valid && (ok || sidx + 1 == k.m_limit);
+        const unsigned long long bal = __ballot(stop);
+        drawn = min(base + 64, k.m_limit);
+        if (bal) {
+            const int L = __ffsll((long long)bal) - 1;
+            McPoint r;
+            r.pass = __shfl((int)ok, L) != 0;
+            r.mean = __shfl(mean, L);
+            r.sig = __shfl(sig, L);
+            r.drawn = drawn;
+            return r;
+        }
+        s1 += __shfl(p1, 63);
+        s2 += __shfl(p2, 63);
+    }
+    McPoint r;
+    r.pass = false;
+    r.mean = r.sig = 0.0;
+    r.drawn = drawn;
+    return r;
 }
 
 // 2. Monte Carlo test and commit (Algorithms 3-5), one workgroup per triple.
-// Pass 1 samples every point of the distinct nodes (stopping early once a
-// point has failed); the triple is summarized only if all points pass, in
-// which case pass 2 commits T_i mu and T_i (mu - z sigma_mu) per point.
+// Waves take the points of the distinct nodes in turn; the triple is
+// summarized only if every point passes (any failure ends the test), in
+// which case the points are credited T_i mu and T_i (mu - z sigma_mu).
 __global__ __launch_bounds__(kMcThreads) void mc_kernel(
     const Item *__restrict__ mc_list, NodeView nv, const double *__restrict__ xs,
     const double *__restrict__ node_phil, double *__restrict__ est, double *__restrict__ lb,
@@ -386,6 +440,8 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
     Item *__restrict__ base_list, Item *__restrict__ child_buf, uint8_t *__restrict__ child_flag) {
     __shared__ int failed;
     __shared__ double c_mean[kMcCache], c_low[kMcCache];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
     const unsigned long long n_mc = ctr->n_mc;
     for (unsigned long long w = blockIdx.x; w < n_mc; w += gridDim.x) {
         const Item it = mc_list[w];
@@ -403,26 +459,26 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
         if (threadIdx.x == 0) failed = 0;
         __syncthreads();
         unsigned long long drawn = 0;
-        for (int64_t e = threadIdx.x; e < total; e += kMcThreads) {
+        for (int64_t e = wave; e < total; e += kMcWaves) {
+            if (failed) break;
             int q = 0;
             int64_t off = e;
             while (off >= sz[q]) off -= sz[q++];
             const int64_t xr = nv.begin[r.node[q]] + off;
-            double mean, sig;
-            int m;
-            const bool ok = mc_point(it, cs, r.slot[q], off, xr, n1, n2, n3, pn, nv, xs,
-                                     (double)r.t[q], node_phil[r.node[q]], k, &failed, mean, sig, m);
-            drawn += m;
-            if (!ok) {
-                failed = 1;
+            const McPoint res = mc_point_wave(it, cs, r.slot[q], off, xr, n1, n2, n3, pn, nv, xs,
+                                              (double)r.t[q], node_phil[r.node[q]], k, &failed,
+                                              lane);
+            drawn += res.drawn;
+            if (!res.pass) {
+                if (lane == 0) failed = 1;
                 break;
             }
-            if (e < kMcCache) {
-                c_mean[e] = mean;
-                c_low[e] = mean - k.z * sig;
+            if (e < kMcCache && lane == 0) {
+                c_mean[e] = res.mean;
+                c_low[e] = res.mean - k.z * res.sig;
             }
         }
-        atomicAdd(&ctr->mc_samples, drawn);
+        if (lane == 0) atomicAdd(&ctr->mc_samples, drawn);
         __syncthreads();
         if (failed) {
             if (threadIdx.x == 0) {
@@ -434,7 +490,7 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
             }
             continue;
         }
-        for (int64_t e = threadIdx.x; e < total; e += kMcThreads) {
+        for (int64_t e = wave; e < total; e += kMcWaves) {
             int q = 0;
             int64_t off = e;
             while (off >= sz[q]) off -= sz[q++];
@@ -445,14 +501,15 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
                 mean = c_mean[e];
                 low = c_low[e];
             } else {
-                double sig;
-                int m;
-                mc_point(it, cs, r.slot[q], off, xr, n1, n2, n3, pn, nv, xs, t,
-                         node_phil[r.node[q]], k, nullptr, mean, sig, m);
-                low = mean - k.z * sig;
+                const McPoint res = mc_point_wave(it, cs, r.slot[q], off, xr, n1, n2, n3, pn, nv, xs,
+                                                  t, node_phil[r.node[q]], k, nullptr, lane);
+                mean = res.mean;
+                low = res.mean - k.z * res.sig;
             }
-            atomicAdd(&est[xr], t * mean);
-            atomicAdd(&lb[xr], t * low);
+            if (lane == 0) {
+                atomicAdd(&est[xr], t * mean);
+                atomicAdd(&lb[xr], t * low);
+            }
         }
         if (threadIdx.x == 0) {
             atomicAdd(&ctr->mc_prunes, 1ull);
@@ -775,7 +832,11 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
     const Item root{0, 0, 0, 0};
     MB_HIP(hipMemcpyAsync(stack, &root, sizeof(Item), hipMemcpyHostToDevice, s));
     int64_t top = 1, far_top = 0;
-    int phase = 0;  // 0: near stack (far triples deferred), 1: far stack
+    // bands of spread: 0 (all boxes touching), then unit * 2^(phase - 1)
+    int phase = 0;
+    auto spread_limit = [&](int ph) {
+        return ph == 0 ? 0.0 : prm.spread_unit * std::ldexp(1.0, ph - 1);
+    };
 
     NodeView nv{t->begin, t->end, t->left, t->right, t->lo, t->hi, t->centroid};
     MtConst k;
@@ -784,6 +845,7 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
     k.tau = prm.tau;
     k.z = prm.alpha > 0.0 ? normal_quantile_upper(prm.alpha / 2.0) : 0.0;
     k.t_root = (double)(n - 1) * (double)(n - 2) / 2.0;
+    k.r_min = prm.r_min;
     k.m_limit = prm.m_limit;
     k.m_min = prm.m_min;
     k.zeta = prm.zeta;
@@ -809,11 +871,13 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
     };
 
     int64_t max_stack = 1, rounds = 0;
+    const bool trace = std::getenv("MB_TRACE") != nullptr;
+    auto last_print = std::chrono::steady_clock::now();
     for (;;) {
         if (top == 0) {
-            if (phase == 1 || far_top == 0) break;
-            // near field done: the deferred far triples become the stack
-            phase = 1;
+            if (far_top == 0) break;
+            // this band is done: the deferred triples become the stack
+            ++phase;
             std::swap(s_stack.ptr, s_far.ptr);
             std::swap(stack, far);
             std::swap(cap, fcap);
@@ -821,13 +885,14 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
             far_top = 0;
             continue;
         }
+        const double limit = (prm.spread_unit > 0.0 && phase < 64) ? spread_limit(phase) : INFINITY;
         const int B = (int)std::min<int64_t>(top, chunk);
         Item *items = stack + (top - B);
         reset_round_kernel<<<1, 1, 0, s>>>(ctr);
         classify_kernel<<<(B + 255) / 256, 256, 0, s>>>(items, B, nv, node_phil, node_acc, node_lo,
                                                        node_cov, k, ctr, mc_list, base_list,
-                                                       child_buf, child_flag, phase == 0 ? 1 : 0,
-                                                       defer_buf, defer_flag);
+                                                       child_buf, child_flag, limit, defer_buf,
+                                                       defer_flag);
         if (k.use_mc)
             mc_kernel<<<std::min(B, 4096), kMcThreads, 0, s>>>(mc_list, nv, t->xs, node_phil, est,
                                                                lb, node_cov, k, ctr, base_list,
@@ -844,7 +909,7 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
         if ((st = grow(s_stack, stack, cap, top - B, top - B + 8 * (int64_t)B)) != MB_OK) return st;
         MB_HIP(hipcub::DeviceSelect::Flagged(s_tmp.ptr, tmp_bytes, child_buf, child_flag,
                                              stack + (top - B), d_num, 8 * B, s));
-        if (phase == 0) {
+        if (limit < INFINITY) {
             if ((st = grow(s_far, far, fcap, far_top, far_top + B)) != MB_OK) return st;
             MB_HIP(hipcub::DeviceSelect::Flagged(s_tmp.ptr, tmp_bytes, defer_buf, defer_flag,
                                                  far + far_top, d_num + 1, B, s));
@@ -861,9 +926,19 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
         MB_HIP(hipGetLastError());
         MB_HIP(hipStreamSynchronize(s));
         top = top - B + num[0];
-        if (phase == 0) far_top += num[1];
+        if (limit < INFINITY) far_top += num[1];
         max_stack = std::max(max_stack, top + far_top);
         ++rounds;
+        if (trace && std::chrono::steady_clock::now() - last_print > std::chrono::seconds(5)) {
+            last_print = std::chrono::steady_clock::now();
+            MtCounters hc;
+            MB_HIP(hipMemcpy(&hc, ctr, sizeof hc, hipMemcpyDeviceToHost));
+            std::fprintf(stderr,
+                         "[mb multitree] round %lld phase %d stack %lld far %lld visited %llu det %llu "
+                         "mc %llu/%llu base %llu\n",
+                         (long long)rounds, phase, (long long)top, (long long)far_top, hc.visited,
+                         hc.det_prunes, hc.mc_prunes, hc.mc_failed, hc.base_cases);
+        }
     }
     topdown_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, t->leaf_of, t->parent, t->perm, est, node_acc,
                                                    node_cov, phi, coverage);

@@ -14,7 +14,12 @@ struct MtParams {
     double zeta = 4.0;
     uint64_t seed = 0;
     int base_prec = MB_FP32C;
-    int chunk = 32768;
+    int chunk = 65536;
+    double r_min = 0.0;  // closest pair distance (a sound floor for box distances)
+    // traversal order: triples are taken in bands of increasing spread (the
+    // largest box distance within the triple): 0, unit, 2 unit, 4 unit, ...;
+    // 0 disables the bands (one LIFO stack)
+    double spread_unit = 0.0;
 };
 
 struct MtStats {

@@ -44,4 +44,7 @@ TreeHost tree_topology(int64_t n, int leaf_size);
 mb_status tree_build(const double *x, int64_t n, int leaf_size, hipStream_t s, DeviceTree **out);
 void tree_free(DeviceTree *t);
 
+// Mean diagonal of the leaf bounding boxes (waits on s).
+double tree_mean_leaf_diagonal(const DeviceTree *t, hipStream_t s);
+
 }  // namespace mb
