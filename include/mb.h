@@ -197,6 +197,42 @@ mb_status mb_eval_multitree(const double *x, int64_t n, int32_t leaf_size,
                             const mb_mt_params *params, mb_tree tree, double *phi,
                             int64_t *coverage, mb_mt_stats *stats, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Factorized form (matrix products on MFMA)
+ * ---------------------------------------------------------------------- */
+
+typedef enum { MB_FP16 = 0, MB_BF16 = 1 } mb_half;
+
+typedef struct {
+    double pairmat_ms;  /* building the pair-matrix planes                          */
+    double gemm_ms;     /* the five products with their epilogues                   */
+    double near_ms;     /* exact near-field triples and the final combination       */
+    int64_t near_pairs; /* pairs closer than r_near                                  */
+    double gemm_flops;  /* MFMA flops issued (10 N_pad^3 per plane product)         */
+} mb_factor_stats;
+
+/*
+ * Phi(x) for all points through the product form of the potential.  The
+ * law of cosines writes the Axilrod-Teller phi (Section 1) as ten products
+ * of pairwise powers r_ij^e1 r_ik^e2 r_jk^e3 - the product-of-pairwise form
+ * the paper's method requires - so Phi_i = 1/2 sum_t c_t (A_t C_t B_t^T)_ii
+ * with pair matrices of r^e (e in -5, -3, -1, +1) with zero diagonals; this
+ * form is an extension, not in the paper.  Triples with a side shorter than
+ * r_near are excluded from the matrices and summed exactly in binary64.
+ *   fmt    : MB_FP16 or MB_BF16 operands of the matrix products.
+ *   planes : 1..3 - each matrix entry is held as a sum of `planes` numbers of
+ *            the format (a per-64x64-tile power of two keeps all in range);
+ *            products of planes are kept while their level is < planes.
+ *            Accumulation is binary32 inside 64-wide chunks, binary64 across.
+ *   r_near : >= 0, in the units of x.
+ *   stats  : host, nullable.
+ * Device memory: 4 * planes * Np^2 * 2 bytes, Np = N rounded up to 128
+ * (MB_ERR_OOM if it cannot be allocated).  Validation as mb_eval_direct.
+ * Waits on stream.
+ */
+mb_status mb_eval_factorized(const double *x, int64_t n, int32_t fmt, int32_t planes,
+                             double r_near, double *phi, mb_factor_stats *stats, void *stream);
+
 /*
  * z such that P(Z > z) = alpha_half for a standard normal Z: the quantile
  * z_{alpha/2} of the Monte Carlo stop rule is mb_normal_quantile(alpha / 2).

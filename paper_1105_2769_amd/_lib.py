@@ -57,6 +57,15 @@ class MtStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class FactorStats(ctypes.Structure):
+    _fields_ = [("pairmat_ms", ctypes.c_double), ("gemm_ms", ctypes.c_double),
+                ("near_ms", ctypes.c_double), ("near_pairs", ctypes.c_int64),
+                ("gemm_flops", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "mb_last_error": (ctypes.c_char_p, []),
@@ -74,7 +83,10 @@ SIGNATURES = {
     "mb_eval_multitree": (_c_i32, [_c_vp, _c_i64, _c_i32, ctypes.POINTER(MtParams), _c_vp, _c_vp,
                                    _c_vp, ctypes.POINTER(MtStats), _c_vp]),
     "mb_normal_quantile": (_c_dbl, [_c_dbl]),
+    "mb_eval_factorized": (_c_i32, [_c_vp, _c_i64, _c_i32, _c_i32, _c_dbl, _c_vp,
+                                    ctypes.POINTER(FactorStats), _c_vp]),
 }
+HALF = {"fp16": 0, "bf16": 1}
 
 
 def lib() -> ctypes.CDLL:
@@ -214,3 +226,16 @@ def eval_multitree(x, eps: float = 1e-2, alpha: float = 0.05, leaf_size: int = 3
 
 def normal_quantile(alpha_half: float) -> float:
     return float(lib().mb_normal_quantile(float(alpha_half)))
+
+
+def eval_factorized(x, fmt: str = "fp16", planes: int = 2, r_near: float = 1.5):
+    """Phi through the product form on MFMA (mb_eval_factorized); (phi, stats)."""
+    import torch
+
+    x = _points(x)
+    n = x.shape[0]
+    phi = torch.empty(n, dtype=torch.float64, device=x.device)
+    st = FactorStats()
+    check(lib().mb_eval_factorized(_c_vp(x.data_ptr()), n, HALF[fmt], int(planes), float(r_near),
+                                   _c_vp(phi.data_ptr()), ctypes.byref(st), stream_of(x)))
+    return phi, st.as_dict()

@@ -296,6 +296,36 @@ mb_status mb_eval_multitree(const double *x, int64_t n, int32_t leaf_size,
     return st;
 }
 
+mb_status mb_eval_factorized(const double *x, int64_t n, int32_t fmt, int32_t planes,
+                             double r_near, double *phi, mb_factor_stats *stats, void *stream) {
+    clear_error();
+    if (n < 0 || (n > 0 && (!x || !phi))) return fail(MB_ERR_INVALID, "bad points or output");
+    if (fmt != MB_FP16 && fmt != MB_BF16) return fail(MB_ERR_INVALID, "unknown operand format");
+    if (planes < 1 || planes > 3) return fail(MB_ERR_INVALID, "planes must be 1..3");
+    if (!(r_near >= 0.0) || !std::isfinite(r_near)) return fail(MB_ERR_INVALID, "bad r_near");
+    if (n >= ((int64_t)1 << 31)) return fail(MB_ERR_UNSUPPORTED, "n must be < 2^31");
+    if (stats) *stats = mb_factor_stats{};
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) return MB_OK;
+    ValidateOut v{};
+    mb_status st = check_points(x, n, s, &v);
+    if (st != MB_OK) return st;
+    if (n < 3) return zero_doubles(phi, n, s);
+    DeviceTree *t = nullptr;
+    if ((st = tree_build(x, n, 32, s, &t)) != MB_OK) return st;
+    FactorStats fs;
+    st = factorized_eval(t, (int)n, fmt, planes, r_near, phi, s, &fs);
+    tree_free(t);
+    if (st == MB_OK && stats) {
+        stats->pairmat_ms = fs.pairmat_ms;
+        stats->gemm_ms = fs.gemm_ms;
+        stats->near_ms = fs.near_ms;
+        stats->near_pairs = fs.near_pairs;
+        stats->gemm_flops = fs.gemm_flops;
+    }
+    return st;
+}
+
 double mb_normal_quantile(double alpha_half) { return normal_quantile_upper(alpha_half); }
 
 }  // extern "C"

@@ -82,4 +82,10 @@ size_t table_budget_bytes();
 mb_status direct_launch(const double *x, int64_t n, int prec, double scale, double *phi,
                         hipStream_t s);
 
+struct FactorStats {
+    double pairmat_ms = 0.0, gemm_ms = 0.0, near_ms = 0.0;
+    int64_t near_pairs = 0;
+    double gemm_flops = 0.0;
+};
+
 }  // namespace mb

@@ -44,6 +44,12 @@ TreeHost tree_topology(int64_t n, int leaf_size);
 mb_status tree_build(const double *x, int64_t n, int leaf_size, hipStream_t s, DeviceTree **out);
 void tree_free(DeviceTree *t);
 
+// Factorized (matrix-product) evaluation over the points of a tree, in
+// the tree's depth-first order; phi receives input order.
+//   fmt: 0 = FP16, 1 = BF16; planes: 1..3.
+mb_status factorized_eval(const DeviceTree *tr, int n, int fmt, int planes, double r_near,
+                          double *phi, hipStream_t s, FactorStats *stats);
+
 // Mean diagonal of the leaf bounding boxes (waits on s).
 double tree_mean_leaf_diagonal(const DeviceTree *t, hipStream_t s);
 

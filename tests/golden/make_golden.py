@@ -54,9 +54,30 @@ def c3_samples(threads: int = 0):
         json.dump(out, f, indent=1)
 
 
+def c4_samples(threads: int = 0):
+    """Direct Phi at 64 sampled particles of the 16384-point jittered lattice."""
+    x = workloads.jittered_lattice(16384, seed=4)
+    idx = workloads.sample_indices(16384, 64, seed=1004)
+    t = time.time()
+    phi = direct.phi(x, idx, threads=threads)
+    out = {
+        "workload": "jittered lattice, N = 16384 (26^3 sites nearest the centre), spacing 1.0, "
+                    "jitter 0.25, seed 4",
+        "n": 16384,
+        "sample_seed": 1004,
+        "indices": idx.tolist(),
+        "phi": [repr(float(v)) for v in phi],
+        "oracle_seconds": time.time() - t,
+    }
+    with open(os.path.join(HERE, "c4_direct_samples.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "c2"
     if which == "c2":
         c2_samples()
     elif which == "c3":
         c3_samples(int(sys.argv[2]) if len(sys.argv) > 2 else 0)
+    elif which == "c4":
+        c4_samples(int(sys.argv[2]) if len(sys.argv) > 2 else 0)

@@ -100,3 +100,28 @@ def test_lattice_generator():
     assert d.min() >= 0.5
     assert np.all(np.abs(x - np.rint(x)) <= 0.25)
     assert workloads.jittered_lattice(1000, 3).shape == (1000, 3)
+
+
+def test_factorized_identity_matches_direct():
+    # the law-of-cosines product form is an identity: same sum, FP64
+    from oracle import factorized
+
+    for n, seed in ((7, 1), (40, 2)):
+        x = workloads.rng(seed).normal(size=(n, 3)) * 2.0
+        np.testing.assert_allclose(factorized.phi(x), direct.phi(x), rtol=1e-11)
+    x = workloads.jittered_lattice(216, seed=3)
+    ref = direct.phi(x)
+    for r_near in (0.0, 1.5, 2.5):
+        np.testing.assert_allclose(factorized.phi(x, r_near), ref, rtol=1e-12)
+        np.testing.assert_allclose(factorized.phi_far(x, r_near),
+                                   direct.phi_split(x, r_near, far=True), rtol=1e-10,
+                                   atol=1e-14 * np.abs(ref).max())
+
+
+def test_factorized_coefficients_equilateral():
+    # equilateral triangle: the six sums reproduce 11/8 d^-9 for each vertex
+    from oracle import factorized
+
+    s = np.sqrt(3.0) / 2.0
+    x = np.array([[0, 0, 0], [2.0, 0, 0], [1.0, 2 * s, 0]])
+    np.testing.assert_allclose(factorized.phi(x), [11 / 8 / 2 ** 9] * 3, rtol=1e-14)
