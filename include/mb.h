@@ -240,6 +240,86 @@ mb_status mb_eval_factorized(const double *x, int64_t n, int32_t fmt, int32_t pl
  */
 double mb_normal_quantile(double alpha_half);
 
+/*
+ * Serving (an extension: the paper evaluates one point set at a time).  A
+ * server owns a host thread that batches exhaustive Phi evaluations of many
+ * point sets of different N as they arrive:
+ *   - admission: requests are admitted in arrival order while a slot is free
+ *     and their device footprint fits the HBM budget; the footprint of a
+ *     request of N points is 24 N + 8 N bytes plus its (i, j) pair-term
+ *     table (about 3 N^2 binary32 or binary64 numbers, each rounded up to
+ *     256 B; binary64 is reserved until validation shows it is not needed);
+ *   - continuous batching: the work units (block triples) of all admitted
+ *     requests are drained together by a kernel whose resident workgroups
+ *     pop (request, unit) items, in slices of a bounded number of units;
+ *     requests with the fewest units left go first;
+ *   - completion: when a request's last unit has run, its Phi is copied back
+ *     and the request counts as done (latency = done - submit, host clock).
+ * Results are those of mb_eval_direct with the same precision, up to the
+ * order of binary64 additions.
+ */
+typedef struct {
+    int64_t submitted, completed, failed; /* failed: finished with an error     */
+    int64_t fp64_fallbacks;                /* binary32 requests run in binary64  */
+    int64_t slices, units;                 /* drain launches, work units run     */
+    int64_t mixed_slices;                  /* slices holding units of >= 2 requests */
+    int64_t peak_reserved;                 /* bytes of the budget held at most   */
+    int32_t peak_active, pad;              /* admitted requests at most          */
+    double triples;                        /* sum of C(N, 3) of completed ones   */
+    double busy_ms;                        /* compute-stream time of the slices  */
+} mb_server_stats;
+
+/*
+ * Create a server.  hbm_budget_bytes > 0 bounds the device memory held by
+ * admitted requests; 1 <= max_slots <= 4096 bounds how many are admitted at
+ * once.  stream: the compute stream (NULL: the server creates its own); a
+ * second, server-owned stream stages requests.  Uses the current device.
+ * *srv receives an opaque handle.
+ */
+mb_status mb_server_create(int64_t hbm_budget_bytes, int32_t max_slots, void *stream, void **srv);
+
+/*
+ * Queue one request.  host_x: host pointer to N x 3 float64, row-major; it is
+ * copied before the call returns.  prec: MB_FP64 or MB_FP32C (which falls
+ * back to binary64 as mb_eval_direct does).  *req_id receives the id.
+ * Errors at submission: MB_ERR_INVALID (bad argument or non-finite
+ * coordinate), MB_ERR_OOM (the footprint exceeds the whole budget), and
+ * MB_ERR_DEVICE once the server has stopped after a device error.  N < 3
+ * completes at once with Phi = 0.  Coincident points are found on the device:
+ * the request then finishes with MB_ERR_DEGENERATE.
+ */
+mb_status mb_server_submit(void *srv, const double *host_x, int64_t n, int32_t prec,
+                           int64_t *req_id);
+
+/*
+ * Non-blocking status of a request.  *done = 1 once it has finished.  If it
+ * finished with an error, that status is returned (with *done = 1).  If
+ * host_phi is non-NULL and the request succeeded, its N results are copied
+ * there (caller's input order) and the server drops its copy: a second fetch
+ * is MB_ERR_INVALID.  Unknown id: MB_ERR_INVALID.
+ */
+mb_status mb_server_poll(void *srv, int64_t req_id, double *host_phi, int32_t *done);
+
+/*
+ * Block until request req_id (or, for req_id < 0, every request submitted so
+ * far) has finished, or timeout_ms milliseconds have passed (timeout_ms < 0:
+ * no limit).  *done (nullable) tells which.
+ */
+mb_status mb_server_wait(void *srv, int64_t req_id, int32_t timeout_ms, int32_t *done);
+
+/* Seconds from submission to completion of a finished request. */
+mb_status mb_server_latency(void *srv, int64_t req_id, double *seconds);
+
+/* Counters of the server so far (host struct). */
+mb_status mb_server_stats_get(void *srv, mb_server_stats *out);
+
+/* Units per slice (>= 1, at most 65536); the default is 8 per resident
+ * workgroup of the drain kernel.  Takes effect at the next slice. */
+mb_status mb_server_set_slice_units(void *srv, int64_t units);
+
+/* Finish every request already submitted, then free the server. */
+mb_status mb_server_destroy(void *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -66,6 +66,17 @@ class FactorStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in
+                ("submitted", "completed", "failed", "fp64_fallbacks", "slices", "units",
+                 "mixed_slices", "peak_reserved")] + \
+               [("peak_active", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("triples", ctypes.c_double), ("busy_ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
+
+
 # name -> (restype, argtypes)
 SIGNATURES = {
     "mb_last_error": (ctypes.c_char_p, []),
@@ -85,6 +96,14 @@ SIGNATURES = {
     "mb_normal_quantile": (_c_dbl, [_c_dbl]),
     "mb_eval_factorized": (_c_i32, [_c_vp, _c_i64, _c_i32, _c_i32, _c_dbl, _c_vp,
                                     ctypes.POINTER(FactorStats), _c_vp]),
+    "mb_server_create": (_c_i32, [_c_i64, _c_i32, _c_vp, ctypes.POINTER(_c_vp)]),
+    "mb_server_submit": (_c_i32, [_c_vp, _c_vp, _c_i64, _c_i32, ctypes.POINTER(_c_i64)]),
+    "mb_server_poll": (_c_i32, [_c_vp, _c_i64, _c_vp, ctypes.POINTER(_c_i32)]),
+    "mb_server_wait": (_c_i32, [_c_vp, _c_i64, _c_i32, ctypes.POINTER(_c_i32)]),
+    "mb_server_latency": (_c_i32, [_c_vp, _c_i64, ctypes.POINTER(_c_dbl)]),
+    "mb_server_stats_get": (_c_i32, [_c_vp, ctypes.POINTER(ServerStats)]),
+    "mb_server_set_slice_units": (_c_i32, [_c_vp, _c_i64]),
+    "mb_server_destroy": (_c_i32, [_c_vp]),
 }
 HALF = {"fp16": 0, "bf16": 1}
 
@@ -239,3 +258,78 @@ def eval_factorized(x, fmt: str = "fp16", planes: int = 2, r_near: float = 1.5):
     check(lib().mb_eval_factorized(_c_vp(x.data_ptr()), n, HALF[fmt], int(planes), float(r_near),
                                    _c_vp(phi.data_ptr()), ctypes.byref(st), stream_of(x)))
     return phi, st.as_dict()
+
+
+class Server:
+    """A serving loop (mb_server_*): host arrays in, host arrays out.
+
+    ``submit`` copies the points and returns a request id at once; ``poll``
+    and ``wait`` report completion; ``result`` fetches Phi (numpy, input
+    order) once.  The server finishes all submitted work when closed.
+    """
+
+    def __init__(self, hbm_budget_bytes: int = 32 << 30, max_slots: int = 256, stream=None):
+        import torch
+
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self._srv = _c_vp()
+        self._stream = s  # keep the stream alive while the server uses it
+        check(lib().mb_server_create(int(hbm_budget_bytes), int(max_slots), _c_vp(s.cuda_stream),
+                                     ctypes.byref(self._srv)))
+        self._n = {}
+
+    def submit(self, x, prec: str = "fp32c") -> int:
+        import numpy as np
+
+        a = np.ascontiguousarray(x, dtype=np.float64)
+        if a.ndim != 2 or a.shape[1] != 3:
+            raise TypeError("x must have shape (N, 3)")
+        rid = _c_i64()
+        check(lib().mb_server_submit(self._srv, _c_vp(a.ctypes.data), a.shape[0], PREC[prec],
+                                     ctypes.byref(rid)))
+        self._n[rid.value] = a.shape[0]
+        return rid.value
+
+    def poll(self, rid: int) -> bool:
+        done = _c_i32()
+        check(lib().mb_server_poll(self._srv, int(rid), None, ctypes.byref(done)))
+        return bool(done.value)
+
+    def wait(self, rid: int = -1, timeout_ms: int = -1) -> bool:
+        done = _c_i32()
+        check(lib().mb_server_wait(self._srv, int(rid), int(timeout_ms), ctypes.byref(done)))
+        return bool(done.value)
+
+    def result(self, rid: int):
+        import numpy as np
+
+        out = np.empty(self._n[rid], dtype=np.float64)
+        done = _c_i32()
+        check(lib().mb_server_poll(self._srv, int(rid), _c_vp(out.ctypes.data), ctypes.byref(done)))
+        if not done.value:
+            raise RuntimeError(f"request {rid} has not finished")
+        return out
+
+    def latency(self, rid: int) -> float:
+        v = _c_dbl()
+        check(lib().mb_server_latency(self._srv, int(rid), ctypes.byref(v)))
+        return v.value
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        check(lib().mb_server_stats_get(self._srv, ctypes.byref(st)))
+        return st.as_dict()
+
+    def set_slice_units(self, units: int) -> None:
+        check(lib().mb_server_set_slice_units(self._srv, int(units)))
+
+    def close(self) -> None:
+        if self._srv:
+            check(lib().mb_server_destroy(self._srv))
+            self._srv = _c_vp()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -59,10 +59,6 @@ void device_pool_setup() {
     done[dev] = true;
 }
 
-// Ratio limit between the bounding-box diagonal and the closest pair above
-// which the binary32 path hands over to binary64.
-constexpr double kFp32MaxRatio = 65536.0;
-
 mb_status check_points(const double *x, int64_t n, hipStream_t s, ValidateOut *v) {
     mb_status st = validate_points(x, n, s, v);
     if (st != MB_OK) return st;
@@ -76,7 +72,6 @@ mb_status check_points(const double *x, int64_t n, hipStream_t s, ValidateOut *v
     return MB_OK;
 }
 
-// Power of two that maps the closest-pair distance into [1, 2).
 double unit_scale(double min_d2) {
     int e;
     std::frexp(std::sqrt(min_d2), &e);  // r = f * 2^e, f in [0.5, 1)

@@ -1,0 +1,308 @@
+// Tile code of the exhaustive per-particle Axilrod-Teller sum (the naive
+// algorithm of Section 6, definition in Section 1), shared by the one-shot
+// kernel and the serving kernel.
+//
+// Work decomposition.  A work unit is a block triple (I, J, K): an I block of
+// 8 * IPW points, a J block of 64 and a K tile of 256.  Units are enumerated
+// so that together they hold every unordered triple i < j < k exactly once;
+// inside a unit the global-index masks i < j < k < n drop the rest.  One
+// 512-thread workgroup (8 wave64s) runs one unit:
+//
+//   * lane l owns the four points k = K0 + l + 64 m, m = 0..3;
+//   * wave w owns IPW points i and keeps the (i, k) pair terms of its
+//     4 * IPW combinations in registers for the whole unit;
+//   * the (i, j) pair terms do not depend on the lane.  A table kernel writes
+//     them to HBM per (I, J) block pair, and the triple kernel reads them
+//     with scalar loads into SGPRs, issued one j ahead of their use;
+//   * the (j, k) terms (one per lane) are staged in LDS per chunk of 16 j
+//     and also read one j ahead into registers.
+//
+// Inner step for one triple, with (a, qa, wa) the (i, j) terms, (g, qg, wg)
+// the (i, k) terms and (b, qb, ob = 3/8 / b) the (j, k) terms:
+//
+//   phi = qb * psi,   psi = qa qg + ob (wa wg) (a + g - b)(b^2 - (a - g)^2)
+//
+// which is 11 VALU operations per triple including the sums
+// Phi_k += qb * sum_i psi (register), Phi_i += qb * psi (register array) and
+// Phi_j += sum over lanes, waves of sum_k qb * sum_i psi (one LDS atomic per
+// lane and j into a per-(j, lane) slot, reduced once per chunk).  Unit sums
+// go to Phi with FP64 atomics.
+#pragma once
+
+#include "at_device.hpp"
+
+namespace mb {
+namespace {
+
+constexpr int kNW = 8;              // waves per workgroup
+constexpr int kThreads = kNW * 64;
+constexpr int kB = 64;              // points per J block
+constexpr int kKT = 256;            // points per K tile (four per lane)
+constexpr int kKR = kKT / 64;       // k points per lane
+constexpr int kJC = 16;             // j points per LDS chunk
+
+// Tile shape per arithmetic type: i points per wave.
+template <typename T> struct DirectShape;
+template <> struct DirectShape<double> { static constexpr int IPW = 4; };
+template <> struct DirectShape<float> { static constexpr int IPW = 8; };
+
+template <typename T>
+struct DirectLds {
+    static constexpr int IB = kNW * DirectShape<T>::IPW;
+    static constexpr int XS = IB + kB + kKT;
+    double xs[3][XS];                              // coordinates of the I, J blocks and K tile
+    T cb[kJC][kKT], cq[kJC][kKT], co[kJC][kKT];    // (j, k) terms of the chunk
+    double pj[kJC][64];                            // Phi_j partials per (j, lane), all waves
+    double pjacc[kB];                              // Phi_j of the unit
+    double kacc[kKT];                              // Phi_k of the unit
+};
+
+// Units of J block b: a in [0, na_b) times t in [b / 4, nt).
+__host__ __device__ __forceinline__ int units_a(int b, int ib, int na) {
+    return min(na, (64 * b + 62) / ib + 1);
+}
+
+__device__ __forceinline__ void decode_unit(int64_t u, const int64_t *__restrict__ off, int nb,
+                                            int nt, int &a, int &b, int &t) {
+    int lo = 0, hi = nb;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= u) lo = mid; else hi = mid;
+    }
+    b = lo;
+    const int64_t rem = u - off[b];
+    const int tc = nt - (b >> 2);
+    a = (int)(rem / tc);
+    t = (b >> 2) + (int)(rem % tc);
+}
+
+// s_waitcnt lgkmcnt(0) (vmcnt and expcnt left at their maxima), with
+// scheduling barriers so no memory operation moves across it.
+__device__ __forceinline__ void lgkm_wait_all() {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+__device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+// (i, j) pair-term table for J blocks b0 <= b < b0 + gridDim.y: block (a, b)
+// holds (a_ij, q_ij, w_ij) at [jl][il][3] for i = IB a + il, j = 64 b + jl,
+// masked unless i < j < n.
+template <typename T>
+__global__ __launch_bounds__(256) void pair_table_kernel(const double *__restrict__ x, int n,
+                                                         int na, int b0, double scale,
+                                                         T *__restrict__ tab) {
+    constexpr int IB = DirectLds<T>::IB;
+    const int a = blockIdx.x, b = b0 + blockIdx.y;
+    if (a >= units_a(b, IB, na)) return;
+    __shared__ double xa[3][IB], xb[3][kB];
+    const int tid = threadIdx.x;
+    if (tid < IB) {
+        const int i = a * IB + tid;
+        for (int c = 0; c < 3; ++c) xa[c][tid] = i < n ? x[3 * (int64_t)i + c] * scale : 0.0;
+    } else if (tid < IB + kB) {
+        const int j = b * kB + tid - IB;
+        for (int c = 0; c < 3; ++c) xb[c][tid - IB] = j < n ? x[3 * (int64_t)j + c] * scale : 0.0;
+    }
+    __syncthreads();
+    T *out = tab + ((int64_t)blockIdx.y * na + a) * (IB * kB * 3);
+    for (int e = tid; e < IB * kB; e += 256) {
+        const int jl = e / IB, il = e % IB;
+        const int i = a * IB + il, j = b * kB + jl;
+        double pa, pq, pw, pia;
+        pair_terms(xb[0][jl] - xa[0][il], xb[1][jl] - xa[1][il], xb[2][jl] - xa[2][il],
+                   (i < j) && (j < n), pa, pq, pw, pia);
+        out[3 * e + 0] = (T)pa;
+        out[3 * e + 1] = (T)pq;
+        out[3 * e + 2] = (T)pw;
+    }
+}
+
+// One work unit (I block a, J block b, K tile t) of the triple sum; ublk is
+// the (i, j) table block of (a, b), read with scalar loads (a pointer into
+// the constant address space where the caller cannot otherwise show the
+// table is unchanged during the kernel).  Every thread of the workgroup
+// calls it.
+template <typename T, typename TabPtr = const T *>
+__device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__restrict__ x, int n,
+                                            int a, int b, int t, TabPtr ublk,
+                                            double scale, double out_scale,
+                                            double *__restrict__ phi) {
+    constexpr int IPW = DirectShape<T>::IPW;
+    constexpr int IB = DirectLds<T>::IB;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    constexpr int XI = 0, XJ = IB, XK = IB + kB;
+    const int I0 = a * IB, J0 = b * kB, K0 = t * kKT;
+    const TabPtr up = ublk + wave * (IPW * 3);
+
+    __syncthreads();  // the previous unit is done with the LDS
+    for (int p = tid; p < DirectLds<T>::XS; p += kThreads) {
+        const int g = p < XJ ? I0 + p : (p < XK ? J0 + p - XJ : K0 + p - XK);
+        const bool ok = g < n;
+        s.xs[0][p] = ok ? x[3 * (int64_t)g + 0] * scale : 0.0;
+        s.xs[1][p] = ok ? x[3 * (int64_t)g + 1] * scale : 0.0;
+        s.xs[2][p] = ok ? x[3 * (int64_t)g + 2] * scale : 0.0;
+    }
+    if (tid < kKT) s.kacc[tid] = 0.0;
+    __syncthreads();
+
+    // (i, k) pair terms of this wave, in registers for the whole unit
+    T ag[IPW][kKR], aq[IPW][kKR], aw[IPW][kKR];
+    T acc_i[IPW];
+    double acc_i64[IPW];
+#pragma unroll
+    for (int ii = 0; ii < IPW; ++ii) {
+        const int il = wave * IPW + ii;
+        const int i = I0 + il;
+#pragma unroll
+        for (int kk = 0; kk < kKR; ++kk) {
+            const int kl = lane + 64 * kk;
+            const int k = K0 + kl;
+            double pa, pq, pw, pia;
+            pair_terms(s.xs[0][XK + kl] - s.xs[0][XI + il], s.xs[1][XK + kl] - s.xs[1][XI + il],
+                       s.xs[2][XK + kl] - s.xs[2][XI + il], (i < k) && (k < n), pa, pq, pw,
+                       pia);
+            ag[ii][kk] = (T)pa;
+            aq[ii][kk] = (T)pq;
+            aw[ii][kk] = (T)pw;
+        }
+        acc_i[ii] = T(0);
+        acc_i64[ii] = 0.0;
+    }
+    double acck[kKR];
+#pragma unroll
+    for (int kk = 0; kk < kKR; ++kk) acck[kk] = 0.0;
+
+    for (int jc = 0; jc < kB / kJC; ++jc) {
+        __syncthreads();  // previous chunk's readers are done
+        for (int e = tid; e < kJC * kKT; e += kThreads) {
+            const int jj = e / kKT, kl = e % kKT;
+            const int jl = jc * kJC + jj;
+            const int j = J0 + jl, k = K0 + kl;
+            double pa, pq, pw, pia;
+            pair_terms(s.xs[0][XK + kl] - s.xs[0][XJ + jl], s.xs[1][XK + kl] - s.xs[1][XJ + jl],
+                       s.xs[2][XK + kl] - s.xs[2][XJ + jl], (j < k) && (k < n), pa, pq, pw,
+                       pia);
+            s.cb[jj][kl] = (T)pa;
+            s.cq[jj][kl] = (T)pq;
+            s.co[jj][kl] = (T)(0.375 * pia);
+        }
+        for (int e = tid; e < kJC * 64; e += kThreads) s.pj[e / 64][e % 64] = 0.0;
+        __syncthreads();
+
+        const TabPtr uc = up + (jc * kJC) * (IB * 3);
+        // Operands of one j step: the (i, j) terms of the wave's IPW points
+        // (uniform, SGPRs) and the (j, k) terms of the lane's four k.
+        struct Ops {
+            T u[IPW * 3];
+            T cb[kKR], cq[kKR], co[kKR];
+        };
+        auto load = [&](int jj, Ops &o) {
+            const TabPtr p = uc + jj * (IB * 3);
+#pragma unroll
+            for (int e = 0; e < IPW * 3; ++e) o.u[e] = p[e];
+#pragma unroll
+            for (int kk = 0; kk < kKR; ++kk) {
+                o.cb[kk] = s.cb[jj][lane + 64 * kk];
+                o.cq[kk] = s.cq[jj][lane + 64 * kk];
+                o.co[kk] = s.co[jj][lane + 64 * kk];
+            }
+        };
+        // One j step: 4 * IPW triples per lane.
+        auto step = [&](int jj, const Ops &o) {
+            T bb[kKR], sk[kKR];
+#pragma unroll
+            for (int kk = 0; kk < kKR; ++kk) bb[kk] = o.cb[kk] * o.cb[kk];
+#pragma unroll
+            for (int ii = 0; ii < IPW; ++ii) {
+                const T al = o.u[3 * ii], qa = o.u[3 * ii + 1], wa = o.u[3 * ii + 2];
+#pragma unroll
+                for (int kk = 0; kk < kKR; ++kk) {
+                    const T g = ag[ii][kk];
+                    const T d = al - g;
+                    const T tt = (al + g) - o.cb[kk];
+                    const T m = fma(-d, d, bb[kk]);
+                    const T X = qa * aq[ii][kk];
+                    const T W = wa * aw[ii][kk];
+                    const T P = tt * m;
+                    const T Y = W * P;
+                    const T psi = fma(o.co[kk], Y, X);
+                    sk[kk] = ii ? sk[kk] + psi : psi;
+                    acc_i[ii] = fma(o.cq[kk], psi, acc_i[ii]);
+                }
+            }
+            double pjv = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < kKR; ++kk) {
+                const double v = (double)(o.cq[kk] * sk[kk]);
+                acck[kk] += v;
+                pjv += v;
+            }
+            atomicAdd(&s.pj[jj][lane], pjv);
+        };
+        // Two operand sets: everything step jj + 1 reads is loaded while
+        // step jj computes, so one wait per step covers loads issued a
+        // whole step earlier (LDS and scalar loads share one counter).
+        // The explicit wait + scheduling barriers keep the compiler from
+        // hoisting the next set's loads above the wait for this set.
+        Ops A, B;
+        load(0, A);
+#pragma unroll 1
+        for (int jj = 0; jj < kJC; jj += 2) {
+            lgkm_wait_all();
+            load(jj + 1, B);
+            sched_fence();
+            step(jj, A);
+            lgkm_wait_all();
+            if (jj + 2 < kJC) load(jj + 2, A);
+            sched_fence();
+            step(jj + 1, B);
+        }
+        // fold the short binary32 partial sums of Phi_i into binary64
+        if constexpr (sizeof(T) == 4) {
+#pragma unroll
+            for (int ii = 0; ii < IPW; ++ii) {
+                acc_i64[ii] += (double)acc_i[ii];
+                acc_i[ii] = T(0);
+            }
+        }
+        __syncthreads();
+        {
+            // Phi_j of the chunk: 16 rows of 64 slots, 32 threads per row
+            const int row = tid >> 5, c = tid & 31;
+            double v = s.pj[row][c] + s.pj[row][c + 32];
+#pragma unroll
+            for (int m = 16; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+            if (c == 0) s.pjacc[jc * kJC + row] = v;
+        }
+    }
+
+#pragma unroll
+    for (int ii = 0; ii < IPW; ++ii) {
+        const double v = wave_sum(sizeof(T) == 4 ? acc_i64[ii] : (double)acc_i[ii]);
+        const int i = I0 + wave * IPW + ii;
+        if (lane == 0 && i < n) atomicAdd(&phi[i], v * out_scale);
+    }
+#pragma unroll
+    for (int kk = 0; kk < kKR; ++kk) atomicAdd(&s.kacc[lane + 64 * kk], acck[kk]);
+    __syncthreads();
+    if (tid < kKT) {
+        const int k = K0 + tid;
+        if (k < n) atomicAdd(&phi[k], s.kacc[tid] * out_scale);
+    } else if (tid < kKT + kB) {
+        const int j = J0 + tid - kKT;
+        if (j < n) atomicAdd(&phi[j], s.pjacc[tid - kKT] * out_scale);
+    }
+}
+
+}  // namespace
+}  // namespace mb

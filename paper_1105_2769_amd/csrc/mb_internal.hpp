@@ -14,6 +14,7 @@ namespace mb {
 // Record a message for mb_last_error() and return the status.
 mb_status fail(mb_status st, const std::string &msg);
 void clear_error();
+const char *last_error_cstr();
 
 // Map a HIP error to MB_ERR_DEVICE (or MB_ERR_OOM for allocation failures).
 mb_status hip_fail(hipError_t e, const char *what);
@@ -81,6 +82,17 @@ size_t table_budget_bytes();
 // differences (the result is rescaled exactly).
 mb_status direct_launch(const double *x, int64_t n, int prec, double scale, double *phi,
                         hipStream_t s);
+
+// Ratio limit between the bounding-box diagonal and the closest pair above
+// which the binary32 path hands over to binary64.
+constexpr double kFp32MaxRatio = 65536.0;
+
+// validate_points plus the status it implies: MB_ERR_INVALID for a
+// non-finite coordinate, MB_ERR_DEGENERATE for coincident points (n >= 3).
+mb_status check_points(const double *x, int64_t n, hipStream_t s, ValidateOut *v);
+
+// Power of two that maps the closest-pair distance sqrt(min_d2) into [1, 2).
+double unit_scale(double min_d2);
 
 struct FactorStats {
     double pairmat_ms = 0.0, gemm_ms = 0.0, near_ms = 0.0;

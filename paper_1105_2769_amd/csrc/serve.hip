@@ -1,0 +1,671 @@
+// Serving loop (an extension: the paper has no serving mode).  Requests of
+// different N arrive on the host; a scheduler thread admits them under an
+// HBM budget and a slot limit, stages and validates their points on the
+// device while earlier requests compute, and drains the work units of all
+// admitted requests together: each slice is one launch of a drain kernel
+// whose resident workgroups pop (request, block triple) items from a list
+// and run the exhaustive-sum tile code on them.  A request finishes when
+// every one of its units has run; its Phi is then copied back to the host.
+//
+// One slice is in flight at a time.  While it runs the thread copies back
+// the results of the previous slice and stages newly admitted requests on a
+// second stream, so the compute stream sees back-to-back slices.  Every
+// slice ends with a count check: each slot's items run == items issued.
+#include "direct_tile.hpp"
+#include "mb_internal.hpp"
+#include "serve_sched.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+namespace mb {
+namespace {
+
+struct ServeDesc {
+    const double *x;
+    double *phi;
+    const void *tab;
+    int32_t n, na;
+    double scale, out_scale;
+};
+
+struct ServeItem {
+    int32_t slot, a, b, t;
+};
+
+// Load a small struct at a wave-uniform address and mark every word uniform,
+// so that pointers and sizes read from it live in SGPRs (the loop's atomics
+// keep the compiler from proving the loads scalar by itself).
+template <typename S>
+__device__ __forceinline__ S uniform_load(const S *p) {
+    static_assert(sizeof(S) % 4 == 0, "word-sized struct");
+    constexpr int W = sizeof(S) / 4;
+    const unsigned *w = reinterpret_cast<const unsigned *>(p);
+    unsigned v[W];
+#pragma unroll
+    for (int e = 0; e < W; ++e) v[e] = __builtin_amdgcn_readfirstlane(w[e]);
+    S out;
+    __builtin_memcpy(&out, v, sizeof(S));
+    return out;
+}
+
+constexpr int kHeaderWords = 16;  // next-item counters (two used), padded to 64 B
+
+// Resident workgroups pop items until the list is exhausted.  Every
+// workgroup reaches the exit: the counter only grows.
+//
+// The item fetch and the count update are done by all 64 lanes of wave 0
+// under a wave-uniform branch (lane 0 adds 1, the others 0), never under a
+// per-lane condition: a lane-divergent region at the loop boundary can be
+// merged across the back edge by the compiler so that the other lanes of
+// the wave re-enter the barrier without the fetching lane, and the item
+// index is then never refreshed.
+template <typename T>
+__global__ __launch_bounds__(kThreads, 1) void serve_kernel(const ServeDesc *__restrict__ desc,
+                                                            const ServeItem *__restrict__ items,
+                                                            int n_items, unsigned *__restrict__ next,
+                                                            unsigned *__restrict__ counts) {
+    constexpr int IB = DirectLds<T>::IB;
+    __shared__ DirectLds<T> s;
+    __shared__ int cur;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (;;) {
+        if (wave == 0) {
+            const unsigned got = atomicAdd(next, lane == 0 ? 1u : 0u);
+            cur = (int)__builtin_amdgcn_readfirstlane(got);  // lane 0's old value
+        }
+        __syncthreads();
+        // read before the unit's first barrier, so wave 0 cannot overwrite it
+        // first; uniform, so the item and its descriptor sit in SGPRs
+        const int idx = __builtin_amdgcn_readfirstlane(cur);
+        if (idx >= n_items) break;
+        const ServeItem it = uniform_load(items + idx);
+        const ServeDesc d = uniform_load(desc + it.slot);
+        // the tables are written before the launch and only read by it
+        using CT = __attribute__((address_space(4))) const T;
+        CT *blk = (CT *)static_cast<const T *>(d.tab) + ((int64_t)it.b * d.na + it.a) * (IB * kB * 3);
+        direct_unit<T, CT *>(s, d.x, d.n, it.a, it.b, it.t, blk, d.scale, d.out_scale, d.phi);
+        if (wave == 0) atomicAdd(&counts[it.slot], lane == 0 ? 1u : 0u);
+    }
+}
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
+
+// Unit enumeration of the exhaustive sum for one request and tile type.
+struct UnitMap {
+    int ib = 0, na = 0, nb = 0, nt = 0;
+    std::vector<int64_t> off;  // units of J blocks < b
+    void build(int64_t n, int ib_) {
+        ib = ib_;
+        na = (int)((n + ib - 1) / ib);
+        nb = (int)((n + kB - 1) / kB);
+        nt = (int)((n + kKT - 1) / kKT);
+        off.assign(nb + 1, 0);
+        for (int b = 0; b < nb; ++b) off[b + 1] = off[b] + (int64_t)units_a(b, ib, na) * (nt - (b >> 2));
+    }
+    int64_t units() const { return off.empty() ? 0 : off.back(); }
+    void decode(int64_t u, int &a, int &b, int &t) const {
+        b = (int)(std::upper_bound(off.begin(), off.end(), u) - off.begin()) - 1;
+        const int64_t rem = u - off[b];
+        const int tc = nt - (b >> 2);
+        a = (int)(rem / tc);
+        t = (b >> 2) + (int)(rem % tc);
+    }
+};
+
+int64_t table_bytes(int64_t n, bool f64) {
+    const int64_t ib = f64 ? DirectLds<double>::IB : DirectLds<float>::IB;
+    const int64_t na = (n + ib - 1) / ib, nb = (n + kB - 1) / kB;
+    return na * nb * ib * kB * 3 * (f64 ? 8 : 4);
+}
+
+// Device bytes a request holds while admitted: points, Phi and the (i, j)
+// table, for binary64 tiles when binary64 may be needed.
+int64_t footprint(int64_t n, bool f64) {
+    return align256(24 * n) + align256(8 * n) + align256(table_bytes(n, f64));
+}
+
+struct Request {
+    int64_t id = 0, n = 0;
+    int prec_req = MB_FP32C, prec = MB_FP32C;
+    std::vector<double> x, phi;
+    mb_status status = MB_OK;
+    std::string msg;
+    double t_submit = 0.0, t_done = 0.0;
+    bool done = false, fetched = false;
+    // device side, owned by the scheduler thread
+    void *chunk = nullptr;
+    double *dx = nullptr, *dphi = nullptr;
+    void *dtab = nullptr;
+    double scale = 1.0, out_scale = 1.0;
+    UnitMap um;
+};
+
+class Server {
+public:
+    Server(int64_t budget, int max_slots, hipStream_t user)
+        : sched_(budget, max_slots, 1), max_slots_(max_slots), user_stream_(user) {}
+
+    mb_status init() {
+        MB_HIP(hipGetDevice(&dev_));
+        device_pool_setup();
+        int cus = 0;
+        MB_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_));
+        int occ_f = 0, occ_d = 0;
+        MB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_f, serve_kernel<float>, kThreads, 0));
+        MB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_d, serve_kernel<double>, kThreads, 0));
+        grid_f_ = std::max(1, occ_f) * cus;
+        grid_d_ = std::max(1, occ_d) * cus;
+        sched_.set_slice_units(std::min<int64_t>(8 * (int64_t)grid_f_, kMaxSliceUnits));
+        if (user_stream_) {
+            cs_ = user_stream_;
+        } else {
+            MB_HIP(hipStreamCreateWithFlags(&own_cs_, hipStreamNonBlocking));
+            cs_ = own_cs_;
+        }
+        MB_HIP(hipStreamCreateWithFlags(&as_, hipStreamNonBlocking));
+        MB_HIP(hipEventCreateWithFlags(&ev_end_, hipEventDefault));
+        MB_HIP(hipEventCreateWithFlags(&ev_start_, hipEventDefault));
+        MB_HIP(hipEventCreateWithFlags(&ev_adm_, hipEventDisableTiming));
+        MB_HIP(hipMalloc(&d_desc_, sizeof(ServeDesc) * max_slots_));
+        MB_HIP(hipHostMalloc(&h_desc_, sizeof(ServeDesc) * max_slots_, hipHostMallocDefault));
+        std::memset(h_desc_, 0, sizeof(ServeDesc) * max_slots_);
+        ring_bytes_ = sizeof(unsigned) * (kHeaderWords + align_slots()) +
+                      sizeof(ServeItem) * (size_t)kMaxSliceUnits;
+        MB_HIP(hipMalloc(&d_ring_, ring_bytes_));
+        MB_HIP(hipHostMalloc(&h_ring_, ring_bytes_, hipHostMallocDefault));
+        MB_HIP(hipHostMalloc(&h_counts_, sizeof(unsigned) * max_slots_, hipHostMallocDefault));
+        thread_ = std::thread([this] { loop(); });
+        return MB_OK;
+    }
+
+    ~Server() {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            stop_ = true;
+        }
+        cv_work_.notify_all();
+        if (thread_.joinable()) thread_.join();
+        if (d_desc_) (void)hipFree(d_desc_);
+        if (d_ring_) (void)hipFree(d_ring_);
+        if (h_desc_) (void)hipHostFree(h_desc_);
+        if (h_ring_) (void)hipHostFree(h_ring_);
+        if (h_counts_) (void)hipHostFree(h_counts_);
+        if (ev_end_) (void)hipEventDestroy(ev_end_);
+        if (ev_start_) (void)hipEventDestroy(ev_start_);
+        if (ev_adm_) (void)hipEventDestroy(ev_adm_);
+        if (as_) (void)hipStreamDestroy(as_);
+        if (own_cs_) (void)hipStreamDestroy(own_cs_);
+    }
+
+    mb_status submit(const double *hx, int64_t n, int prec, int64_t *id) {
+        if (!id || n < 0 || (n > 0 && !hx)) return fail(MB_ERR_INVALID, "bad request");
+        if (prec != MB_FP64 && prec != MB_FP32C) return fail(MB_ERR_INVALID, "unknown precision");
+        if (n > (int64_t)65535 * kB) return fail(MB_ERR_UNSUPPORTED, "n must be <= 65535 * 64");
+        for (int64_t e = 0; e < 3 * n; ++e)
+            if (!std::isfinite(hx[e])) return fail(MB_ERR_INVALID, "non-finite coordinate");
+        const int64_t need = footprint(n, true);
+        if (n >= 3 && !sched_.can_ever_fit(need))
+            return fail(MB_ERR_OOM, "request needs " + std::to_string(need) +
+                                        " device bytes, more than the server's budget");
+        auto r = std::make_unique<Request>();
+        r->n = n;
+        r->prec_req = r->prec = prec;
+        r->t_submit = now_s();
+        std::lock_guard<std::mutex> g(mu_);
+        if (broken_) return fail(MB_ERR_DEVICE, "server stopped after a device error: " + broken_msg_);
+        r->id = next_id_++;
+        *id = r->id;
+        stats_.submitted += 1;
+        if (n < 3) {  // the empty sum
+            r->phi.assign(n, 0.0);
+            r->t_done = r->t_submit;
+            r->done = true;
+            stats_.completed += 1;
+            reqs_[r->id] = std::move(r);
+            cv_done_.notify_all();
+            return MB_OK;
+        }
+        r->x.assign(hx, hx + 3 * n);
+        inbox_.push_back(r->id);
+        reqs_[r->id] = std::move(r);
+        cv_work_.notify_all();
+        return MB_OK;
+    }
+
+    mb_status poll(int64_t id, double *out, int32_t *done) {
+        std::lock_guard<std::mutex> g(mu_);
+        auto it = reqs_.find(id);
+        if (it == reqs_.end()) return fail(MB_ERR_INVALID, "unknown request id");
+        Request &r = *it->second;
+        if (done) *done = r.done ? 1 : 0;
+        if (!r.done) return MB_OK;
+        if (r.status != MB_OK) return fail(r.status, r.msg);
+        if (out) {
+            if (r.fetched) return fail(MB_ERR_INVALID, "result already fetched");
+            std::copy(r.phi.begin(), r.phi.end(), out);
+            r.fetched = true;
+            std::vector<double>().swap(r.phi);
+        }
+        return MB_OK;
+    }
+
+    mb_status wait(int64_t id, int32_t timeout_ms, int32_t *done) {
+        std::unique_lock<std::mutex> g(mu_);
+        auto ready = [&] {
+            if (id < 0) return stats_.completed + stats_.failed == stats_.submitted;
+            auto it = reqs_.find(id);
+            return it == reqs_.end() || it->second->done;
+        };
+        if (id >= 0 && reqs_.find(id) == reqs_.end()) return fail(MB_ERR_INVALID, "unknown request id");
+        bool ok;
+        if (timeout_ms < 0) {
+            cv_done_.wait(g, ready);
+            ok = true;
+        } else {
+            ok = cv_done_.wait_for(g, std::chrono::milliseconds(timeout_ms), ready);
+        }
+        if (done) *done = ok ? 1 : 0;
+        return MB_OK;
+    }
+
+    mb_status latency(int64_t id, double *sec) {
+        std::lock_guard<std::mutex> g(mu_);
+        auto it = reqs_.find(id);
+        if (it == reqs_.end()) return fail(MB_ERR_INVALID, "unknown request id");
+        if (!it->second->done) return fail(MB_ERR_INVALID, "request not finished");
+        *sec = it->second->t_done - it->second->t_submit;
+        return MB_OK;
+    }
+
+    void get_stats(mb_server_stats *out) {
+        std::lock_guard<std::mutex> g(mu_);
+        *out = stats_;
+    }
+
+    mb_status set_slice_units(int64_t u) {
+        if (u < 1) return fail(MB_ERR_INVALID, "slice_units < 1");
+        std::lock_guard<std::mutex> g(mu_);
+        slice_request_ = std::min<int64_t>(u, kMaxSliceUnits);
+        return MB_OK;
+    }
+
+private:
+    static constexpr int64_t kMaxSliceUnits = 1 << 16;
+
+    size_t align_slots() const { return (size_t)((max_slots_ + 15) / 16) * 16; }
+    unsigned *d_header() const { return static_cast<unsigned *>(d_ring_); }
+    unsigned *d_counts() const { return d_header() + kHeaderWords; }
+    ServeItem *d_items() const {
+        return reinterpret_cast<ServeItem *>(d_counts() + align_slots());
+    }
+    unsigned *h_header() const { return static_cast<unsigned *>(h_ring_); }
+    ServeItem *h_items() const {
+        return reinterpret_cast<ServeItem *>(h_header() + kHeaderWords + align_slots());
+    }
+
+    Request &req(int64_t id) {
+        std::lock_guard<std::mutex> g(mu_);
+        return *reqs_.at(id);
+    }
+
+    // Mark a request finished (result or error) and wake waiters.
+    void complete(Request &r, mb_status st, const std::string &msg) {
+        std::lock_guard<std::mutex> g(mu_);
+        r.status = st;
+        r.msg = msg;
+        r.t_done = now_s();
+        r.done = true;
+        if (st == MB_OK) {
+            stats_.completed += 1;
+            const double n = (double)r.n;
+            stats_.triples += n * (n - 1) * (n - 2) / 6.0;
+        } else {
+            stats_.failed += 1;
+        }
+        std::vector<double>().swap(r.x);
+        cv_done_.notify_all();
+    }
+
+    // Copy points in, validate, choose the tile type and build the (i, j)
+    // table.  Runs on the staging stream while the compute stream is busy.
+    mb_status stage(Request &r, int64_t &units, int64_t &keep, std::string &why) {
+        const int64_t n = r.n;
+        if (hipMallocAsync(&r.chunk, footprint(n, true), as_) != hipSuccess) {
+            r.chunk = nullptr;
+            return fail(MB_ERR_OOM, "device allocation of " + std::to_string(footprint(n, true)) +
+                                        " bytes failed");
+        }
+        char *base = static_cast<char *>(r.chunk);
+        r.dx = reinterpret_cast<double *>(base);
+        r.dphi = reinterpret_cast<double *>(base + align256(24 * n));
+        r.dtab = base + align256(24 * n) + align256(8 * n);
+        MB_HIP(hipMemcpyAsync(r.dx, r.x.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, as_));
+        mb_status st = zero_doubles(r.dphi, n, as_);
+        if (st != MB_OK) return st;
+        ValidateOut v{};
+        st = check_points(r.dx, n, as_, &v);
+        if (st == MB_ERR_DEGENERATE || st == MB_ERR_INVALID) {
+            why = st == MB_ERR_DEGENERATE ? "two points coincide" : "non-finite coordinate";
+            units = 0;
+            return st;
+        }
+        if (st != MB_OK) return st;
+        double md2;
+        std::memcpy(&md2, &v.min_d2_bits, sizeof md2);
+        r.prec = r.prec_req;
+        r.scale = 1.0;
+        if (r.prec == MB_FP32C) {
+            double diag2 = 0.0;
+            for (int c = 0; c < 3; ++c) diag2 += (v.hi[c] - v.lo[c]) * (v.hi[c] - v.lo[c]);
+            if (diag2 > kFp32MaxRatio * kFp32MaxRatio * md2) {
+                r.prec = MB_FP64;
+                std::lock_guard<std::mutex> g(mu_);
+                stats_.fp64_fallbacks += 1;
+            } else {
+                r.scale = unit_scale(md2);
+            }
+        }
+        const double s2 = r.scale * r.scale;
+        r.out_scale = s2 * s2 * s2 * s2 * r.scale;
+        const bool f64 = r.prec == MB_FP64;
+        r.um.build(n, f64 ? DirectLds<double>::IB : DirectLds<float>::IB);
+        dim3 g((unsigned)r.um.na, (unsigned)r.um.nb);
+        if (f64)
+            pair_table_kernel<double><<<g, 256, 0, as_>>>(r.dx, (int)n, r.um.na, 0, r.scale,
+                                                          static_cast<double *>(r.dtab));
+        else
+            pair_table_kernel<float><<<g, 256, 0, as_>>>(r.dx, (int)n, r.um.na, 0, r.scale,
+                                                         static_cast<float *>(r.dtab));
+        MB_HIP(hipGetLastError());
+        units = r.um.units();
+        keep = footprint(n, f64);
+        return MB_OK;
+    }
+
+    mb_status launch(const serve::Slice &sl, int &nf, int &nd) {
+        // items of binary32 requests first, then binary64
+        std::vector<ServeItem> fi, di;
+        for (const auto &rg : sl.ranges) {
+            Request &r = req(rg.id);
+            auto &dst = r.prec == MB_FP64 ? di : fi;
+            for (int64_t u = rg.u0; u < rg.u1; ++u) {
+                ServeItem it;
+                it.slot = rg.slot;
+                r.um.decode(u, it.a, it.b, it.t);
+                dst.push_back(it);
+            }
+            ServeDesc &d = h_desc_[rg.slot];
+            d.x = r.dx;
+            d.phi = r.dphi;
+            d.tab = r.dtab;
+            d.n = (int32_t)r.n;
+            d.na = r.um.na;
+            d.scale = r.scale;
+            d.out_scale = r.out_scale;
+        }
+        nf = (int)fi.size();
+        nd = (int)di.size();
+        std::memset(h_ring_, 0, sizeof(unsigned) * (kHeaderWords + align_slots()));
+        std::copy(fi.begin(), fi.end(), h_items());
+        std::copy(di.begin(), di.end(), h_items() + nf);
+        const size_t bytes = sizeof(unsigned) * (kHeaderWords + align_slots()) +
+                             sizeof(ServeItem) * (size_t)(nf + nd);
+        MB_HIP(hipEventRecord(ev_start_, cs_));
+        MB_HIP(hipMemcpyAsync(d_desc_, h_desc_, sizeof(ServeDesc) * max_slots_,
+                              hipMemcpyHostToDevice, cs_));
+        MB_HIP(hipMemcpyAsync(d_ring_, h_ring_, bytes, hipMemcpyHostToDevice, cs_));
+        if (nf)
+            serve_kernel<float><<<(unsigned)std::min(nf, grid_f_), kThreads, 0, cs_>>>(
+                d_desc_, d_items(), nf, d_header() + 0, d_counts());
+        if (nd)
+            serve_kernel<double><<<(unsigned)std::min(nd, grid_d_), kThreads, 0, cs_>>>(
+                d_desc_, d_items() + nf, nd, d_header() + 1, d_counts());
+        MB_HIP(hipGetLastError());
+        MB_HIP(hipMemcpyAsync(h_counts_, d_counts(), sizeof(unsigned) * max_slots_,
+                              hipMemcpyDeviceToHost, cs_));
+        MB_HIP(hipEventRecord(ev_end_, cs_));
+        return MB_OK;
+    }
+
+    mb_status finish_slice(const serve::Slice &sl, std::vector<int64_t> &finished) {
+        MB_HIP(hipEventSynchronize(ev_end_));
+        float ms = 0.f;
+        MB_HIP(hipEventElapsedTime(&ms, ev_start_, ev_end_));
+        std::vector<int64_t> expect(max_slots_, 0);
+        for (const auto &rg : sl.ranges) expect[rg.slot] += rg.u1 - rg.u0;
+        for (int s = 0; s < max_slots_; ++s)
+            if ((int64_t)h_counts_[s] != expect[s])
+                return fail(MB_ERR_DEVICE, "drain kernel ran " + std::to_string(h_counts_[s]) +
+                                               " items of slot " + std::to_string(s) + ", issued " +
+                                               std::to_string(expect[s]));
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            stats_.slices += 1;
+            stats_.units += sl.units;
+            if (sl.ranges.size() > 1) stats_.mixed_slices += 1;
+            stats_.busy_ms += ms;
+        }
+        finished = sched_.slice_done(sl);
+        return MB_OK;
+    }
+
+    mb_status finalize(int64_t id) {
+        Request &r = req(id);
+        r.phi.resize(r.n);
+        MB_HIP(hipMemcpyAsync(r.phi.data(), r.dphi, sizeof(double) * r.n, hipMemcpyDeviceToHost, as_));
+        MB_HIP(hipStreamSynchronize(as_));
+        MB_HIP(hipFreeAsync(r.chunk, as_));
+        r.chunk = nullptr;
+        sched_.release(id);
+        complete(r, MB_OK, "");
+        return MB_OK;
+    }
+
+    void drop(int64_t id, mb_status st, const std::string &msg) {
+        Request &r = req(id);
+        if (r.chunk) (void)hipFreeAsync(r.chunk, as_);
+        r.chunk = nullptr;
+        sched_.release(id);
+        complete(r, st, msg);
+    }
+
+    mb_status step(std::vector<int64_t> &to_finalize, bool &idle) {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            if (slice_request_ > 0) {
+                sched_.set_slice_units(slice_request_);
+                slice_request_ = 0;
+            }
+            for (int64_t id : inbox_) sched_.enqueue(id, footprint(reqs_.at(id)->n, true));
+            inbox_.clear();
+        }
+        // 1. the next slice goes to the compute stream
+        serve::Slice sl = sched_.next_slice();
+        int nf = 0, nd = 0;
+        mb_status st;
+        if (!sl.empty() && (st = launch(sl, nf, nd)) != MB_OK) return st;
+        // 2. results of the previous slice come back meanwhile
+        for (int64_t id : to_finalize)
+            if ((st = finalize(id)) != MB_OK) return st;
+        to_finalize.clear();
+        // 3. admit and stage new requests on the staging stream
+        bool staged = false;
+        for (int64_t id : sched_.admit()) {
+            Request &r = req(id);
+            int64_t units = 0, keep = 0;
+            std::string why;
+            st = stage(r, units, keep, why);
+            if (st == MB_ERR_OOM) {  // this request only; the server goes on
+                (void)hipGetLastError();
+                why = last_error_cstr();
+            }
+            if (st == MB_ERR_DEGENERATE || st == MB_ERR_INVALID || st == MB_ERR_OOM) {
+                drop(id, st, why);
+                continue;
+            }
+            if (st != MB_OK) return st;
+            sched_.start(id, units, keep);
+            staged = true;
+        }
+        if (staged) {
+            MB_HIP(hipEventRecord(ev_adm_, as_));
+            MB_HIP(hipStreamWaitEvent(cs_, ev_adm_, 0));
+        }
+        // 4. wait for the slice
+        if (!sl.empty()) {
+            if ((st = finish_slice(sl, to_finalize)) != MB_OK) return st;
+            idle = false;
+        } else {
+            idle = to_finalize.empty() && !sched_.has_runnable();
+        }
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            stats_.peak_reserved = sched_.peak_reserved();
+            stats_.peak_active = sched_.peak_active();
+        }
+        return MB_OK;
+    }
+
+    void loop() {
+        if (hipSetDevice(dev_) != hipSuccess) {
+            break_all("hipSetDevice failed in the serving thread");
+            return;
+        }
+        std::vector<int64_t> to_finalize;
+        for (;;) {
+            bool idle = false;
+            mb_status st = step(to_finalize, idle);
+            if (st != MB_OK) {
+                break_all(last_error_cstr());
+                return;
+            }
+            if (idle) {
+                std::unique_lock<std::mutex> g(mu_);
+                if (inbox_.empty()) {
+                    if (stop_ && sched_.idle()) return;
+                    cv_work_.wait_for(g, std::chrono::milliseconds(2));
+                }
+            }
+        }
+    }
+
+    // A device error ends the server: every unfinished request fails.
+    void break_all(const std::string &msg) {
+        std::lock_guard<std::mutex> g(mu_);
+        broken_ = true;
+        broken_msg_ = msg;
+        for (auto &kv : reqs_) {
+            Request &r = *kv.second;
+            if (r.done) continue;
+            r.status = MB_ERR_DEVICE;
+            r.msg = msg;
+            r.t_done = now_s();
+            r.done = true;
+            stats_.failed += 1;
+        }
+        cv_done_.notify_all();
+    }
+
+    serve::Scheduler sched_;  // scheduler thread only
+    int max_slots_;
+    hipStream_t user_stream_ = nullptr, own_cs_ = nullptr, cs_ = nullptr, as_ = nullptr;
+    hipEvent_t ev_start_ = nullptr, ev_end_ = nullptr, ev_adm_ = nullptr;
+    int dev_ = 0, grid_f_ = 1, grid_d_ = 1;
+    ServeDesc *d_desc_ = nullptr, *h_desc_ = nullptr;
+    void *d_ring_ = nullptr, *h_ring_ = nullptr;
+    unsigned *h_counts_ = nullptr;
+    size_t ring_bytes_ = 0;
+    std::thread thread_;
+
+    std::mutex mu_;  // guards everything below
+    std::condition_variable cv_work_, cv_done_;
+    std::map<int64_t, std::unique_ptr<Request>> reqs_;
+    std::vector<int64_t> inbox_;
+    int64_t next_id_ = 0;
+    int64_t slice_request_ = 0;
+    bool stop_ = false, broken_ = false;
+    std::string broken_msg_;
+    mb_server_stats stats_{};
+};
+
+}  // namespace
+}  // namespace mb
+
+using namespace mb;
+
+extern "C" {
+
+mb_status mb_server_create(int64_t hbm_budget_bytes, int32_t max_slots, void *stream, void **srv) {
+    clear_error();
+    if (!srv) return fail(MB_ERR_INVALID, "null output");
+    *srv = nullptr;
+    if (hbm_budget_bytes <= 0 || max_slots < 1 || max_slots > 4096)
+        return fail(MB_ERR_INVALID, "budget must be > 0 and 1 <= max_slots <= 4096");
+    auto s = std::make_unique<Server>(hbm_budget_bytes, max_slots, (hipStream_t)stream);
+    mb_status st = s->init();
+    if (st != MB_OK) return st;
+    *srv = s.release();
+    return MB_OK;
+}
+
+mb_status mb_server_submit(void *srv, const double *host_x, int64_t n, int32_t prec,
+                           int64_t *req_id) {
+    clear_error();
+    if (!srv) return fail(MB_ERR_INVALID, "null server");
+    return static_cast<Server *>(srv)->submit(host_x, n, prec, req_id);
+}
+
+mb_status mb_server_poll(void *srv, int64_t req_id, double *host_phi, int32_t *done) {
+    clear_error();
+    if (!srv || !done) return fail(MB_ERR_INVALID, "null argument");
+    return static_cast<Server *>(srv)->poll(req_id, host_phi, done);
+}
+
+mb_status mb_server_wait(void *srv, int64_t req_id, int32_t timeout_ms, int32_t *done) {
+    clear_error();
+    if (!srv) return fail(MB_ERR_INVALID, "null server");
+    return static_cast<Server *>(srv)->wait(req_id, timeout_ms, done);
+}
+
+mb_status mb_server_latency(void *srv, int64_t req_id, double *seconds) {
+    clear_error();
+    if (!srv || !seconds) return fail(MB_ERR_INVALID, "null argument");
+    return static_cast<Server *>(srv)->latency(req_id, seconds);
+}
+
+mb_status mb_server_stats_get(void *srv, mb_server_stats *out) {
+    clear_error();
+    if (!srv || !out) return fail(MB_ERR_INVALID, "null argument");
+    static_cast<Server *>(srv)->get_stats(out);
+    return MB_OK;
+}
+
+mb_status mb_server_set_slice_units(void *srv, int64_t units) {
+    clear_error();
+    if (!srv) return fail(MB_ERR_INVALID, "null server");
+    return static_cast<Server *>(srv)->set_slice_units(units);
+}
+
+mb_status mb_server_destroy(void *srv) {
+    clear_error();
+    delete static_cast<Server *>(srv);
+    return MB_OK;
+}
+
+}  // extern "C"

@@ -71,3 +71,21 @@ def test_multitree_bad_params_no_device():
     out = ctypes.c_void_p()
     assert lib.mb_build_kdtree(None, 10, 0, None, ctypes.byref(out)) == 1
     assert lib.mb_build_kdtree(None, 10, 64, None, ctypes.byref(out)) in (1, 5)
+
+
+def test_server_bad_arguments_no_device():
+    import ctypes
+
+    lib = _lib.lib()
+    h = ctypes.c_void_p()
+    assert lib.mb_server_create(0, 4, None, ctypes.byref(h)) == 1
+    assert lib.mb_server_create(1 << 20, 0, None, ctypes.byref(h)) == 1
+    assert lib.mb_server_create(1 << 20, 4, None, None) == 1
+    assert not h.value
+    rid = ctypes.c_int64()
+    assert lib.mb_server_submit(None, None, 3, 1, ctypes.byref(rid)) == 1
+    done = ctypes.c_int32()
+    assert lib.mb_server_poll(None, 0, None, ctypes.byref(done)) == 1
+    assert lib.mb_server_wait(None, 0, 0, None) == 1
+    assert lib.mb_server_set_slice_units(None, 4) == 1
+    assert lib.mb_server_destroy(None) == 0
