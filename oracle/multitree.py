@@ -234,6 +234,72 @@ def sample_partners(case: str, slot: int, x_local: np.ndarray, n: tuple[int, int
     return t // nb, t % nb, others[0], others[1]
 
 
+def det_bounds(d12: float, d13: float, d23: float) -> tuple[float, float]:
+    """(phi_lo, span) over all triangles whose sides are at least d12, d13, d23.
+
+    With R^u = 1 / (d12 d13 d23)^3 the distance factor is at most R^u and the
+    angular factor 1 + 3 cos cos cos lies in [-2, 11/8] (collinear,
+    equilateral), so phi lies in [-2 R^u, 11/8 R^u]: phi_lo = -2 R^u and
+    span = 27/8 R^u (the bound of Section 4 for a sign-indefinite potential).
+    """
+    ru = 1.0 / (d12 * d13 * d23) ** 3
+    return -2.0 * ru, 3.375 * ru
+
+
+def mc_try(tree: KdTree, xs: np.ndarray, p: tuple[int, int, int], roles, cnt, phil,
+           eps: float, tau: float, t_root: int, z: float, seed: int, m_limit: int, m_min: int):
+    """Monte Carlo test of one node triple (Algorithm 3, Algorithm 4 per point).
+
+    For every point x of every distinct node P_i (``roles`` = (node, T_i,
+    slot), ``phil`` = Phi^l(P_i)), samples are drawn one at a time and the
+    running mean and unbiased variance updated; x stops at the first m with
+    m >= m_min and
+        z sigma_mu <= (eps (Phi^l(P_i) + T_i (mu - z sigma_mu)) + tau) / T_root,
+    and passes if that holds, else fails at m = m_limit.  Points are scanned
+    in order and the scan ends at the first failure.  Returns (all passed,
+    [(first rank, T_i, mu per point, sigma_mu per point)], samples used).
+    """
+    case = canonical_case(*p)
+    commits = []
+    used_total = 0
+    for (node, t, slot), plo in zip(roles, phil):
+        base = int(tree.begin[node])
+        npts = cnt[slot]
+        xl = np.arange(npts, dtype=np.int64)[:, None]
+        xr = base + xl
+        r = np.stack([mc_draw(seed, p, int(base + q), np.arange(m_limit, dtype=np.uint64))
+                      for q in range(npts)])
+        u, v, su, sv = sample_partners(case, slot, xl, cnt, r)
+        f = at_phi_np(xs[xr], xs[tree.begin[p[su]] + u], xs[tree.begin[p[sv]] + v])
+        mean = np.zeros(npts)
+        m2 = np.zeros(npts)
+        stop_m = np.full(npts, -1, dtype=np.int64)
+        mu_s = np.zeros(npts)
+        sg_s = np.zeros(npts)
+        passed = np.zeros(npts, dtype=bool)
+        for k in range(m_limit):
+            m = k + 1
+            d = f[:, k] - mean
+            mean = mean + d / m
+            m2 = m2 + d * (f[:, k] - mean)
+            if m < 2:
+                continue
+            sig_mu = np.sqrt(m2 / (m - 1) / m)
+            cond = z * sig_mu <= (eps * (plo + t * (mean - z * sig_mu)) + tau) / t_root
+            fresh = (stop_m < 0) & ((cond & (m >= m_min)) | (m == m_limit))
+            stop_m[fresh] = m
+            mu_s[fresh] = mean[fresh]
+            sg_s[fresh] = sig_mu[fresh]
+            passed[fresh] = cond[fresh] & (m >= m_min)
+        fail = np.nonzero(~passed)[0]
+        used = stop_m if fail.size == 0 else stop_m[: fail[0] + 1]
+        used_total += int(used.sum())
+        if fail.size:
+            return False, [], used_total
+        commits.append((base, t, mu_s, sg_s))
+    return True, commits, used_total
+
+
 @dataclass
 class MTResult:
     phi: np.ndarray                # estimate, input order
@@ -283,9 +349,7 @@ def multitree(x, eps: float, alpha: float, leaf_size: int, tau: float = 0.0, see
             d13 = box_min_dist(tree.lo[p1], tree.hi[p1], tree.lo[p3], tree.hi[p3])
             d23 = box_min_dist(tree.lo[p2], tree.hi[p2], tree.lo[p3], tree.hi[p3])
             if d12 > 0 and d13 > 0 and d23 > 0:
-                ru = 1.0 / (d12 * d13 * d23) ** 3
-                phi_lo = -2.0 * ru
-                span = 3.375 * ru
+                phi_lo, span = det_bounds(d12, d13, d23)
                 allow = min(phi_l(node) + t * phi_lo for node, t, _ in roles)
                 if span <= (eps * allow + tau) / t_root:
                     phic = float(at_phi_np(tree.centroid[p1], tree.centroid[p2], tree.centroid[p3]))
@@ -298,47 +362,9 @@ def multitree(x, eps: float, alpha: float, leaf_size: int, tau: float = 0.0, see
 
         # (b) Monte Carlo prune (Algorithm 3 over the distinct nodes, Algorithm 4 per point)
         if alpha > 0 and zeta * m_limit <= min(t for _, t, _ in roles):
-            ok = True
-            commits = []
-            for node, t, slot in roles:
-                base = int(tree.begin[node])
-                npts = cnt[slot]
-                plo = phi_l(node)
-                xl = np.arange(npts, dtype=np.int64)[:, None]
-                xr = base + xl
-                r = np.stack([mc_draw(seed, p, int(base + q), np.arange(m_limit, dtype=np.uint64))
-                              for q in range(npts)])
-                u, v, su, sv = sample_partners(case, slot, xl, cnt, r)
-                f = at_phi_np(xs[xr], xs[tree.begin[p[su]] + u], xs[tree.begin[p[sv]] + v])
-                # Welford running mean and unbiased variance, sample by sample
-                mean = np.zeros(npts)
-                m2 = np.zeros(npts)
-                stop_m = np.full(npts, -1, dtype=np.int64)
-                mu_s = np.zeros(npts)
-                sg_s = np.zeros(npts)
-                passed = np.zeros(npts, dtype=bool)
-                for k in range(m_limit):
-                    m = k + 1
-                    d = f[:, k] - mean
-                    mean = mean + d / m
-                    m2 = m2 + d * (f[:, k] - mean)
-                    if m < 2:
-                        continue
-                    sig_mu = np.sqrt(m2 / (m - 1) / m)
-                    cond = z * sig_mu <= (eps * (plo + t * (mean - z * sig_mu)) + tau) / t_root
-                    fresh = (stop_m < 0) & ((cond & (m >= m_min)) | (m == m_limit))
-                    stop_m[fresh] = m
-                    mu_s[fresh] = mean[fresh]
-                    sg_s[fresh] = sig_mu[fresh]
-                    passed[fresh] = cond[fresh] & (m >= m_min)
-                # Algorithm 3 scans points in order and stops at the first failure
-                fail = np.nonzero(~passed)[0]
-                used = stop_m if fail.size == 0 else stop_m[: fail[0] + 1]
-                st["mc_samples"] += int(used.sum())
-                if fail.size:
-                    ok = False
-                    break
-                commits.append((base, t, mu_s, sg_s))
+            ok, commits, used = mc_try(tree, xs, p, roles, cnt, [phi_l(node) for node, _, _ in roles],
+                                       eps, tau, t_root, z, seed, m_limit, m_min)
+            st["mc_samples"] += used
             if ok:
                 for base, t, mu_s, sg_s in commits:
                     sl = slice(base, base + mu_s.shape[0])
