@@ -19,6 +19,15 @@ Extra fields:
   cpu_baseline - the CPU oracle timed on the host's cores on a bounded
                  sample of the same workload (a few particles' full sums);
                  its values also give the accuracy check above.
+  latency      - the serving loop on a Poisson trace: 4096 requests at
+                 200 requests/s (trace seed 5), N log-uniform in [64, 8192],
+                 request r the jittered lattice of N points with seed
+                 10^6 + r, FP32C; p50/p99 of submit-to-result latency,
+                 completed triples per second over the trace, and the error
+                 against the binary64 GPU sum on sampled requests.
+  factorized   - the matrix-product form (FP16, two planes, r_near = 1.5)
+                 on the N = 16384 lattice (seed 4) against the binary64 GPU
+                 sum on all points.
 """
 from __future__ import annotations
 
@@ -51,6 +60,9 @@ def main() -> int:
                     help="particles for the CPU-oracle leg (0: two per host thread)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--prec", choices=["fp64", "fp32c", "both"], default="both")
+    ap.add_argument("--serve-requests", type=int, default=4096,
+                    help="requests of the serving trace (0: skip the serving leg)")
+    ap.add_argument("--no-factorized", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (the "
                          "reference kernel for scaling HBM byte counters), then exit")
@@ -135,6 +147,9 @@ def main() -> int:
               f"max rel err {rel}", flush=True)
         results[prec] = dict(step_s=step_s, kern_s=kern_s, rel=rel)
 
+    latency = serve_leg(args.serve_requests, dev) if args.serve_requests else None
+    factorized = None if args.no_factorized else factorized_leg(dev)
+
     ok = [p for p in precs if results[p]["rel"] is None or results[p]["rel"] <= 1e-6]
     best = min(ok, key=lambda p: results[p]["step_s"]) if ok else None
     if best is None:
@@ -162,6 +177,8 @@ def main() -> int:
                      "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[best], "traffic": None,
                      "kernel": "direct_kernel", "kernel_ms": r["kern_s"] * 1e3},
         "cpu_baseline": cpu,
+        "latency": latency,
+        "factorized": factorized,
         "accuracy": {p: results[p]["rel"] for p in precs},
         "paths": {p: {"triples_per_s": triples / results[p]["step_s"],
                       "kernel_ms": results[p]["kern_s"] * 1e3,
@@ -169,6 +186,118 @@ def main() -> int:
     }
     print(json.dumps(out), flush=True)
     return 0
+
+
+def serve_leg(n_req: int, dev) -> dict:
+    """Replay the Poisson trace through mb.Server; p50/p99 latency."""
+    import numpy as np
+    import torch
+
+    import paper_1105_2769_amd as mb
+    import workloads
+
+    t_arr, sizes = workloads.poisson_trace(n_req, seed=5, rate_hz=200.0, n_min=64, n_max=8192)
+    print(f"serving: generating {n_req} requests", flush=True)
+    pts = [workloads.jittered_lattice(int(nr), seed=1_000_000 + r) for r, nr in enumerate(sizes)]
+    srv = mb.Server(hbm_budget_bytes=64 << 30, max_slots=512)
+    # one short request first so that the server's first launches are not timed
+    warm = srv.submit(workloads.jittered_lattice(300, seed=7))
+    srv.wait(warm)
+    srv.result(warm)
+    st0 = srv.stats()
+    print(f"serving: replaying {n_req} requests at 200/s", flush=True)
+    ids = []
+    t0 = time.perf_counter()
+    next_report = 5.0
+    for ta, x in zip(t_arr, pts):
+        while True:
+            now = time.perf_counter() - t0
+            if now >= ta:
+                break
+            time.sleep(min(ta - now, 2e-3))
+        ids.append(srv.submit(x))
+        if ta > next_report:
+            print(f"serving: {len(ids)} submitted at {ta:.1f} s", flush=True)
+            next_report += 5.0
+    srv.wait(-1)
+    t_end = time.perf_counter() - t0
+    st = srv.stats()
+    lat = np.array([srv.latency(r) for r in ids])
+    # accuracy on sampled requests against the binary64 GPU sum
+    pick = workloads.sample_indices(n_req, min(32, n_req), seed=55)
+    worst = 0.0
+    results = {r: srv.result(ids[r]) for r in pick}
+    srv.close()
+    for r in pick:
+        x = torch.from_numpy(pts[r]).to(dev)
+        ref = mb.eval_direct(x, prec="fp64").cpu().numpy()
+        worst = max(worst, float(np.max(np.abs(results[r] - ref) / np.abs(ref))))
+    n_arr = sizes.astype(np.float64)
+    total = float(np.sum(n_arr * (n_arr - 1) * (n_arr - 2) / 6.0))
+    out = {
+        "workload": f"{n_req} requests, Poisson arrivals at 200/s (seed 5), N log-uniform "
+                    f"[64, 8192] (mean {sizes.mean():.0f}), jittered lattices, fp32c",
+        "p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "mean_ms": float(lat.mean() * 1e3),
+        "trace_s": t_end,
+        "triples_per_s": total / t_end,
+        "offered_triples_per_s": total / float(t_arr[-1]),
+        "gpu_busy_frac": (st["busy_ms"] - st0["busy_ms"]) / 1e3 / t_end,
+        "slices": st["slices"] - st0["slices"],
+        "mixed_slices": st["mixed_slices"] - st0["mixed_slices"],
+        "peak_active": st["peak_active"],
+        "fp64_fallbacks": st["fp64_fallbacks"],
+        "max_rel_err_vs_fp64_sampled": worst,
+        "sampled_requests": int(len(pick)),
+    }
+    print(f"serving: p50 {out['p50_ms']:.2f} ms p99 {out['p99_ms']:.2f} ms, "
+          f"{out['triples_per_s']:.3e} triples/s, max rel err {worst:.2e}", flush=True)
+    return out
+
+
+def factorized_leg(dev, n: int = 16384, steps: int = 3) -> dict:
+    """The product form on MFMA against the binary64 GPU sum."""
+    import numpy as np
+    import torch
+
+    import paper_1105_2769_amd as mb
+    import workloads
+
+    x = torch.from_numpy(workloads.jittered_lattice(n, seed=4)).to(dev)
+    print(f"factorized: N={n}", flush=True)
+    ref = mb.eval_direct(x, prec="fp64").cpu().numpy()
+    t_direct = {}
+    for prec in ("fp64", "fp32c"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mb.eval_direct(x, prec=prec)
+        torch.cuda.synchronize()
+        t_direct[prec] = time.perf_counter() - t0
+    mb.eval_factorized(x, fmt="fp16", planes=2, r_near=1.5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        phi, st = mb.eval_factorized(x, fmt="fp16", planes=2, r_near=1.5)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    got = phi.cpu().numpy()
+    rel = float(np.max(np.abs(got - ref) / np.abs(ref)))
+    out = {
+        "workload": f"all N={n} points, jittered lattice (seed 4); fp16 operands, 2 planes, "
+                    f"r_near 1.5",
+        "ms": dt * 1e3,
+        "triples_per_s": comb3(n) / dt,
+        "gemm_ms": st["gemm_ms"],
+        "gemm_tflops": st["gemm_flops"] / (st["gemm_ms"] * 1e-3) / 1e12 if st["gemm_ms"] else None,
+        "near_ms": st["near_ms"],
+        "max_rel_err_vs_fp64": rel,
+        "direct_fp32c_ms_same_n": t_direct["fp32c"] * 1e3,
+        "direct_fp64_ms_same_n": t_direct["fp64"] * 1e3,
+    }
+    print(f"factorized: {dt * 1e3:.1f} ms (direct fp32c {t_direct['fp32c'] * 1e3:.1f} ms), "
+          f"max rel err {rel:.2e}", flush=True)
+    return out
 
 
 if __name__ == "__main__":

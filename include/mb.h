@@ -69,6 +69,12 @@ int32_t mb_version(void);
  * (else MB_ERR_DEGENERATE).  N < 3 writes zeros (the empty sum) and returns
  * MB_OK.  n < 0, a NULL x or phi with n > 0, or an unknown prec return
  * MB_ERR_INVALID.  On any error phi is left unspecified.
+ *
+ * Device memory: a table of (i, j) pair terms, 12 bytes per pair in binary32
+ * and 24 in binary64 over the blocks the work units touch (about N^2 / 2
+ * pairs), built and consumed in stripes of at most MB_TABLE_BUDGET_MB
+ * mebibytes (environment variable, default 32768); MB_ERR_OOM if it cannot
+ * be allocated.
  */
 mb_status mb_eval_direct(const double *x, int64_t n, int32_t prec, double *phi, void *stream);
 

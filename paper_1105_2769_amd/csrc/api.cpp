@@ -37,7 +37,7 @@ mb_status hip_fail(hipError_t e, const char *what) {
 size_t table_budget_bytes() {
     static const size_t v = [] {
         const char *e = std::getenv("MB_TABLE_BUDGET_MB");
-        long mb = e ? std::atol(e) : 2048;
+        long mb = e ? std::atol(e) : 32768;
         if (mb < 1) mb = 1;
         return (size_t)mb << 20;
     }();

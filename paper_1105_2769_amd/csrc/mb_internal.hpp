@@ -74,7 +74,8 @@ mb_status validate_points(const double *x, int64_t n, hipStream_t s, ValidateOut
 mb_status zero_doubles(double *p, int64_t n, hipStream_t s);
 
 // Upper bound on the bytes of the (i, j) pair-term table the exhaustive sum
-// keeps per launch stripe (MB_TABLE_BUDGET_MB overrides, default 2048 MiB).
+// keeps per launch stripe (MB_TABLE_BUDGET_MB overrides, default 32 GiB: one
+// stripe up to N = 46000 in binary32, 32768 in binary64).
 size_t table_budget_bytes();
 
 // Direct (exhaustive) evaluation, no validation; phi is zeroed and
