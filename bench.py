@@ -6,9 +6,10 @@ headline metric is quoted on.  A step is one full evaluation through the C
 ABI (validation + exhaustive sum) with the points already in HBM.
 
 Metric: effective unordered triples per second, C(N, 3) per step, counted
-only for a precision whose relative error against the binary64 CPU oracle
-is <= 1e-6 on sampled particles.  Both precisions are timed; the faster one
-that meets the bar is reported.
+only for a precision whose relative error is <= 1e-6 both against the
+binary64 CPU oracle on sampled particles and, at every particle, against the
+binary64 GPU sum.  Both precisions are timed; the faster one that meets the
+bar is reported.
 
 Extra fields:
   roofline     - the exhaustive-sum kernel (19 flops per unordered triple,
@@ -130,27 +131,41 @@ def main() -> int:
             mb.eval_direct(x, prec=prec, out=phi)
         torch.cuda.synchronize()
         step_s = (time.perf_counter() - t0) / args.steps
-        # kernel timing with HIP events on the launch stream (enqueue-only calls)
+        got = phi.cpu().numpy()  # the result of a full step
+        # kernel timing with HIP events on the launch stream (enqueue-only
+        # calls: the binary32 tiles without the binary64 repairs)
+        scratch = torch.empty_like(phi)
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
         for _ in range(args.steps):
-            mb.eval_direct(x, prec=prec, out=phi, checked=False)
+            mb.eval_direct(x, prec=prec, out=scratch, checked=False)
         ev1.record(stream)
         ev1.synchronize()
         kern_s = ev0.elapsed_time(ev1) / 1e3 / args.steps
-        got = phi.cpu().numpy()
         rel = None
         if ref is not None:
             rel = float(np.max(np.abs(got[sample_idx] - ref) / np.abs(ref)))
         print(f"gpu {prec}: step {step_s * 1e3:.1f} ms, kernel {kern_s * 1e3:.1f} ms, "
               f"max rel err {rel}", flush=True)
-        results[prec] = dict(step_s=step_s, kern_s=kern_s, rel=rel)
+        results[prec] = dict(step_s=step_s, kern_s=kern_s, rel=rel, phi=got)
+    # every particle of a binary32 result against the binary64 GPU sum (which
+    # the oracle samples above pin to ~1e-14)
+    if "fp64" in results:
+        base = results["fp64"]["phi"]
+        for prec in precs:
+            r_all = np.abs(results[prec]["phi"] - base) / np.abs(base)
+            results[prec]["rel_all"] = float(r_all.max())
+            results[prec]["frac_above_1e6"] = float(np.mean(r_all > 1e-6))
 
     latency = serve_leg(args.serve_requests, dev) if args.serve_requests else None
     factorized = None if args.no_factorized else factorized_leg(dev)
 
-    ok = [p for p in precs if results[p]["rel"] is None or results[p]["rel"] <= 1e-6]
+    def meets(p):
+        errs = [v for v in (results[p]["rel"], results[p].get("rel_all")) if v is not None]
+        return all(v <= 1e-6 for v in errs)
+
+    ok = [p for p in precs if meets(p)]
     best = min(ok, key=lambda p: results[p]["step_s"]) if ok else None
     if best is None:
         print("no precision met the 1e-6 accuracy bar", file=sys.stderr)
@@ -179,10 +194,13 @@ def main() -> int:
         "cpu_baseline": cpu,
         "latency": latency,
         "factorized": factorized,
-        "accuracy": {p: results[p]["rel"] for p in precs},
+        "accuracy": {p: {"max_rel_err_oracle_sampled": results[p]["rel"],
+                         "max_rel_err_all_vs_fp64": results[p].get("rel_all"),
+                         "frac_particles_above_1e-6": results[p].get("frac_above_1e6")}
+                     for p in precs},
         "paths": {p: {"triples_per_s": triples / results[p]["step_s"],
                       "kernel_ms": results[p]["kern_s"] * 1e3,
-                      "max_rel_err": results[p]["rel"]} for p in precs},
+                      "meets_1e-6": p in ok} for p in precs},
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -61,8 +61,18 @@ int32_t mb_version(void);
  *
  *   prec : MB_FP64 or MB_FP32C.  MB_FP32C rescales the point set by a power
  *          of two so the closest pair is near unit distance (exact), and
- *          falls back to MB_FP64 when the ratio of the largest to the
- *          smallest pair distance exceeds 2^16.
+ *          falls back to MB_FP64 when the ratio of the bounding-box
+ *          diagonal to the closest-pair distance exceeds 2^16, or when the
+ *          closest pair is shorter than a quarter of the mean spacing (cube
+ *          root of bounding-box volume per point).  After the binary32 tiles
+ *          it (1) re-adds in binary64 every triple whose three sides are
+ *          shorter than 4 times the closest-pair distance (at most 64
+ *          forward neighbours per point), the triples where the reuse of
+ *          binary32 pair terms errs most, and (2) recomputes in binary64,
+ *          point by point, the Phi of every point where |Phi| < 1/4 of the
+ *          summed |phi| of those near triples (strong cancellation); if more
+ *          than max(256, N/64) points qualify the whole sum is redone in
+ *          binary64.  MB_FP32C therefore waits on `stream` at the end.
  *
  * Validation (device side, then a wait on `stream`): every coordinate must
  * be finite (else MB_ERR_INVALID); for N >= 3 no two points may coincide
@@ -84,7 +94,8 @@ mb_status mb_eval_direct(const double *x, int64_t n, int32_t prec, double *phi, 
  * validated the same points (mb_validate) and must not block, e.g. a timing
  * loop or a request pipeline.  Preconditions (unchecked on the device): all
  * coordinates finite, no two points coincide.  prec MB_FP32C here never
- * falls back and uses no rescaling.  Host-side argument errors are reported
+ * falls back, uses no rescaling and skips both binary64 repairs of
+ * mb_eval_direct (binary32 tiles only).  Host-side argument errors are reported
  * as for mb_eval_direct.
  */
 mb_status mb_eval_direct_unchecked(const double *x, int64_t n, int32_t prec, double *phi,
@@ -269,6 +280,7 @@ typedef struct {
     int64_t fp64_fallbacks;                /* binary32 requests run in binary64  */
     int64_t slices, units;                 /* drain launches, work units run     */
     int64_t mixed_slices;                  /* slices holding units of >= 2 requests */
+    int64_t points_fp64;                   /* points recomputed in binary64 after binary32 */
     int64_t peak_reserved;                 /* bytes of the budget held at most   */
     int32_t peak_active, pad;              /* admitted requests at most          */
     double triples;                        /* sum of C(N, 3) of completed ones   */

@@ -69,7 +69,7 @@ class FactorStats(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in
                 ("submitted", "completed", "failed", "fp64_fallbacks", "slices", "units",
-                 "mixed_slices", "peak_reserved")] + \
+                 "mixed_slices", "points_fp64", "peak_reserved")] + \
                [("peak_active", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("triples", ctypes.c_double), ("busy_ms", ctypes.c_double)]
 

@@ -2,6 +2,7 @@
 // validation step and dispatch to the kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -72,6 +73,19 @@ mb_status check_points(const double *x, int64_t n, hipStream_t s, ValidateOut *v
     return MB_OK;
 }
 
+bool fp32c_suitable(const ValidateOut &v, int64_t n) {
+    double md2;
+    std::memcpy(&md2, &v.min_d2_bits, sizeof md2);
+    double diag2 = 0.0;
+    for (int c = 0; c < 3; ++c) diag2 += (v.hi[c] - v.lo[c]) * (v.hi[c] - v.lo[c]);
+    if (diag2 > kFp32MaxRatio * kFp32MaxRatio * md2) return false;
+    const double floor_ext = 1e-3 * std::sqrt(diag2);
+    double vol = 1.0;
+    for (int c = 0; c < 3; ++c) vol *= std::max(v.hi[c] - v.lo[c], floor_ext);
+    const double spacing = std::cbrt(vol / (double)std::max<int64_t>(n, 1));
+    return 16.0 * md2 >= spacing * spacing;  // closest pair >= spacing / 4
+}
+
 double unit_scale(double min_d2) {
     int e;
     std::frexp(std::sqrt(min_d2), &e);  // r = f * 2^e, f in [0.5, 1)
@@ -118,19 +132,19 @@ mb_status mb_eval_direct(const double *x, int64_t n, int32_t prec, double *phi, 
     mb_status st = check_points(x, n, s, &v);
     if (st != MB_OK) return st;
     if (n < 3) return zero_doubles(phi, n, s);
-    double scale = 1.0;
+    double scale = 1.0, r_fix = 0.0;
     int p = prec;
     if (p == MB_FP32C) {
         double md2;
         std::memcpy(&md2, &v.min_d2_bits, sizeof md2);
-        double diag2 = 0.0;
-        for (int c = 0; c < 3; ++c) diag2 += (v.hi[c] - v.lo[c]) * (v.hi[c] - v.lo[c]);
-        if (diag2 > kFp32MaxRatio * kFp32MaxRatio * md2)
-            p = MB_FP64;  // dynamic range too wide for binary32 pair terms
-        else
+        if (!fp32c_suitable(v, n)) {
+            p = MB_FP64;  // too wide a range or too close a pair for binary32 tiles
+        } else {
             scale = unit_scale(md2);
+            r_fix = kNearFixFactor * std::sqrt(md2);
+        }
     }
-    return direct_launch(x, n, p, scale, phi, s);
+    return direct_launch(x, n, p, scale, phi, s, r_fix);
 }
 
 mb_status mb_eval_direct_unchecked(const double *x, int64_t n, int32_t prec, double *phi,

@@ -27,6 +27,187 @@ __global__ __launch_bounds__(kThreads, 1) void direct_kernel(
     }
 }
 
+// Near-field refinement of the binary32 tiles.  Each pair term is rounded to
+// binary32 once and reused by every triple through that pair, so its
+// rounding error does not average out over those triples; through the
+// difference of two squared sides in the law of cosines it is largest for
+// the compact triangles of near neighbours, which also carry the largest
+// phi.  For every triple whose three sides are shorter than r_c the
+// refinement adds phi in binary64 minus the binary32 value the tiles
+// computed for it (same pair terms, same operations: tile_psi), so those
+// triples end up in binary64.  The identity holds for any subset of
+// triples, each taken at most once, so the neighbour cap below only limits
+// how much is refined.
+constexpr int kNearMax = 64;  // forward neighbours kept per point
+
+// Forward neighbours v > u with |x_v - x_u| < r_c, in index order, at most
+// kNearMax per point.
+__global__ __launch_bounds__(256) void near_list_kernel(const double *__restrict__ x, int n,
+                                                        double rc2, int32_t *__restrict__ cnt,
+                                                        int32_t *__restrict__ nbr) {
+    __shared__ double xv[3][256];
+    const int u = blockIdx.x * 256 + threadIdx.x;
+    double x0 = 0.0, x1 = 0.0, x2 = 0.0;
+    if (u < n) {
+        x0 = x[3 * (int64_t)u];
+        x1 = x[3 * (int64_t)u + 1];
+        x2 = x[3 * (int64_t)u + 2];
+    }
+    int c = 0;
+    for (int v0 = blockIdx.x * 256; v0 < n; v0 += 256) {
+        __syncthreads();
+        const int v = v0 + threadIdx.x;
+        for (int d = 0; d < 3; ++d) xv[d][threadIdx.x] = v < n ? x[3 * (int64_t)v + d] : 0.0;
+        __syncthreads();
+        if (u < n) {
+            const int lim = min(256, n - v0);
+            for (int q = 0; q < lim; ++q) {
+                const int vv = v0 + q;
+                if (vv <= u || c >= kNearMax) continue;
+                const double dx = xv[0][q] - x0, dy = xv[1][q] - x1, dz = xv[2][q] - x2;
+                if (fma(dx, dx, fma(dy, dy, dz * dz)) < rc2) nbr[(int64_t)u * kNearMax + c++] = vv;
+            }
+        }
+    }
+    if (u < n) cnt[u] = c;
+}
+
+// One thread per point u: every triple u < v < w with v, w in u's list and
+// |x_w - x_v| < r_c (so each triple once, from its smallest index).
+__global__ __launch_bounds__(256) void near_fix_kernel(const double *__restrict__ x, int n,
+                                                       double scale, double out_scale, double rc2,
+                                                       const int32_t *__restrict__ cnt,
+                                                       const int32_t *__restrict__ nbr,
+                                                       double *__restrict__ phi,
+                                                       double *__restrict__ mag) {
+    const int u = blockIdx.x * 256 + threadIdx.x;
+    if (u >= n) return;
+    const int c = cnt[u];
+    const int32_t *list = nbr + (int64_t)u * kNearMax;
+    double xu[3];
+    for (int d = 0; d < 3; ++d) xu[d] = x[3 * (int64_t)u + d] * scale;
+    double acc_u = 0.0, mag_u = 0.0;
+    for (int p = 0; p < c; ++p) {
+        for (int q = p + 1; q < c; ++q) {
+            int v = list[p], w = list[q];
+            if (v > w) {
+                const int t = v;
+                v = w;
+                w = t;
+            }
+            double xv[3], xw[3], r2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                const double dv = x[3 * (int64_t)w + d] - x[3 * (int64_t)v + d];
+                r2 = fma(dv, dv, r2);
+                xv[d] = x[3 * (int64_t)v + d] * scale;
+                xw[d] = x[3 * (int64_t)w + d] * scale;
+            }
+            if (r2 >= rc2) continue;
+            // pair terms as the tiles form them: (i, j) = (u, v), (i, k) = (u, w),
+            // (j, k) = (v, w), each from the difference of scaled coordinates
+            double a1, q1, w1, i1, a2, q2, w2, i2, a3, q3, w3, i3;
+            pair_terms(xv[0] - xu[0], xv[1] - xu[1], xv[2] - xu[2], true, a1, q1, w1, i1);
+            pair_terms(xw[0] - xu[0], xw[1] - xu[1], xw[2] - xu[2], true, a2, q2, w2, i2);
+            pair_terms(xw[0] - xv[0], xw[1] - xv[1], xw[2] - xv[2], true, a3, q3, w3, i3);
+            const double f64 = phi_from_pairs<double>(a1, q1, w1, a2, q2, w2, a3, q3, w3);
+            const float cb = (float)a3;
+            const float psi = tile_psi<float>((float)a1, (float)q1, (float)w1, (float)a2, (float)q2,
+                                              (float)w2, cb, cb * cb, (float)(0.375 * i3));
+            const double f32 = (double)(float)q3 * (double)psi;
+            const double dlt = (f64 - f32) * out_scale;
+            const double m = fabs(f64) * out_scale;
+            acc_u += dlt;
+            mag_u += m;
+            atomicAdd(&phi[v], dlt);
+            atomicAdd(&phi[w], dlt);
+            atomicAdd(&mag[v], m);
+            atomicAdd(&mag[w], m);
+        }
+    }
+    atomicAdd(&phi[u], acc_u);
+    atomicAdd(&mag[u], mag_u);
+}
+
+// Points whose binary32 result may miss the relative bar: |Phi| small next
+// to the magnitude of their near-field terms (the binary32 error of a point
+// stays below about 1.2e-7 of that magnitude on the workloads measured).
+__global__ void flag_kernel(const double *__restrict__ phi, const double *__restrict__ mag, int n,
+                            double ratio, int32_t *__restrict__ list, int32_t *__restrict__ count,
+                            int cap) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    if (fabs(phi[p]) < ratio * mag[p]) {
+        const int slot = atomicAdd(count, 1);
+        if (slot < cap) list[slot] = p;
+    }
+}
+
+// Phi of listed points in binary64, one workgroup per (point, tile of 256 j):
+// thread j sums phi(p, j, k) over k > j (k != p), with the (p, k) pair terms
+// staged in LDS per tile of k.
+__global__ __launch_bounds__(256) void point_fp64_kernel(const double *__restrict__ x, int n,
+                                                         const int32_t *__restrict__ list,
+                                                         double *__restrict__ out) {
+    const int f = blockIdx.y;
+    const int p = list[f];
+    const int j0 = blockIdx.x * 256;
+    const int j = j0 + threadIdx.x;
+    __shared__ double xk[3][256], ak[256], qk[256], wk[256];
+    const double xp0 = x[3 * (int64_t)p], xp1 = x[3 * (int64_t)p + 1], xp2 = x[3 * (int64_t)p + 2];
+    const bool jok = j < n && j != p;
+    double xj0 = 0.0, xj1 = 0.0, xj2 = 0.0, a1 = 1.0, q1 = 0.0, w1 = 0.0, i1;
+    if (jok) {
+        xj0 = x[3 * (int64_t)j];
+        xj1 = x[3 * (int64_t)j + 1];
+        xj2 = x[3 * (int64_t)j + 2];
+        pair_terms(xj0 - xp0, xj1 - xp1, xj2 - xp2, true, a1, q1, w1, i1);
+    }
+    double acc = 0.0;
+    for (int k0 = j0; k0 < n; k0 += 256) {
+        __syncthreads();
+        {
+            const int k = k0 + threadIdx.x;
+            const bool kok = k < n && k != p;
+            double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+            if (k < n) {
+                d0 = x[3 * (int64_t)k];
+                d1 = x[3 * (int64_t)k + 1];
+                d2 = x[3 * (int64_t)k + 2];
+            }
+            xk[0][threadIdx.x] = d0;
+            xk[1][threadIdx.x] = d1;
+            xk[2][threadIdx.x] = d2;
+            double a, q, w, ia;
+            pair_terms(d0 - xp0, d1 - xp1, d2 - xp2, kok, a, q, w, ia);
+            ak[threadIdx.x] = a;
+            qk[threadIdx.x] = q;
+            wk[threadIdx.x] = w;
+        }
+        __syncthreads();
+        if (jok) {
+            const int lim = min(256, n - k0);
+            for (int t = 0; t < lim; ++t) {
+                const int k = k0 + t;
+                if (k <= j || qk[t] == 0.0) continue;
+                double a3, q3, w3, i3;
+                pair_terms(xk[0][t] - xj0, xk[1][t] - xj1, xk[2][t] - xj2, true, a3, q3, w3, i3);
+                acc += phi_from_pairs<double>(a1, q1, w1, ak[t], qk[t], wk[t], a3, q3, w3);
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&out[f], acc);
+}
+
+__global__ void zero_i32_kernel(int32_t *p) { *p = 0; }
+
+__global__ void scatter_points_kernel(const int32_t *__restrict__ list, int m,
+                                      const double *__restrict__ vals, double *__restrict__ phi) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f < m) phi[list[f]] = vals[f];
+}
+
 // Prefix offsets of the unit list, units of J block b: units_a(b) * (nt - b / 4).
 __global__ void unit_offsets_kernel(int nb, int nt, int ib, int na, int64_t *__restrict__ off) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -179,13 +360,73 @@ mb_status validate_points(const double *x, int64_t n, hipStream_t s, ValidateOut
     return MB_OK;
 }
 
+mb_status near_refine_launch(const double *x, int64_t n, double scale, double r_fix, double *phi,
+                             double *mag, hipStream_t s) {
+    if (n < 3 || !(r_fix > 0.0)) return MB_OK;
+    Scratch lists;
+    mb_status st = lists.alloc(sizeof(int32_t) * (size_t)n * (kNearMax + 1), s);
+    if (st != MB_OK) return st;
+    int32_t *cnt = lists.as<int32_t>();
+    int32_t *nbr = cnt + n;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    const double rc2 = r_fix * r_fix;
+    const double s2 = scale * scale;
+    const double out_scale = s2 * s2 * s2 * s2 * scale;
+    if ((st = zero_doubles(mag, n, s)) != MB_OK) return st;
+    near_list_kernel<<<blocks, 256, 0, s>>>(x, (int)n, rc2, cnt, nbr);
+    near_fix_kernel<<<blocks, 256, 0, s>>>(x, (int)n, scale, out_scale, rc2, cnt, nbr, phi, mag);
+    MB_HIP(hipGetLastError());
+    return MB_OK;
+}
+
+mb_status point_fp64_finish(const double *x, int64_t n, const double *mag, double *phi,
+                            hipStream_t s, int64_t *recomputed) {
+    if (recomputed) *recomputed = 0;
+    if (n < 3) return MB_OK;
+    const int cap = (int)std::max<int64_t>(kPointFixMin, n / kPointFixShare);
+    Scratch buf;
+    mb_status st = buf.alloc(sizeof(int32_t) * (cap + 1) + sizeof(double) * cap + 64, s);
+    if (st != MB_OK) return st;
+    int32_t *count = buf.as<int32_t>();
+    int32_t *list = count + 1;
+    double *vals = reinterpret_cast<double *>(
+        (reinterpret_cast<uintptr_t>(list + cap) + 15) & ~(uintptr_t)15);
+    zero_i32_kernel<<<1, 1, 0, s>>>(count);
+    flag_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(phi, mag, (int)n, kPointFixRatio, list,
+                                                             count, cap);
+    MB_HIP(hipGetLastError());
+    int32_t m = 0;
+    MB_HIP(hipMemcpyAsync(&m, count, sizeof m, hipMemcpyDeviceToHost, s));
+    MB_HIP(hipStreamSynchronize(s));
+    if (m == 0) return MB_OK;
+    if (m > cap) {
+        // too many ill-conditioned points for point-wise repair: binary64 throughout
+        if (recomputed) *recomputed = n;
+        if ((st = zero_doubles(phi, n, s)) != MB_OK) return st;
+        return direct_launch_t<double>(x, n, 1.0, phi, s);
+    }
+    if (recomputed) *recomputed = m;
+    if ((st = zero_doubles(vals, m, s)) != MB_OK) return st;
+    point_fp64_kernel<<<dim3((unsigned)((n + 255) / 256), (unsigned)m), 256, 0, s>>>(x, (int)n, list,
+                                                                                   vals);
+    scatter_points_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(list, m, vals, phi);
+    MB_HIP(hipGetLastError());
+    return MB_OK;
+}
+
 mb_status direct_launch(const double *x, int64_t n, int prec, double scale, double *phi,
-                        hipStream_t s) {
+                        hipStream_t s, double r_fix, int64_t *recomputed) {
+    if (recomputed) *recomputed = 0;
     mb_status st = zero_doubles(phi, n, s);
     if (st != MB_OK) return st;
     if (n < 3) return MB_OK;
-    return prec == MB_FP64 ? direct_launch_t<double>(x, n, scale, phi, s)
-                           : direct_launch_t<float>(x, n, scale, phi, s);
+    if (prec == MB_FP64) return direct_launch_t<double>(x, n, scale, phi, s);
+    if ((st = direct_launch_t<float>(x, n, scale, phi, s)) != MB_OK) return st;
+    if (!(r_fix > 0.0)) return MB_OK;
+    Scratch mag;
+    if ((st = mag.alloc(sizeof(double) * (size_t)n, s)) != MB_OK) return st;
+    if ((st = near_refine_launch(x, n, scale, r_fix, phi, mag.as<double>(), s)) != MB_OK) return st;
+    return point_fp64_finish(x, n, mag.as<double>(), phi, s, recomputed);
 }
 
 }  // namespace mb

@@ -40,6 +40,9 @@ constexpr int kB = 64;              // points per J block
 constexpr int kKT = 256;            // points per K tile (four per lane)
 constexpr int kKR = kKT / 64;       // k points per lane
 constexpr int kJC = 16;             // j points per LDS chunk
+#ifndef MB_FOLD_J
+#define MB_FOLD_J 16                // j steps per binary32 partial of Phi_i
+#endif
 
 // Tile shape per arithmetic type: i points per wave.
 template <typename T> struct DirectShape;
@@ -123,6 +126,22 @@ __global__ __launch_bounds__(256) void pair_table_kernel(const double *__restric
         out[3 * e + 1] = (T)pq;
         out[3 * e + 2] = (T)pw;
     }
+}
+
+// psi of one triple as the tiles evaluate it (phi = q_jk psi), from the
+// (i, j) terms (a, qa, wa), the (i, k) terms (g, qg, wg) and the (j, k)
+// terms (b, bb = b * b, ob = 3/8 / b).  Written once so that the binary32
+// near-field refinement reproduces the tile value bit for bit.
+template <typename T>
+__device__ __forceinline__ T tile_psi(T a, T qa, T wa, T g, T qg, T wg, T b, T bb, T ob) {
+    const T d = a - g;
+    const T tt = (a + g) - b;
+    const T m = fma(-d, d, bb);
+    const T X = qa * qg;
+    const T W = wa * wg;
+    const T P = tt * m;
+    const T Y = W * P;
+    return fma(ob, Y, X);
 }
 
 // One work unit (I block a, J block b, K tile t) of the triple sum; ublk is
@@ -227,15 +246,8 @@ __device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__res
                 const T al = o.u[3 * ii], qa = o.u[3 * ii + 1], wa = o.u[3 * ii + 2];
 #pragma unroll
                 for (int kk = 0; kk < kKR; ++kk) {
-                    const T g = ag[ii][kk];
-                    const T d = al - g;
-                    const T tt = (al + g) - o.cb[kk];
-                    const T m = fma(-d, d, bb[kk]);
-                    const T X = qa * aq[ii][kk];
-                    const T W = wa * aw[ii][kk];
-                    const T P = tt * m;
-                    const T Y = W * P;
-                    const T psi = fma(o.co[kk], Y, X);
+                    const T psi = tile_psi(al, qa, wa, ag[ii][kk], aq[ii][kk], aw[ii][kk], o.cb[kk],
+                                           bb[kk], o.co[kk]);
                     sk[kk] = ii ? sk[kk] + psi : psi;
                     acc_i[ii] = fma(o.cq[kk], psi, acc_i[ii]);
                 }
@@ -266,6 +278,17 @@ __device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__res
             if (jj + 2 < kJC) load(jj + 2, A);
             sched_fence();
             step(jj + 1, B);
+#if MB_FOLD_J < 16
+            if constexpr (sizeof(T) == 4) {
+                if (((jj + 2) % MB_FOLD_J) == 0 && jj + 2 < kJC) {
+#pragma unroll
+                    for (int ii = 0; ii < IPW; ++ii) {
+                        acc_i64[ii] += (double)acc_i[ii];
+                        acc_i[ii] = T(0);
+                    }
+                }
+            }
+#endif
         }
         // fold the short binary32 partial sums of Phi_i into binary64
         if constexpr (sizeof(T) == 4) {

@@ -80,9 +80,34 @@ size_t table_budget_bytes();
 
 // Direct (exhaustive) evaluation, no validation; phi is zeroed and
 // accumulated.  `scale` is a power of two applied to all coordinate
-// differences (the result is rescaled exactly).
+// differences (the result is rescaled exactly).  For binary32 tiles, r_fix > 0
+// also runs the near-field refinement below.
+// `recomputed` (nullable) receives how many points point_fp64_finish redid.
 mb_status direct_launch(const double *x, int64_t n, int prec, double scale, double *phi,
-                        hipStream_t s);
+                        hipStream_t s, double r_fix = 0.0, int64_t *recomputed = nullptr);
+
+// Near-field refinement of a binary32 tile sum already in (or going to)
+// phi: every triple with all sides < r_fix (input units), at most 64
+// forward neighbours per point, is moved from its binary32 tile value to
+// binary64.  mag[0:n] receives, per point, the sum of |phi| over those
+// triples.  Enqueue only.
+mb_status near_refine_launch(const double *x, int64_t n, double scale, double r_fix, double *phi,
+                             double *mag, hipStream_t s);
+
+// After a refined binary32 sum: points with |Phi| < kPointFixRatio * mag
+// (where cancellation can lift the binary32 error above 1e-6 of |Phi|) get
+// Phi recomputed point by point in binary64; beyond
+// max(kPointFixMin, n / kPointFixShare) such points the whole sum is redone
+// in binary64.  Waits on the stream.
+mb_status point_fp64_finish(const double *x, int64_t n, const double *mag, double *phi,
+                            hipStream_t s, int64_t *recomputed);
+
+// Radius of the near-field refinement, in multiples of the closest-pair
+// distance.
+constexpr double kNearFixFactor = 4.0;
+constexpr double kPointFixRatio = 0.25;
+constexpr int64_t kPointFixMin = 256;
+constexpr int64_t kPointFixShare = 64;
 
 // Ratio limit between the bounding-box diagonal and the closest pair above
 // which the binary32 path hands over to binary64.
@@ -94,6 +119,13 @@ mb_status check_points(const double *x, int64_t n, hipStream_t s, ValidateOut *v
 
 // Power of two that maps the closest-pair distance sqrt(min_d2) into [1, 2).
 double unit_scale(double min_d2);
+
+// Whether binary32 tiles suit a validated point set: the bounding-box
+// diagonal is within kFp32MaxRatio of the closest pair, and the closest pair
+// is at least a quarter of the mean spacing (cube root of box volume per
+// point).  A pair much closer than the spacing makes thin triangles whose
+// binary32 law-of-cosines terms lose about log2(spacing / pair) bits.
+bool fp32c_suitable(const ValidateOut &v, int64_t n);
 
 struct FactorStats {
     double pairmat_ms = 0.0, gemm_ms = 0.0, near_ms = 0.0;

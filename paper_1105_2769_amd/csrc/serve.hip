@@ -134,10 +134,11 @@ int64_t table_bytes(int64_t n, bool f64) {
     return na * nb * ib * kB * 3 * (f64 ? 8 : 4);
 }
 
-// Device bytes a request holds while admitted: points, Phi and the (i, j)
-// table, for binary64 tiles when binary64 may be needed.
+// Device bytes a request holds while admitted: points, Phi, the near-field
+// magnitudes of the binary32 refinement and the (i, j) table, for binary64
+// tiles when binary64 may be needed.
 int64_t footprint(int64_t n, bool f64) {
-    return align256(24 * n) + align256(8 * n) + align256(table_bytes(n, f64));
+    return align256(24 * n) + 2 * align256(8 * n) + align256(table_bytes(n, f64));
 }
 
 struct Request {
@@ -150,7 +151,7 @@ struct Request {
     bool done = false, fetched = false;
     // device side, owned by the scheduler thread
     void *chunk = nullptr;
-    double *dx = nullptr, *dphi = nullptr;
+    double *dx = nullptr, *dphi = nullptr, *dmag = nullptr;
     void *dtab = nullptr;
     double scale = 1.0, out_scale = 1.0;
     UnitMap um;
@@ -354,7 +355,8 @@ private:
         char *base = static_cast<char *>(r.chunk);
         r.dx = reinterpret_cast<double *>(base);
         r.dphi = reinterpret_cast<double *>(base + align256(24 * n));
-        r.dtab = base + align256(24 * n) + align256(8 * n);
+        r.dmag = reinterpret_cast<double *>(base + align256(24 * n) + align256(8 * n));
+        r.dtab = base + align256(24 * n) + 2 * align256(8 * n);
         MB_HIP(hipMemcpyAsync(r.dx, r.x.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, as_));
         mb_status st = zero_doubles(r.dphi, n, as_);
         if (st != MB_OK) return st;
@@ -371,9 +373,7 @@ private:
         r.prec = r.prec_req;
         r.scale = 1.0;
         if (r.prec == MB_FP32C) {
-            double diag2 = 0.0;
-            for (int c = 0; c < 3; ++c) diag2 += (v.hi[c] - v.lo[c]) * (v.hi[c] - v.lo[c]);
-            if (diag2 > kFp32MaxRatio * kFp32MaxRatio * md2) {
+            if (!fp32c_suitable(v, n)) {
                 r.prec = MB_FP64;
                 std::lock_guard<std::mutex> g(mu_);
                 stats_.fp64_fallbacks += 1;
@@ -393,6 +393,12 @@ private:
             pair_table_kernel<float><<<g, 256, 0, as_>>>(r.dx, (int)n, r.um.na, 0, r.scale,
                                                          static_cast<float *>(r.dtab));
         MB_HIP(hipGetLastError());
+        if (!f64) {
+            const mb_status fx =
+                near_refine_launch(r.dx, n, r.scale, kNearFixFactor * std::sqrt(md2), r.dphi,
+                                   r.dmag, as_);
+            if (fx != MB_OK) return fx;
+        }
         units = r.um.units();
         keep = footprint(n, f64);
         return MB_OK;
@@ -467,6 +473,15 @@ private:
 
     mb_status finalize(int64_t id) {
         Request &r = req(id);
+        if (r.prec == MB_FP32C) {
+            int64_t redone = 0;
+            const mb_status st = point_fp64_finish(r.dx, r.n, r.dmag, r.dphi, as_, &redone);
+            if (st != MB_OK) return st;
+            if (redone) {
+                std::lock_guard<std::mutex> g(mu_);
+                stats_.points_fp64 += redone;
+            }
+        }
         r.phi.resize(r.n);
         MB_HIP(hipMemcpyAsync(r.phi.data(), r.dphi, sizeof(double) * r.n, hipMemcpyDeviceToHost, as_));
         MB_HIP(hipStreamSynchronize(as_));

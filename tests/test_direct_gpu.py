@@ -123,3 +123,29 @@ def test_c2_sampled(prec, cuda):
     rel = np.abs(got - ref) / np.abs(ref)
     print(f"C2 {prec}: max rel err {rel.max():.3e} mean {rel.mean():.3e}")
     assert rel.max() <= TOL[prec]
+
+
+@pytest.mark.parametrize("n,seed", [(4096, 2), (32768, 2)])
+def test_fp32c_every_particle_within_1e6(n, seed, cuda):
+    # Every particle of the binary32 path against the binary64 path, which the
+    # oracle pins to 1e-12 on the same points (C1, C2 samples above).  The
+    # near-field refinement is what brings the worst (smallest-|Phi|, surface)
+    # particles under the bar.
+    x = workloads.jittered_lattice(n, seed=seed)
+    f64 = run(x, "fp64", cuda)
+    f32 = run(x, "fp32c", cuda)
+    rel = np.abs(f32 - f64) / np.abs(f64)
+    print(f"N={n}: fp32c vs fp64 max rel {rel.max():.3e} at phi {f64[np.argmax(rel)]:.4g}")
+    assert rel.max() <= 1e-6
+
+
+def test_fp32c_falls_back_for_close_pairs(cuda):
+    # uniform random points have pairs far closer than the mean spacing; the
+    # thin triangles they make lose bits in binary32, so FP32C hands over to
+    # binary64 and meets the binary64 bar
+    x = workloads.uniform_cube(3000, seed=12) * 20.0
+    f64 = run(x, "fp64", cuda)
+    f32 = run(x, "fp32c", cuda)
+    rel = np.abs(f32 - f64) / np.abs(f64)
+    print(f"uniform N=3000: fp32c vs fp64 max rel {rel.max():.3e}")
+    assert rel.max() <= 1e-12

@@ -118,9 +118,9 @@ def test_budget_admission(cuda):
     import paper_1105_2769_amd as mb
 
     n = 600
-    # 24 N + 8 N + a binary64 table of ceil(N/32) ceil(N/64) 32*64*3*8 bytes,
-    # each part rounded up to 256 bytes
-    need = 14592 + 4864 + (19 * 10 * 32 * 64 * 3 * 8)
+    # 24 N (points) + 8 N (Phi) + 8 N (near-field magnitudes) + a binary64
+    # table of ceil(N/32) ceil(N/64) 32*64*3*8 bytes, each part rounded up to 256
+    need = 14592 + 2 * 4864 + (19 * 10 * 32 * 64 * 3 * 8)
     with server(hbm_budget_bytes=need - 1) as srv:
         with pytest.raises(mb.MBError) as e:
             srv.submit(workloads.jittered_lattice(n, seed=1))
