@@ -16,7 +16,9 @@ Extra fields:
                  FMA = 2) against the MI355X FP64 (or FP32) vector peak; its
                  duration is measured with HIP events around enqueue-only
                  calls (mb_eval_direct_unchecked) on the stream the kernel
-                 runs on.
+                 runs on; traffic = HBM bytes per launch from the committed
+                 FETCH_SIZE / WRITE_SIZE summary (scaled by a 1 GiB copy),
+                 null when the tile sources changed since.
   cpu_baseline - the CPU oracle timed on the host's cores on a bounded
                  sample of the same workload (a few particles' full sums);
                  its values also give the accuracy check above.
@@ -49,6 +51,33 @@ DTYPE = {"fp64": "f64", "fp32c": "f32"}
 
 def comb3(n: int) -> int:
     return n * (n - 1) * (n - 2) // 6
+
+
+def measured_traffic(prec: str):
+    """HBM bytes per launch of the tile kernel from the committed PMC summary.
+
+    The counts hold only for the tile sources they were taken with, so they
+    are returned only while the SHA-256 of those sources matches the one
+    recorded beside them; otherwise None.
+    """
+    import hashlib
+
+    csrc = os.path.join(ROOT, "paper_1105_2769_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("direct_tile.hpp", "at_device.hpp"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    path = os.path.join(ROOT, "profiles", "direct_kernel_n32768_pmc.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if not line.startswith("traffic-record:"):
+            continue
+        kv = dict(tok.split("=", 1) for tok in line.split()[1:])
+        if kv.get("prec") == prec and kv.get("source_sha256") == h.hexdigest():
+            return 1024.0 * (float(kv["fetch_kib"]) * float(kv["fetch_scale"]) +
+                             float(kv["write_kib"]) * float(kv["write_scale"]))
+    return None
 
 
 def main() -> int:
@@ -189,7 +218,8 @@ def main() -> int:
                                f"(spacing 1.0, jitter 0.25, seed 2)",
                    "n": n, "prec": best, "triples_per_step": triples},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[best],
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[best], "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[best],
+                     "traffic": measured_traffic(best) if args.n == 32768 else None,
                      "kernel": "direct_kernel", "kernel_ms": r["kern_s"] * 1e3},
         "cpu_baseline": cpu,
         "latency": latency,
@@ -262,6 +292,9 @@ def serve_leg(n_req: int, dev) -> dict:
         "triples_per_s": total / t_end,
         "offered_triples_per_s": total / float(t_arr[-1]),
         "gpu_busy_frac": (st["busy_ms"] - st0["busy_ms"]) / 1e3 / t_end,
+        "host_stage_ms": st["stage_ms"] - st0["stage_ms"],
+        "host_finalize_ms": st["finalize_ms"] - st0["finalize_ms"],
+        "points_fp64": st["points_fp64"] - st0["points_fp64"],
         "slices": st["slices"] - st0["slices"],
         "mixed_slices": st["mixed_slices"] - st0["mixed_slices"],
         "peak_active": st["peak_active"],

@@ -285,6 +285,7 @@ typedef struct {
     int32_t peak_active, pad;              /* admitted requests at most          */
     double triples;                        /* sum of C(N, 3) of completed ones   */
     double busy_ms;                        /* compute-stream time of the slices  */
+    double stage_ms, finalize_ms;          /* host time staging / finishing requests */
 } mb_server_stats;
 
 /*
@@ -337,6 +338,13 @@ mb_status mb_server_set_slice_units(void *srv, int64_t units);
 
 /* Finish every request already submitted, then free the server. */
 mb_status mb_server_destroy(void *srv);
+
+/*
+ * sizeof of a struct of this header by name ("mb_mt_params", "mb_mt_stats",
+ * "mb_factor_stats", "mb_server_stats"), so that bindings can check their
+ * layouts; -1 for an unknown name.  Host only.
+ */
+int64_t mb_struct_size(const char *name);
 
 #ifdef __cplusplus
 }

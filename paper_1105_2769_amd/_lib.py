@@ -71,7 +71,8 @@ class ServerStats(ctypes.Structure):
                 ("submitted", "completed", "failed", "fp64_fallbacks", "slices", "units",
                  "mixed_slices", "points_fp64", "peak_reserved")] + \
                [("peak_active", ctypes.c_int32), ("pad", ctypes.c_int32),
-                ("triples", ctypes.c_double), ("busy_ms", ctypes.c_double)]
+                ("triples", ctypes.c_double), ("busy_ms", ctypes.c_double),
+                ("stage_ms", ctypes.c_double), ("finalize_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
@@ -104,6 +105,7 @@ SIGNATURES = {
     "mb_server_stats_get": (_c_i32, [_c_vp, ctypes.POINTER(ServerStats)]),
     "mb_server_set_slice_units": (_c_i32, [_c_vp, _c_i64]),
     "mb_server_destroy": (_c_i32, [_c_vp]),
+    "mb_struct_size": (_c_i64, [ctypes.c_char_p]),
 }
 HALF = {"fp16": 0, "bf16": 1}
 

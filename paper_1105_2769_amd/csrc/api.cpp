@@ -337,4 +337,14 @@ mb_status mb_eval_factorized(const double *x, int64_t n, int32_t fmt, int32_t pl
 
 double mb_normal_quantile(double alpha_half) { return normal_quantile_upper(alpha_half); }
 
+int64_t mb_struct_size(const char *name) {
+    if (!name) return -1;
+    const std::string s(name);
+    if (s == "mb_mt_params") return (int64_t)sizeof(mb_mt_params);
+    if (s == "mb_mt_stats") return (int64_t)sizeof(mb_mt_stats);
+    if (s == "mb_factor_stats") return (int64_t)sizeof(mb_factor_stats);
+    if (s == "mb_server_stats") return (int64_t)sizeof(mb_server_stats);
+    return -1;
+}
+
 }  // extern "C"

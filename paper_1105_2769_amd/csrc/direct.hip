@@ -147,8 +147,10 @@ __global__ void flag_kernel(const double *__restrict__ phi, const double *__rest
 // staged in LDS per tile of k.
 __global__ __launch_bounds__(256) void point_fp64_kernel(const double *__restrict__ x, int n,
                                                          const int32_t *__restrict__ list,
+                                                         const int32_t *__restrict__ count,
                                                          double *__restrict__ out) {
     const int f = blockIdx.y;
+    if (f >= *count) return;  // grid sized for the cap; the list may be shorter
     const int p = list[f];
     const int j0 = blockIdx.x * 256;
     const int j = j0 + threadIdx.x;
@@ -202,10 +204,11 @@ __global__ __launch_bounds__(256) void point_fp64_kernel(const double *__restric
 
 __global__ void zero_i32_kernel(int32_t *p) { *p = 0; }
 
-__global__ void scatter_points_kernel(const int32_t *__restrict__ list, int m,
-                                      const double *__restrict__ vals, double *__restrict__ phi) {
+__global__ void scatter_points_kernel(const int32_t *__restrict__ list, const int32_t *count,
+                                      int cap, const double *__restrict__ vals,
+                                      double *__restrict__ phi) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f < m) phi[list[f]] = vals[f];
+    if (f < min(*count, cap)) phi[list[f]] = vals[f];
 }
 
 // Prefix offsets of the unit list, units of J block b: units_a(b) * (nt - b / 4).
@@ -379,11 +382,15 @@ mb_status near_refine_launch(const double *x, int64_t n, double scale, double r_
     return MB_OK;
 }
 
-mb_status point_fp64_finish(const double *x, int64_t n, const double *mag, double *phi,
-                            hipStream_t s, int64_t *recomputed) {
-    if (recomputed) *recomputed = 0;
+int64_t point_fix_cap(int64_t n) {
+    return std::min<int64_t>(65535, std::max<int64_t>(kPointFixMin, n / kPointFixShare));
+}
+
+mb_status point_fp64_enqueue(const double *x, int64_t n, const double *mag, double *phi,
+                             hipStream_t s, int32_t *count_host) {
+    *count_host = 0;
     if (n < 3) return MB_OK;
-    const int cap = (int)std::max<int64_t>(kPointFixMin, n / kPointFixShare);
+    const int cap = (int)point_fix_cap(n);
     Scratch buf;
     mb_status st = buf.alloc(sizeof(int32_t) * (cap + 1) + sizeof(double) * cap + 64, s);
     if (st != MB_OK) return st;
@@ -392,26 +399,20 @@ mb_status point_fp64_finish(const double *x, int64_t n, const double *mag, doubl
     double *vals = reinterpret_cast<double *>(
         (reinterpret_cast<uintptr_t>(list + cap) + 15) & ~(uintptr_t)15);
     zero_i32_kernel<<<1, 1, 0, s>>>(count);
-    flag_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(phi, mag, (int)n, kPointFixRatio, list,
-                                                             count, cap);
+    if ((st = zero_doubles(vals, cap, s)) != MB_OK) return st;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    flag_kernel<<<blocks, 256, 0, s>>>(phi, mag, (int)n, kPointFixRatio, list, count, cap);
+    point_fp64_kernel<<<dim3(blocks, (unsigned)cap), 256, 0, s>>>(x, (int)n, list, count, vals);
+    scatter_points_kernel<<<(unsigned)((cap + 255) / 256), 256, 0, s>>>(list, count, cap, vals, phi);
     MB_HIP(hipGetLastError());
-    int32_t m = 0;
-    MB_HIP(hipMemcpyAsync(&m, count, sizeof m, hipMemcpyDeviceToHost, s));
-    MB_HIP(hipStreamSynchronize(s));
-    if (m == 0) return MB_OK;
-    if (m > cap) {
-        // too many ill-conditioned points for point-wise repair: binary64 throughout
-        if (recomputed) *recomputed = n;
-        if ((st = zero_doubles(phi, n, s)) != MB_OK) return st;
-        return direct_launch_t<double>(x, n, 1.0, phi, s);
-    }
-    if (recomputed) *recomputed = m;
-    if ((st = zero_doubles(vals, m, s)) != MB_OK) return st;
-    point_fp64_kernel<<<dim3((unsigned)((n + 255) / 256), (unsigned)m), 256, 0, s>>>(x, (int)n, list,
-                                                                                   vals);
-    scatter_points_kernel<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(list, m, vals, phi);
-    MB_HIP(hipGetLastError());
+    MB_HIP(hipMemcpyAsync(count_host, count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     return MB_OK;
+}
+
+mb_status point_fp64_redo_all(const double *x, int64_t n, double *phi, hipStream_t s) {
+    mb_status st = zero_doubles(phi, n, s);
+    if (st != MB_OK) return st;
+    return direct_launch_t<double>(x, n, 1.0, phi, s);
 }
 
 mb_status direct_launch(const double *x, int64_t n, int prec, double scale, double *phi,
@@ -426,7 +427,14 @@ mb_status direct_launch(const double *x, int64_t n, int prec, double scale, doub
     Scratch mag;
     if ((st = mag.alloc(sizeof(double) * (size_t)n, s)) != MB_OK) return st;
     if ((st = near_refine_launch(x, n, scale, r_fix, phi, mag.as<double>(), s)) != MB_OK) return st;
-    return point_fp64_finish(x, n, mag.as<double>(), phi, s, recomputed);
+    int32_t flagged = 0;
+    if ((st = point_fp64_enqueue(x, n, mag.as<double>(), phi, s, &flagged)) != MB_OK) return st;
+    MB_HIP(hipStreamSynchronize(s));
+    if (recomputed) *recomputed = flagged;
+    if (flagged <= point_fix_cap(n)) return MB_OK;
+    // too many strongly cancelling points for point-wise repair
+    if (recomputed) *recomputed = n;
+    return point_fp64_redo_all(x, n, phi, s);
 }
 
 }  // namespace mb

@@ -96,11 +96,14 @@ mb_status near_refine_launch(const double *x, int64_t n, double scale, double r_
 
 // After a refined binary32 sum: points with |Phi| < kPointFixRatio * mag
 // (where cancellation can lift the binary32 error above 1e-6 of |Phi|) get
-// Phi recomputed point by point in binary64; beyond
-// max(kPointFixMin, n / kPointFixShare) such points the whole sum is redone
-// in binary64.  Waits on the stream.
-mb_status point_fp64_finish(const double *x, int64_t n, const double *mag, double *phi,
-                            hipStream_t s, int64_t *recomputed);
+// Phi recomputed point by point in binary64, at most point_fix_cap(n) of
+// them.  Enqueue only; *count_host receives the number of such points once
+// the stream reaches it (more than the cap: the caller must redo the whole
+// sum, point_fp64_redo_all).
+int64_t point_fix_cap(int64_t n);
+mb_status point_fp64_enqueue(const double *x, int64_t n, const double *mag, double *phi,
+                             hipStream_t s, int32_t *count_host);
+mb_status point_fp64_redo_all(const double *x, int64_t n, double *phi, hipStream_t s);
 
 // Radius of the near-field refinement, in multiples of the closest-pair
 // distance.

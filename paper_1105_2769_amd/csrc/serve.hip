@@ -473,18 +473,26 @@ private:
 
     mb_status finalize(int64_t id) {
         Request &r = req(id);
+        int32_t flagged = 0;
         if (r.prec == MB_FP32C) {
-            int64_t redone = 0;
-            const mb_status st = point_fp64_finish(r.dx, r.n, r.dmag, r.dphi, as_, &redone);
+            const mb_status st = point_fp64_enqueue(r.dx, r.n, r.dmag, r.dphi, as_, &flagged);
             if (st != MB_OK) return st;
-            if (redone) {
-                std::lock_guard<std::mutex> g(mu_);
-                stats_.points_fp64 += redone;
-            }
         }
         r.phi.resize(r.n);
         MB_HIP(hipMemcpyAsync(r.phi.data(), r.dphi, sizeof(double) * r.n, hipMemcpyDeviceToHost, as_));
         MB_HIP(hipStreamSynchronize(as_));
+        if (flagged > point_fix_cap(r.n)) {  // rare: redo the request in binary64
+            const mb_status st = point_fp64_redo_all(r.dx, r.n, r.dphi, as_);
+            if (st != MB_OK) return st;
+            MB_HIP(hipMemcpyAsync(r.phi.data(), r.dphi, sizeof(double) * r.n, hipMemcpyDeviceToHost,
+                                  as_));
+            MB_HIP(hipStreamSynchronize(as_));
+            flagged = (int32_t)r.n;
+        }
+        if (flagged) {
+            std::lock_guard<std::mutex> g(mu_);
+            stats_.points_fp64 += flagged;
+        }
         MB_HIP(hipFreeAsync(r.chunk, as_));
         r.chunk = nullptr;
         sched_.release(id);
@@ -516,11 +524,17 @@ private:
         mb_status st;
         if (!sl.empty() && (st = launch(sl, nf, nd)) != MB_OK) return st;
         // 2. results of the previous slice come back meanwhile
+        const double t_fin = now_s();
         for (int64_t id : to_finalize)
             if ((st = finalize(id)) != MB_OK) return st;
+        if (!to_finalize.empty()) {
+            std::lock_guard<std::mutex> g(mu_);
+            stats_.finalize_ms += (now_s() - t_fin) * 1e3;
+        }
         to_finalize.clear();
         // 3. admit and stage new requests on the staging stream
         bool staged = false;
+        const double t_stage = now_s();
         for (int64_t id : sched_.admit()) {
             Request &r = req(id);
             int64_t units = 0, keep = 0;
@@ -541,6 +555,8 @@ private:
         if (staged) {
             MB_HIP(hipEventRecord(ev_adm_, as_));
             MB_HIP(hipStreamWaitEvent(cs_, ev_adm_, 0));
+            std::lock_guard<std::mutex> g(mu_);
+            stats_.stage_ms += (now_s() - t_stage) * 1e3;
         }
         // 4. wait for the slice
         if (!sl.empty()) {

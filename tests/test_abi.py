@@ -89,3 +89,13 @@ def test_server_bad_arguments_no_device():
     assert lib.mb_server_wait(None, 0, 0, None) == 1
     assert lib.mb_server_set_slice_units(None, 4) == 1
     assert lib.mb_server_destroy(None) == 0
+
+
+def test_struct_layouts_match_the_library():
+    import ctypes
+
+    lib = _lib.lib()
+    for name, cls in (("mb_mt_params", _lib.MtParams), ("mb_mt_stats", _lib.MtStats),
+                      ("mb_factor_stats", _lib.FactorStats), ("mb_server_stats", _lib.ServerStats)):
+        assert lib.mb_struct_size(name.encode()) == ctypes.sizeof(cls), name
+    assert lib.mb_struct_size(b"nope") == -1
