@@ -7,10 +7,11 @@
 // and run the exhaustive-sum tile code on them.  A request finishes when
 // every one of its units has run; its Phi is then copied back to the host.
 //
-// One slice is in flight at a time.  While it runs the thread copies back
-// the results of the previous slice and stages newly admitted requests on a
-// second stream, so the compute stream sees back-to-back slices.  Every
-// slice ends with a count check: each slot's items run == items issued.
+// Up to two slices are queued on the compute stream.  While they run the
+// thread copies back the results of finished requests and stages newly
+// admitted ones on a second stream, so the compute stream sees
+// back-to-back slices.  Every slice ends with a count check: each slot's
+// items run == items issued.
 #include "direct_tile.hpp"
 #include "mb_internal.hpp"
 #include "serve_sched.hpp"
@@ -20,6 +21,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -180,17 +182,19 @@ public:
             cs_ = own_cs_;
         }
         MB_HIP(hipStreamCreateWithFlags(&as_, hipStreamNonBlocking));
-        MB_HIP(hipEventCreateWithFlags(&ev_end_, hipEventDefault));
-        MB_HIP(hipEventCreateWithFlags(&ev_start_, hipEventDefault));
         MB_HIP(hipEventCreateWithFlags(&ev_adm_, hipEventDisableTiming));
-        MB_HIP(hipMalloc(&d_desc_, sizeof(ServeDesc) * max_slots_));
-        MB_HIP(hipHostMalloc(&h_desc_, sizeof(ServeDesc) * max_slots_, hipHostMallocDefault));
-        std::memset(h_desc_, 0, sizeof(ServeDesc) * max_slots_);
+        desc_table_.assign(max_slots_, ServeDesc{});
         ring_bytes_ = sizeof(unsigned) * (kHeaderWords + align_slots()) +
                       sizeof(ServeItem) * (size_t)kMaxSliceUnits;
-        MB_HIP(hipMalloc(&d_ring_, ring_bytes_));
-        MB_HIP(hipHostMalloc(&h_ring_, ring_bytes_, hipHostMallocDefault));
-        MB_HIP(hipHostMalloc(&h_counts_, sizeof(unsigned) * max_slots_, hipHostMallocDefault));
+        for (SliceBuf &b : buf_) {
+            MB_HIP(hipEventCreateWithFlags(&b.ev_end, hipEventDefault));
+            MB_HIP(hipEventCreateWithFlags(&b.ev_start, hipEventDefault));
+            MB_HIP(hipMalloc(&b.d_desc, sizeof(ServeDesc) * max_slots_));
+            MB_HIP(hipHostMalloc(&b.h_desc, sizeof(ServeDesc) * max_slots_, hipHostMallocDefault));
+            MB_HIP(hipMalloc(&b.d_ring, ring_bytes_));
+            MB_HIP(hipHostMalloc(&b.h_ring, ring_bytes_, hipHostMallocDefault));
+            MB_HIP(hipHostMalloc(&b.h_counts, sizeof(unsigned) * max_slots_, hipHostMallocDefault));
+        }
         thread_ = std::thread([this] { loop(); });
         return MB_OK;
     }
@@ -202,13 +206,15 @@ public:
         }
         cv_work_.notify_all();
         if (thread_.joinable()) thread_.join();
-        if (d_desc_) (void)hipFree(d_desc_);
-        if (d_ring_) (void)hipFree(d_ring_);
-        if (h_desc_) (void)hipHostFree(h_desc_);
-        if (h_ring_) (void)hipHostFree(h_ring_);
-        if (h_counts_) (void)hipHostFree(h_counts_);
-        if (ev_end_) (void)hipEventDestroy(ev_end_);
-        if (ev_start_) (void)hipEventDestroy(ev_start_);
+        for (SliceBuf &b : buf_) {
+            if (b.d_desc) (void)hipFree(b.d_desc);
+            if (b.d_ring) (void)hipFree(b.d_ring);
+            if (b.h_desc) (void)hipHostFree(b.h_desc);
+            if (b.h_ring) (void)hipHostFree(b.h_ring);
+            if (b.h_counts) (void)hipHostFree(b.h_counts);
+            if (b.ev_end) (void)hipEventDestroy(b.ev_end);
+            if (b.ev_start) (void)hipEventDestroy(b.ev_start);
+        }
         if (ev_adm_) (void)hipEventDestroy(ev_adm_);
         if (as_) (void)hipStreamDestroy(as_);
         if (own_cs_) (void)hipStreamDestroy(own_cs_);
@@ -309,15 +315,24 @@ public:
 private:
     static constexpr int64_t kMaxSliceUnits = 1 << 16;
 
+    // Buffers of one slice in flight; two alternate, so that the host can
+    // queue slice s + 1 while slice s runs.
+    struct SliceBuf {
+        ServeDesc *d_desc = nullptr, *h_desc = nullptr;
+        void *d_ring = nullptr, *h_ring = nullptr;
+        unsigned *h_counts = nullptr;
+        hipEvent_t ev_start = nullptr, ev_end = nullptr;
+    };
+
     size_t align_slots() const { return (size_t)((max_slots_ + 15) / 16) * 16; }
-    unsigned *d_header() const { return static_cast<unsigned *>(d_ring_); }
-    unsigned *d_counts() const { return d_header() + kHeaderWords; }
-    ServeItem *d_items() const {
-        return reinterpret_cast<ServeItem *>(d_counts() + align_slots());
+    static unsigned *d_header(const SliceBuf &b) { return static_cast<unsigned *>(b.d_ring); }
+    static unsigned *d_counts(const SliceBuf &b) { return d_header(b) + kHeaderWords; }
+    ServeItem *d_items(const SliceBuf &b) const {
+        return reinterpret_cast<ServeItem *>(d_counts(b) + align_slots());
     }
-    unsigned *h_header() const { return static_cast<unsigned *>(h_ring_); }
-    ServeItem *h_items() const {
-        return reinterpret_cast<ServeItem *>(h_header() + kHeaderWords + align_slots());
+    ServeItem *h_items(const SliceBuf &b) const {
+        return reinterpret_cast<ServeItem *>(static_cast<unsigned *>(b.h_ring) + kHeaderWords +
+                                             align_slots());
     }
 
     Request &req(int64_t id) {
@@ -404,7 +419,7 @@ private:
         return MB_OK;
     }
 
-    mb_status launch(const serve::Slice &sl, int &nf, int &nd) {
+    mb_status launch(const serve::Slice &sl, SliceBuf &b) {
         // items of binary32 requests first, then binary64
         std::vector<ServeItem> fi, di;
         for (const auto &rg : sl.ranges) {
@@ -416,7 +431,7 @@ private:
                 r.um.decode(u, it.a, it.b, it.t);
                 dst.push_back(it);
             }
-            ServeDesc &d = h_desc_[rg.slot];
+            ServeDesc &d = desc_table_[rg.slot];
             d.x = r.dx;
             d.phi = r.dphi;
             d.tab = r.dtab;
@@ -425,39 +440,42 @@ private:
             d.scale = r.scale;
             d.out_scale = r.out_scale;
         }
-        nf = (int)fi.size();
-        nd = (int)di.size();
-        std::memset(h_ring_, 0, sizeof(unsigned) * (kHeaderWords + align_slots()));
-        std::copy(fi.begin(), fi.end(), h_items());
-        std::copy(di.begin(), di.end(), h_items() + nf);
+        const int nf = (int)fi.size();
+        const int nd = (int)di.size();
+        // the pinned copies of b were last read by slice seq - 2, which has finished
+        std::memcpy(b.h_desc, desc_table_.data(), sizeof(ServeDesc) * max_slots_);
+        std::memset(b.h_ring, 0, sizeof(unsigned) * (kHeaderWords + align_slots()));
+        std::copy(fi.begin(), fi.end(), h_items(b));
+        std::copy(di.begin(), di.end(), h_items(b) + nf);
         const size_t bytes = sizeof(unsigned) * (kHeaderWords + align_slots()) +
                              sizeof(ServeItem) * (size_t)(nf + nd);
-        MB_HIP(hipEventRecord(ev_start_, cs_));
-        MB_HIP(hipMemcpyAsync(d_desc_, h_desc_, sizeof(ServeDesc) * max_slots_,
+        MB_HIP(hipEventRecord(b.ev_start, cs_));
+        MB_HIP(hipMemcpyAsync(b.d_desc, b.h_desc, sizeof(ServeDesc) * max_slots_,
                               hipMemcpyHostToDevice, cs_));
-        MB_HIP(hipMemcpyAsync(d_ring_, h_ring_, bytes, hipMemcpyHostToDevice, cs_));
+        MB_HIP(hipMemcpyAsync(b.d_ring, b.h_ring, bytes, hipMemcpyHostToDevice, cs_));
         if (nf)
             serve_kernel<float><<<(unsigned)std::min(nf, grid_f_), kThreads, 0, cs_>>>(
-                d_desc_, d_items(), nf, d_header() + 0, d_counts());
+                b.d_desc, d_items(b), nf, d_header(b) + 0, d_counts(b));
         if (nd)
             serve_kernel<double><<<(unsigned)std::min(nd, grid_d_), kThreads, 0, cs_>>>(
-                d_desc_, d_items() + nf, nd, d_header() + 1, d_counts());
+                b.d_desc, d_items(b) + nf, nd, d_header(b) + 1, d_counts(b));
         MB_HIP(hipGetLastError());
-        MB_HIP(hipMemcpyAsync(h_counts_, d_counts(), sizeof(unsigned) * max_slots_,
+        MB_HIP(hipMemcpyAsync(b.h_counts, d_counts(b), sizeof(unsigned) * max_slots_,
                               hipMemcpyDeviceToHost, cs_));
-        MB_HIP(hipEventRecord(ev_end_, cs_));
+        MB_HIP(hipEventRecord(b.ev_end, cs_));
         return MB_OK;
     }
 
-    mb_status finish_slice(const serve::Slice &sl, std::vector<int64_t> &finished) {
-        MB_HIP(hipEventSynchronize(ev_end_));
+    mb_status finish_slice(const serve::Slice &sl, const SliceBuf &b,
+                           std::vector<int64_t> &finished) {
+        MB_HIP(hipEventSynchronize(b.ev_end));
         float ms = 0.f;
-        MB_HIP(hipEventElapsedTime(&ms, ev_start_, ev_end_));
+        MB_HIP(hipEventElapsedTime(&ms, b.ev_start, b.ev_end));
         std::vector<int64_t> expect(max_slots_, 0);
         for (const auto &rg : sl.ranges) expect[rg.slot] += rg.u1 - rg.u0;
         for (int s = 0; s < max_slots_; ++s)
-            if ((int64_t)h_counts_[s] != expect[s])
-                return fail(MB_ERR_DEVICE, "drain kernel ran " + std::to_string(h_counts_[s]) +
+            if ((int64_t)b.h_counts[s] != expect[s])
+                return fail(MB_ERR_DEVICE, "drain kernel ran " + std::to_string(b.h_counts[s]) +
                                                " items of slot " + std::to_string(s) + ", issued " +
                                                std::to_string(expect[s]));
         {
@@ -467,7 +485,7 @@ private:
             if (sl.ranges.size() > 1) stats_.mixed_slices += 1;
             stats_.busy_ms += ms;
         }
-        finished = sched_.slice_done(sl);
+        for (int64_t id : sched_.slice_done(sl)) finished.push_back(id);
         return MB_OK;
     }
 
@@ -518,11 +536,15 @@ private:
             for (int64_t id : inbox_) sched_.enqueue(id, footprint(reqs_.at(id)->n, true));
             inbox_.clear();
         }
-        // 1. the next slice goes to the compute stream
-        serve::Slice sl = sched_.next_slice();
-        int nf = 0, nd = 0;
+        // 1. keep up to two slices queued on the compute stream
         mb_status st;
-        if (!sl.empty() && (st = launch(sl, nf, nd)) != MB_OK) return st;
+        if (inflight_.size() < 2) {
+            serve::Slice sl = sched_.next_slice();
+            if (!sl.empty()) {
+                if ((st = launch(sl, buf_[sl.seq & 1])) != MB_OK) return st;
+                inflight_.push_back(std::move(sl));
+            }
+        }
         // 2. results of the previous slice come back meanwhile
         const double t_fin = now_s();
         for (int64_t id : to_finalize)
@@ -558,11 +580,14 @@ private:
             std::lock_guard<std::mutex> g(mu_);
             stats_.stage_ms += (now_s() - t_stage) * 1e3;
         }
-        // 4. wait for the slice
-        if (!sl.empty()) {
-            if ((st = finish_slice(sl, to_finalize)) != MB_OK) return st;
-            idle = false;
-        } else {
+        // 4. wait for the oldest slice when two are queued or nothing else can
+        // be queued
+        idle = false;
+        if (!inflight_.empty() && (inflight_.size() == 2 || !sched_.has_runnable())) {
+            const serve::Slice &old = inflight_.front();
+            if ((st = finish_slice(old, buf_[old.seq & 1], to_finalize)) != MB_OK) return st;
+            inflight_.pop_front();
+        } else if (inflight_.empty()) {
             idle = to_finalize.empty() && !sched_.has_runnable();
         }
         {
@@ -616,11 +641,11 @@ private:
     serve::Scheduler sched_;  // scheduler thread only
     int max_slots_;
     hipStream_t user_stream_ = nullptr, own_cs_ = nullptr, cs_ = nullptr, as_ = nullptr;
-    hipEvent_t ev_start_ = nullptr, ev_end_ = nullptr, ev_adm_ = nullptr;
+    hipEvent_t ev_adm_ = nullptr;
     int dev_ = 0, grid_f_ = 1, grid_d_ = 1;
-    ServeDesc *d_desc_ = nullptr, *h_desc_ = nullptr;
-    void *d_ring_ = nullptr, *h_ring_ = nullptr;
-    unsigned *h_counts_ = nullptr;
+    SliceBuf buf_[2];
+    std::vector<ServeDesc> desc_table_;   // per slot, host master copy
+    std::deque<serve::Slice> inflight_;   // slices queued on the compute stream
     size_t ring_bytes_ = 0;
     std::thread thread_;
 
