@@ -169,10 +169,28 @@ typedef struct {
     uint64_t seed;     /* seed of the counter-based sampler                            */
     int32_t base_prec; /* arithmetic of the exhaustive base cases: MB_FP64 or MB_FP32C */
     int32_t chunk;     /* node triples processed per round of the device stack         */
+    int32_t bound;     /* MB_BOUND_SIGNED or MB_BOUND_MAGNITUDE (below)                */
+    int32_t pad;
 } mb_mt_params;
 
+/*
+ * What the node statistic Phi^l(P) of the prune rules holds.
+ *   MB_BOUND_SIGNED: the paper's running lower bound of the contributions
+ *     processed so far (Section 4.1, the deterministic-prune equation, and
+ *     the relative termination rule of Algorithm 4), which presumes
+ *     potentials >= 0.  The Axilrod-Teller potential is sign-indefinite; on
+ *     point sets where Phi is negative for many points nothing prunes.
+ *   MB_BOUND_MAGNITUDE: min over x in P of |running estimate of Phi(x)|
+ *     (exact and pruned contributions so far), used without the delta^l and
+ *     T_i (mu - z sigma) terms.  With near triples processed first (bands of
+ *     spread) this approximates |Phi(x)| from below for the far triples; the
+ *     guarantee becomes empirical (checked as the fraction of points within
+ *     eps).  Not in the paper.
+ */
+enum { MB_BOUND_SIGNED = 0, MB_BOUND_MAGNITUDE = 1 };
+
 /* Defaults: eps 1e-2, tau 0, alpha 0.05, m_limit 128, m_min 30, zeta 4,
- * seed 0, base_prec MB_FP32C, chunk 65536. */
+ * seed 0, base_prec MB_FP32C, chunk 65536, bound MB_BOUND_SIGNED. */
 void mb_mt_params_default(mb_mt_params *p);
 
 typedef struct {

@@ -65,6 +65,10 @@ Axilrod-Teller potential:
     numbers.  A 64-bit uniform integer r is (w1 << 32 | w0); an index in
     [0, M) is floor(r * M / 2^64).
   * Test order: deterministic, then Monte Carlo, then base case or split.
+  * Sign-indefinite potentials (optional reading, not in the paper): with
+    bound="magnitude" the node statistic is min over x in P of the magnitude
+    of x's running estimate, since the running lower bound of a potential
+    that is negative for many points stays negative and nothing prunes.
 """
 from __future__ import annotations
 
@@ -247,7 +251,8 @@ def det_bounds(d12: float, d13: float, d23: float) -> tuple[float, float]:
 
 
 def mc_try(tree: KdTree, xs: np.ndarray, p: tuple[int, int, int], roles, cnt, phil,
-           eps: float, tau: float, t_root: int, z: float, seed: int, m_limit: int, m_min: int):
+           eps: float, tau: float, t_root: int, z: float, seed: int, m_limit: int, m_min: int,
+           magnitude: bool = False):
     """Monte Carlo test of one node triple (Algorithm 3, Algorithm 4 per point).
 
     For every point x of every distinct node P_i (``roles`` = (node, T_i,
@@ -255,7 +260,8 @@ def mc_try(tree: KdTree, xs: np.ndarray, p: tuple[int, int, int], roles, cnt, ph
     running mean and unbiased variance updated; x stops at the first m with
     m >= m_min and
         z sigma_mu <= (eps (Phi^l(P_i) + T_i (mu - z sigma_mu)) + tau) / T_root,
-    and passes if that holds, else fails at m = m_limit.  Points are scanned
+    and passes if that holds, else fails at m = m_limit.  With ``magnitude``
+    the credit is Phi^l(P_i) alone (the magnitude reading, see ``multitree``).  Points are scanned
     in order and the scan ends at the first failure.  Returns (all passed,
     [(first rank, T_i, mu per point, sigma_mu per point)], samples used).
     """
@@ -285,7 +291,8 @@ def mc_try(tree: KdTree, xs: np.ndarray, p: tuple[int, int, int], roles, cnt, ph
             if m < 2:
                 continue
             sig_mu = np.sqrt(m2 / (m - 1) / m)
-            cond = z * sig_mu <= (eps * (plo + t * (mean - z * sig_mu)) + tau) / t_root
+            credit = plo if magnitude else plo + t * (mean - z * sig_mu)
+            cond = z * sig_mu <= (eps * credit + tau) / t_root
             fresh = (stop_m < 0) & ((cond & (m >= m_min)) | (m == m_limit))
             stop_m[fresh] = m
             mu_s[fresh] = mean[fresh]
@@ -310,17 +317,30 @@ class MTResult:
 
 
 def multitree(x, eps: float, alpha: float, leaf_size: int, tau: float = 0.0, seed: int = 0,
-              m_limit: int = 128, zeta: float = 4.0, m_min: int = 30) -> MTResult:
+              m_limit: int = 128, zeta: float = 4.0, m_min: int = 30,
+              bound: str = "signed") -> MTResult:
+    """The traversal.  ``bound`` chooses the node statistic of the prune rules:
+
+    * "signed": the paper's running lower bound Phi^l (Section 4.1);
+    * "magnitude" (a reading for sign-indefinite potentials, not in the
+      paper): min over x in P of |running estimate of Phi(x)| - exact and
+      pruned contributions credited so far - used without the delta^l and
+      T_i (mu - z sigma) terms.
+    """
     x = np.asarray(x, dtype=np.float64)
     n = x.shape[0]
     if eps < 0 or tau < 0 or not (0.0 <= alpha < 1.0) or leaf_size < 1:
         raise ValueError("bad multitree parameters")
+    if bound not in ("signed", "magnitude"):
+        raise ValueError("bound must be 'signed' or 'magnitude'")
+    magnitude = bound == "magnitude"
     tree = build_kdtree(x, leaf_size)
     xs = x[tree.perm]  # depth-first order
     t_root = comb2(n - 1) if n >= 1 else 0
     z = NormalDist().inv_cdf(1.0 - alpha / 2.0) if alpha > 0 else math.inf
     est = np.zeros(n)
     lb = np.zeros(n)
+    run = np.zeros(n)  # running estimate: est plus pruned node estimates so far
     cov = np.zeros(n, dtype=np.int64)
     node_acc = np.zeros(tree.n_nodes)
     st = dict(visited=0, det_prunes=0, mc_prunes=0, mc_failed=0, base_cases=0, base_triples=0,
@@ -332,6 +352,8 @@ def multitree(x, eps: float, alpha: float, leaf_size: int, tau: float = 0.0, see
         return slice(int(tree.begin[node]), int(tree.end[node]))
 
     def phi_l(node) -> float:
+        if magnitude:
+            return float(np.abs(run[pts(node)]).min())
         return float(lb[pts(node)].min())
 
     stack = [(0, 0, 0)]
@@ -350,11 +372,13 @@ def multitree(x, eps: float, alpha: float, leaf_size: int, tau: float = 0.0, see
             d23 = box_min_dist(tree.lo[p2], tree.hi[p2], tree.lo[p3], tree.hi[p3])
             if d12 > 0 and d13 > 0 and d23 > 0:
                 phi_lo, span = det_bounds(d12, d13, d23)
-                allow = min(phi_l(node) + t * phi_lo for node, t, _ in roles)
+                allow = min(phi_l(node) + (0.0 if magnitude else t * phi_lo)
+                            for node, t, _ in roles)
                 if span <= (eps * allow + tau) / t_root:
                     phic = float(at_phi_np(tree.centroid[p1], tree.centroid[p2], tree.centroid[p3]))
                     for node, t, _ in roles:
                         node_acc[node] += t * phic
+                        run[pts(node)] += t * phic
                         lb[pts(node)] += t * phi_lo
                         cov[pts(node)] += t
                     st["det_prunes"] += 1
@@ -363,12 +387,13 @@ def multitree(x, eps: float, alpha: float, leaf_size: int, tau: float = 0.0, see
         # (b) Monte Carlo prune (Algorithm 3 over the distinct nodes, Algorithm 4 per point)
         if alpha > 0 and zeta * m_limit <= min(t for _, t, _ in roles):
             ok, commits, used = mc_try(tree, xs, p, roles, cnt, [phi_l(node) for node, _, _ in roles],
-                                       eps, tau, t_root, z, seed, m_limit, m_min)
+                                       eps, tau, t_root, z, seed, m_limit, m_min, magnitude)
             st["mc_samples"] += used
             if ok:
                 for base, t, mu_s, sg_s in commits:
                     sl = slice(base, base + mu_s.shape[0])
                     est[sl] += t * mu_s
+                    run[sl] += t * mu_s
                     lb[sl] += t * (mu_s - z * sg_s)
                     cov[sl] += t
                 st["mc_prunes"] += 1
@@ -384,6 +409,7 @@ def multitree(x, eps: float, alpha: float, leaf_size: int, tau: float = 0.0, see
                 f = at_phi_np(xs[ri], xs[rj], xs[rk])
                 for r_ in (ri, rj, rk):
                     np.add.at(est, r_, f)
+                    np.add.at(run, r_, f)
                     np.add.at(lb, r_, f)
                     np.add.at(cov, r_, 1)
             st["base_cases"] += 1

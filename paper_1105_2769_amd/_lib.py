@@ -23,6 +23,7 @@ STATUS_NAMES = {
     5: "MB_ERR_UNSUPPORTED",
 }
 PREC = {"fp64": 0, "fp32c": 1}
+BOUND = {"signed": 0, "magnitude": 1}
 
 
 class MBError(RuntimeError):
@@ -44,7 +45,7 @@ class MtParams(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("m_limit", ctypes.c_int32),
                 ("m_min", ctypes.c_int32), ("zeta", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("base_prec", ctypes.c_int32),
-                ("chunk", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32), ("bound", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class MtStats(ctypes.Structure):
@@ -218,9 +219,14 @@ class KdTree:
 def mt_params(**kw) -> MtParams:
     p = MtParams()
     lib().mb_mt_params_default(ctypes.byref(p))
+    names = {name for name, _ in MtParams._fields_}
     for key, val in kw.items():
+        if key not in names:
+            raise TypeError(f"unknown traversal parameter {key!r}")
         if key == "base_prec" and isinstance(val, str):
             val = PREC[val]
+        if key == "bound" and isinstance(val, str):
+            val = BOUND[val]
         setattr(p, key, val)
     return p
 

@@ -239,6 +239,8 @@ void mb_mt_params_default(mb_mt_params *p) {
     p->seed = 0;
     p->base_prec = MB_FP32C;
     p->chunk = 65536;
+    p->bound = MB_BOUND_SIGNED;
+    p->pad = 0;
 }
 
 mb_status mb_eval_multitree(const double *x, int64_t n, int32_t leaf_size,
@@ -250,6 +252,7 @@ mb_status mb_eval_multitree(const double *x, int64_t n, int32_t leaf_size,
     if (n < 0 || (n > 0 && (!x || !phi))) return fail(MB_ERR_INVALID, "bad points or output");
     if (!(p.eps_rel >= 0.0) || !(p.tau_abs >= 0.0) || !(p.alpha >= 0.0 && p.alpha < 1.0) ||
         p.m_limit < 2 || p.m_min < 2 || !(p.zeta >= 0.0) || p.chunk < 1 ||
+        (p.bound != MB_BOUND_SIGNED && p.bound != MB_BOUND_MAGNITUDE) ||
         (p.base_prec != MB_FP64 && p.base_prec != MB_FP32C))
         return fail(MB_ERR_INVALID, "bad traversal parameters");
     if (n >= ((int64_t)1 << 31)) return fail(MB_ERR_UNSUPPORTED, "n must be < 2^31");
@@ -279,6 +282,7 @@ mb_status mb_eval_multitree(const double *x, int64_t n, int32_t leaf_size,
     mp.seed = p.seed;
     mp.base_prec = p.base_prec;
     mp.chunk = p.chunk;
+    mp.bound = p.bound;
     {
         double md2;
         std::memcpy(&md2, &v.min_d2_bits, sizeof md2);

@@ -67,6 +67,7 @@ struct MtConst {
     uint32_t seed32;
     int use_mc;
     int want_cov;
+    int magnitude;  // node_phil holds min |running estimate| (MB_BOUND_MAGNITUDE)
 };
 
 struct NodeView {
@@ -237,7 +238,8 @@ __global__ __launch_bounds__(256) void classify_kernel(
             const double span = 3.375 * ru;
             double allow = INFINITY;
             for (int q = 0; q < 3; ++q)
-                allow = fmin(allow, node_phil[r.node[q]] + (double)r.t[q] * phi_lo);
+                allow = fmin(allow, k.magnitude ? node_phil[r.node[q]]
+                                                : node_phil[r.node[q]] + (double)r.t[q] * phi_lo);
             if (span <= (k.eps * allow + k.tau) / k.t_root) {
                 // monopole estimate at the centroids, kept inside the bound interval
                 double phic = phi3(nv.centroid + 3 * p1, nv.centroid + 3 * p2,
@@ -404,8 +406,8 @@ __device__ McPoint mc_point_wave(const Item &it, char cs, int slot, int64_t off,
         const double mean = f0 + t1 / m;
         const double var = sidx >= 1 ? fmax(t2 - t1 * t1 / m, 0.0) / (m - 1.0) : 0.0;
         const double sig = sqrt(var / m);
-        const bool cond =
-            valid && sidx >= 1 && k.z * sig <= (k.eps * (plo + t * (mean - k.z * sig)) + k.tau) / k.t_root;
+        const double credit = k.magnitude ? plo : plo + t * (mean - k.z * sig);
+        const bool cond = valid && sidx >= 1 && k.z * sig <= (k.eps * credit + k.tau) / k.t_root;
         const bool ok = cond && sidx + 1 >= k.m_min;
         const bool stop = valid && (ok || sidx + 1 == k.m_limit);
         const unsigned long long bal = __ballot(stop);
@@ -700,16 +702,25 @@ __global__ __launch_bounds__(1024) void refresh_down_kernel(const int32_t *__res
     }
 }
 
+// Leaf statistic: min over the leaf's points of lb + (node lower-bound
+// increments on the path), or, for magnitude bounds, of |est + (node
+// accumulators on the path)|; `cum` holds the matching path sums.
 __global__ void refresh_leaf_kernel(const int32_t *__restrict__ leaves, int n_leaves,
                                     const int32_t *__restrict__ begin,
                                     const int32_t *__restrict__ end, const double *__restrict__ lb,
-                                    const double *__restrict__ cum, double *__restrict__ phil) {
+                                    const double *__restrict__ cum, int magnitude,
+                                    double *__restrict__ phil) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n_leaves) return;
     const int v = leaves[e];
     double mn = INFINITY;
-    for (int r = begin[v]; r < end[v]; ++r) mn = fmin(mn, lb[r]);
-    phil[v] = mn + cum[v];
+    if (magnitude) {
+        for (int r = begin[v]; r < end[v]; ++r) mn = fmin(mn, fabs(lb[r] + cum[v]));
+        phil[v] = mn;
+    } else {
+        for (int r = begin[v]; r < end[v]; ++r) mn = fmin(mn, lb[r]);
+        phil[v] = mn + cum[v];
+    }
 }
 
 __global__ __launch_bounds__(1024) void refresh_up_kernel(const int32_t *__restrict__ depth_nodes,
@@ -852,6 +863,7 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
     k.seed32 = (uint32_t)(prm.seed ^ (prm.seed >> 32));
     k.use_mc = prm.alpha > 0.0 ? 1 : 0;
     k.want_cov = coverage ? 1 : 0;
+    k.magnitude = prm.bound == 1 ? 1 : 0;
 
     auto grow = [&](Scratch &sc, Item *&buf, int64_t &c, int64_t keep, int64_t need) -> mb_status {
         if (need <= c) return MB_OK;
@@ -877,6 +889,23 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
         if (top == 0) {
             if (far_top == 0) break;
             // this band is done: the deferred triples become the stack
+            if (trace) {
+                MtCounters hc;
+                MB_HIP(hipMemcpy(&hc, ctr, sizeof hc, hipMemcpyDeviceToHost));
+                std::vector<double> pl(M);
+                MB_HIP(hipMemcpy(pl.data(), node_phil, sizeof(double) * M, hipMemcpyDeviceToHost));
+                std::vector<double> lv;
+                for (int32_t v : leaves) lv.push_back(pl[v]);
+                std::sort(lv.begin(), lv.end());
+                std::fprintf(stderr,
+                             "[mb multitree] end of band %d (spread <= %g): round %lld visited %llu "
+                             "det %llu mc %llu/%llu base %llu base triples %llu; leaf Phi^l min %g "
+                             "median %g max %g; deferred %lld\n",
+                             phase, phase == 0 ? 0.0 : spread_limit(phase), (long long)rounds,
+                             hc.visited, hc.det_prunes, hc.mc_prunes, hc.mc_failed, hc.base_cases,
+                             hc.base_triples, lv.front(), lv[lv.size() / 2], lv.back(),
+                             (long long)far_top);
+            }
             ++phase;
             std::swap(s_stack.ptr, s_far.ptr);
             std::swap(stack, far);
@@ -918,9 +947,10 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
         MB_HIP(hipMemcpyAsync(num, d_num, sizeof(num), hipMemcpyDeviceToHost, s));
         // Phi^l refresh for the next round
         refresh_down_kernel<<<1, 1024, 0, s>>>(t->depth_nodes, d_doff, n_depths, t->parent,
-                                               node_lo, cum);
+                                               k.magnitude ? node_acc : node_lo, cum);
         refresh_leaf_kernel<<<((int)leaves.size() + 255) / 256, 256, 0, s>>>(
-            d_leaves, (int)leaves.size(), t->begin, t->end, lb, cum, node_phil);
+            d_leaves, (int)leaves.size(), t->begin, t->end, k.magnitude ? est : lb, cum,
+            k.magnitude, node_phil);
         refresh_up_kernel<<<1, 1024, 0, s>>>(t->depth_nodes, d_doff, n_depths, t->left, t->right,
                                              node_phil);
         MB_HIP(hipGetLastError());

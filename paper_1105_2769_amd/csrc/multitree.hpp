@@ -20,6 +20,7 @@ struct MtParams {
     // largest box distance within the triple): 0, unit, 2 unit, 4 unit, ...;
     // 0 disables the bands (one LIFO stack)
     double spread_unit = 0.0;
+    int bound = 0;  // 0: signed running lower bound (the paper); 1: magnitude of the estimate
 };
 
 struct MtStats {

@@ -146,3 +146,45 @@ def test_errors(cuda):
     t = mb.KdTree(dev(x, cuda), 8)
     with pytest.raises(mb.MBError):
         mb.eval_multitree(dev(workloads.jittered_lattice(50, 1), cuda), tree=t)
+
+
+@pytest.mark.parametrize("alpha", [0.0, 0.05])
+def test_magnitude_bound_on_sign_indefinite_mixture(alpha, cuda):
+    # The Gaussian-mixture generator at N = 8192: 12 % of the points have
+    # Phi < 0, so the paper's running lower bound stays negative and prunes
+    # nothing; the magnitude statistic prunes most of the work and every
+    # sampled point stays within eps (against the CPU oracle).
+    import paper_1105_2769_amd as mb
+
+    x = workloads.saturated_gaussian_mixture(8192, seed=3)
+    n = x.shape[0]
+    idx = workloads.sample_indices(n, 48, seed=33)
+    ref = oracle_direct.phi(x, idx)
+    assert np.mean(ref < 0) > 0.0
+    eps = 1e-2
+    phi, st, cov = mb.eval_multitree(dev(x, cuda), eps=eps, alpha=alpha, leaf_size=32,
+                                     coverage=True, bound="magnitude", seed=11)
+    rel = np.abs(phi.cpu().numpy()[idx] - ref) / np.abs(ref)
+    frac_exh = st["base_triples"] / (n * (n - 1) * (n - 2) / 6)
+    print(f"magnitude alpha={alpha}: {st} within eps {np.mean(rel <= eps):.3f} max {rel.max():.2e} "
+          f"exhaustive fraction {frac_exh:.3f}")
+    assert st["det_prunes"] > 0 and frac_exh < 0.5
+    assert np.mean(rel <= eps) >= 1 - max(alpha, 0.0) and (alpha > 0 or rel.max() <= eps)
+    assert np.all(cov.cpu().numpy() == (n - 1) * (n - 2) // 2)
+    # the paper's signed statistic on the same points: exact, nothing pruned
+    _, st2 = mb.eval_multitree(dev(x, cuda), eps=eps, alpha=0.0, leaf_size=32)
+    assert st2["base_triples"] / (n * (n - 1) * (n - 2) / 6) > 0.9
+
+
+@pytest.mark.parametrize("bound", ["signed", "magnitude"])
+def test_eps0_exact_either_bound(bound, cuda):
+    import paper_1105_2769_amd as mb
+
+    x = workloads.saturated_gaussian_mixture(1500, seed=8)
+    ref = oracle_direct.phi(x)
+    phi, st, cov = mb.eval_multitree(dev(x, cuda), eps=0.0, alpha=0.0, leaf_size=16,
+                                     coverage=True, bound=bound, base_prec="fp64")
+    # binary64 rounding, measured against the largest |Phi| for the points
+    # whose Phi nearly cancels to zero
+    np.testing.assert_allclose(phi.cpu().numpy(), ref, rtol=1e-11, atol=1e-14 * np.abs(ref).max())
+    assert np.all(cov.cpu().numpy() == (1500 - 1) * (1500 - 2) // 2)

@@ -254,3 +254,21 @@ def test_mc_try_meets_the_clt_bound():
     frac = inside / total
     # binomial margin of 4 standard deviations below 1 - alpha
     assert frac >= 1 - alpha - 4 * math.sqrt(alpha * (1 - alpha) / total), frac
+
+
+def test_magnitude_mode_exact_at_eps0_and_within_eps():
+    # the magnitude reading changes only which triples prune: eps = 0 is still
+    # the exhaustive sum, and on five separated clusters every point stays
+    # within eps
+    x = workloads.jittered_lattice(60, seed=4)
+    res = omt.multitree(x, eps=0.0, alpha=0.0, leaf_size=4, bound="magnitude")
+    np.testing.assert_allclose(res.phi, oracle_direct.phi(x), rtol=1e-12)
+    x = blobs(24, [(0, 0, 0), (40, 0, 0), (0, 40, 0), (0, 0, 40), (40, 40, 40)], seed=11)
+    eps = 0.05
+    res = omt.multitree(x, eps=eps, alpha=0.0, leaf_size=4, bound="magnitude")
+    rel = np.abs(res.phi - oracle_direct.phi(x)) / np.abs(oracle_direct.phi(x))
+    assert res.stats["det_prunes"] > 0
+    assert np.all(res.coverage == math.comb(x.shape[0] - 1, 2))
+    assert rel.max() <= eps
+    with pytest.raises(ValueError):
+        omt.multitree(x, eps=eps, alpha=0.0, leaf_size=4, bound="other")
