@@ -28,6 +28,10 @@ Extra fields:
                  10^6 + r, FP32C; p50/p99 of submit-to-result latency,
                  completed triples per second over the trace, and the error
                  against the binary64 GPU sum on sampled requests.
+  multitree    - the triple-tree traversal on the N = 262144 Gaussian-mixture
+                 set (eps 1e-2, alpha 0.05, leaf 32, FP32C base cases,
+                 magnitude bound), effective triples/s = C(N, 3) / time and
+                 the fraction of the 64 stored oracle samples within eps.
   factorized   - the matrix-product form (FP16, two planes, r_near = 1.5)
                  on the N = 16384 lattice (seed 4) against the binary64 GPU
                  sum on all points.
@@ -93,6 +97,10 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=4096,
                     help="requests of the serving trace (0: skip the serving leg)")
     ap.add_argument("--no-factorized", action="store_true")
+    ap.add_argument("--multitree-n", type=int, default=262144,
+                    help="points of the Gaussian-mixture traversal leg (0: skip); 262144 is "
+                         "checked against stored oracle values, other sizes against the "
+                         "binary64 GPU sum")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (the "
                          "reference kernel for scaling HBM byte counters), then exit")
@@ -188,6 +196,7 @@ def main() -> int:
             results[prec]["frac_above_1e6"] = float(np.mean(r_all > 1e-6))
 
     latency = serve_leg(args.serve_requests, dev) if args.serve_requests else None
+    multitree = multitree_leg(args.multitree_n, dev) if args.multitree_n else None
     factorized = None if args.no_factorized else factorized_leg(dev)
 
     def meets(p):
@@ -223,6 +232,7 @@ def main() -> int:
                      "kernel": "direct_kernel", "kernel_ms": r["kern_s"] * 1e3},
         "cpu_baseline": cpu,
         "latency": latency,
+        "multitree": multitree,
         "factorized": factorized,
         "accuracy": {p: {"max_rel_err_oracle_sampled": results[p]["rel"],
                          "max_rel_err_all_vs_fp64": results[p].get("rel_all"),
@@ -304,6 +314,54 @@ def serve_leg(n_req: int, dev) -> dict:
     }
     print(f"serving: p50 {out['p50_ms']:.2f} ms p99 {out['p99_ms']:.2f} ms, "
           f"{out['triples_per_s']:.3e} triples/s, max rel err {worst:.2e}", flush=True)
+    return out
+
+
+def multitree_leg(n: int, dev) -> dict:
+    """The triple-tree traversal on the Gaussian-mixture set (eps 1e-2, alpha 0.05)."""
+    import json as _json
+
+    import numpy as np
+    import torch
+
+    import paper_1105_2769_amd as mb
+    import workloads
+
+    print(f"multitree: generating the N={n} Gaussian mixture", flush=True)
+    x_np = workloads.saturated_gaussian_mixture(n, seed=3)
+    x = torch.from_numpy(x_np).to(dev)
+    golden = os.path.join(ROOT, "tests", "golden", "c3_direct_samples.json")
+    if n == 262144 and os.path.exists(golden):
+        g = _json.load(open(golden))
+        idx = np.array(g["indices"])
+        ref = np.array([float(v) for v in g["phi"]])
+        ref_kind = "CPU oracle at 64 seeded-sampled points"
+    else:
+        idx = np.arange(n)
+        ref = mb.eval_direct(x, prec="fp64").cpu().numpy()
+        ref_kind = "binary64 GPU sum at every point"
+    out = {"workload": f"N={n} saturated 32-component Gaussian mixture (means U[0,100]^3, "
+                       f"sigma 2, min separation 0.3, seed 3), leaf 32, eps 1e-2, alpha 0.05, "
+                       f"FP32C base cases, magnitude bound", "reference": ref_kind}
+    for bound in ("magnitude",):
+        print(f"multitree: bound {bound}", flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        phi, st = mb.eval_multitree(x, eps=1e-2, alpha=0.05, leaf_size=32, bound=bound)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rel = np.abs(phi.cpu().numpy()[idx] - ref) / np.abs(ref)
+        out.update({
+            "seconds": dt,
+            "triples_per_s": comb3(n) / dt,
+            "within_eps_fraction": float(np.mean(rel <= 1e-2)),
+            "max_rel_err": float(rel.max()),
+            "median_rel_err": float(np.median(rel)),
+            "exhaustive_fraction": st["base_triples"] / comb3(n),
+            "stats": st,
+        })
+        print(f"multitree: {dt:.1f} s, {comb3(n) / dt:.3e} effective triples/s, within eps "
+              f"{out['within_eps_fraction']:.3f}", flush=True)
     return out
 
 

@@ -235,7 +235,7 @@ void mb_mt_params_default(mb_mt_params *p) {
     p->alpha = 0.05;
     p->m_limit = 128;
     p->m_min = 30;
-    p->zeta = 4.0;
+    p->zeta = 128.0;
     p->seed = 0;
     p->base_prec = MB_FP32C;
     p->chunk = 65536;

@@ -60,7 +60,7 @@ def test_multitree_bad_params_no_device():
     lib = _lib.lib()
     p = _lib.MtParams()
     lib.mb_mt_params_default(ctypes.byref(p))
-    assert p.m_limit == 128 and p.m_min == 30 and p.zeta == 4.0
+    assert p.m_limit == 128 and p.m_min == 30 and p.zeta == 128.0 and p.bound == 0
     for field, bad in (("eps_rel", -1.0), ("alpha", 1.0), ("alpha", -0.1), ("m_limit", 1),
                        ("base_prec", 9), ("chunk", 0), ("bound", 7)):
         q = _lib.MtParams()
