@@ -13,7 +13,7 @@ namespace mb {
 namespace {
 
 template <typename T>
-__global__ __launch_bounds__(kThreads, 1) void direct_kernel(
+__global__ __launch_bounds__(DirectLds<T>::TPB, 1) void direct_kernel(
     const double *__restrict__ x, int n, int na, int nb, int nt,
     const int64_t *__restrict__ unit_off, int64_t u_begin, int64_t u_end, int b0,
     const T *__restrict__ utab, double scale, double out_scale, double *__restrict__ phi) {
@@ -322,7 +322,7 @@ mb_status direct_launch_t(const double *x, int64_t n, double scale, double *phi,
         pair_table_kernel<T><<<dim3((unsigned)na, (unsigned)(b1 - b0)), 256, 0, s>>>(
             x, (int)n, na, b0, scale, pair_tab.as<T>());
         const unsigned grid = (unsigned)std::min<int64_t>(u1 - u0, (int64_t)1 << 30);
-        direct_kernel<T><<<grid, kThreads, 0, s>>>(x, (int)n, na, nb, nt, unit_tab.as<int64_t>(),
+        direct_kernel<T><<<grid, DirectLds<T>::TPB, 0, s>>>(x, (int)n, na, nb, nt, unit_tab.as<int64_t>(),
                                                    u0, u1, b0, pair_tab.as<T>(), scale,
                                                    out_scale, phi);
         MB_HIP(hipGetLastError());
@@ -341,25 +341,34 @@ mb_status zero_doubles(double *p, int64_t n, hipStream_t s) {
     return MB_OK;
 }
 
-mb_status validate_points(const double *x, int64_t n, hipStream_t s, ValidateOut *out) {
-    Scratch buf;
-    mb_status st = buf.alloc(sizeof(ValidateOut), s);
-    if (st != MB_OK) return st;
-    ValidateOut *d = buf.as<ValidateOut>();
-    validate_init_kernel<<<1, 1, 0, s>>>(d);
+mb_status validate_enqueue(const double *x, int64_t n, hipStream_t s, ValidateOut *dev,
+                           ValidateOut *out) {
+    validate_init_kernel<<<1, 1, 0, s>>>(dev);
     MB_HIP(hipGetLastError());
     if (n > 0) {
         const int64_t nt = (n + kVT - 1) / kVT;
         if (nt > 65535) return fail(MB_ERR_UNSUPPORTED, "validate: n too large for the tile grid");
-        validate_kernel<<<dim3((unsigned)nt, (unsigned)nt), kVT, 0, s>>>(x, (int)n, d);
+        validate_kernel<<<dim3((unsigned)nt, (unsigned)nt), kVT, 0, s>>>(x, (int)n, dev);
         MB_HIP(hipGetLastError());
     }
-    MB_HIP(hipMemcpyAsync(out, d, sizeof(ValidateOut), hipMemcpyDeviceToHost, s));
-    MB_HIP(hipStreamSynchronize(s));
+    MB_HIP(hipMemcpyAsync(out, dev, sizeof(ValidateOut), hipMemcpyDeviceToHost, s));
+    return MB_OK;
+}
+
+void validate_decode(ValidateOut *out, int64_t n) {
     for (int c = 0; c < 3; ++c) {
         out->lo[c] = n > 0 ? key_to_double(out->lo_key[c]) : 0.0;
         out->hi[c] = n > 0 ? key_to_double(out->hi_key[c]) : 0.0;
     }
+}
+
+mb_status validate_points(const double *x, int64_t n, hipStream_t s, ValidateOut *out) {
+    Scratch buf;
+    mb_status st = buf.alloc(sizeof(ValidateOut), s);
+    if (st != MB_OK) return st;
+    if ((st = validate_enqueue(x, n, s, buf.as<ValidateOut>(), out)) != MB_OK) return st;
+    MB_HIP(hipStreamSynchronize(s));
+    validate_decode(out, n);
     return MB_OK;
 }
 

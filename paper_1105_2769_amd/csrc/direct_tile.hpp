@@ -25,8 +25,10 @@
 // which is 11 VALU operations per triple including the sums
 // Phi_k += qb * sum_i psi (register), Phi_i += qb * psi (register array) and
 // Phi_j += sum over lanes, waves of sum_k qb * sum_i psi (one LDS atomic per
-// lane and j into a per-(j, lane) slot, reduced once per chunk).  Unit sums
-// go to Phi with FP64 atomics.
+// lane and j into a per-(j, lane) slot, reduced once per chunk).  The
+// register partials of Phi_i and Phi_k live in the tile type for one chunk
+// of 16 j and are folded into binary64 after it; unit sums go to Phi with
+// FP64 atomics.
 #pragma once
 
 #include "at_device.hpp"
@@ -34,8 +36,6 @@
 namespace mb {
 namespace {
 
-constexpr int kNW = 8;              // waves per workgroup
-constexpr int kThreads = kNW * 64;
 constexpr int kB = 64;              // points per J block
 constexpr int kKT = 256;            // points per K tile (four per lane)
 constexpr int kKR = kKT / 64;       // k points per lane
@@ -44,14 +44,27 @@ constexpr int kJC = 16;             // j points per LDS chunk
 #define MB_FOLD_J 16                // j steps per binary32 partial of Phi_i
 #endif
 
-// Tile shape per arithmetic type: i points per wave.
+// Tile shape per arithmetic type: i points per wave, waves per workgroup.
 template <typename T> struct DirectShape;
-template <> struct DirectShape<double> { static constexpr int IPW = 4; };
-template <> struct DirectShape<float> { static constexpr int IPW = 8; };
+#ifndef MB_IPW64
+#define MB_IPW64 4
+#endif
+#ifndef MB_NW64
+#define MB_NW64 8
+#endif
+template <> struct DirectShape<double> {
+    static constexpr int IPW = MB_IPW64;
+    static constexpr int NW = MB_NW64;
+};
+template <> struct DirectShape<float> {
+    static constexpr int IPW = 8;
+    static constexpr int NW = 8;
+};
 
 template <typename T>
 struct DirectLds {
-    static constexpr int IB = kNW * DirectShape<T>::IPW;
+    static constexpr int TPB = DirectShape<T>::NW * 64;  // threads per workgroup
+    static constexpr int IB = DirectShape<T>::NW * DirectShape<T>::IPW;
     static constexpr int XS = IB + kB + kKT;
     double xs[3][XS];                              // coordinates of the I, J blocks and K tile
     T cb[kJC][kKT], cq[kJC][kKT], co[kJC][kKT];    // (j, k) terms of the chunk
@@ -156,6 +169,7 @@ __device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__res
                                             double *__restrict__ phi) {
     constexpr int IPW = DirectShape<T>::IPW;
     constexpr int IB = DirectLds<T>::IB;
+    constexpr int TPB = DirectLds<T>::TPB;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -164,14 +178,14 @@ __device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__res
     const TabPtr up = ublk + wave * (IPW * 3);
 
     __syncthreads();  // the previous unit is done with the LDS
-    for (int p = tid; p < DirectLds<T>::XS; p += kThreads) {
+    for (int p = tid; p < DirectLds<T>::XS; p += TPB) {
         const int g = p < XJ ? I0 + p : (p < XK ? J0 + p - XJ : K0 + p - XK);
         const bool ok = g < n;
         s.xs[0][p] = ok ? x[3 * (int64_t)g + 0] * scale : 0.0;
         s.xs[1][p] = ok ? x[3 * (int64_t)g + 1] * scale : 0.0;
         s.xs[2][p] = ok ? x[3 * (int64_t)g + 2] * scale : 0.0;
     }
-    if (tid < kKT) s.kacc[tid] = 0.0;
+    for (int e = tid; e < kKT; e += TPB) s.kacc[e] = 0.0;
     __syncthreads();
 
     // (i, k) pair terms of this wave, in registers for the whole unit
@@ -200,10 +214,15 @@ __device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__res
     double acck[kKR];
 #pragma unroll
     for (int kk = 0; kk < kKR; ++kk) acck[kk] = 0.0;
+    // Phi_k partials of the current chunk in the tile type, folded into acck
+    // (binary64) once per chunk
+    T acck32[kKR];
+#pragma unroll
+    for (int kk = 0; kk < kKR; ++kk) acck32[kk] = T(0);
 
     for (int jc = 0; jc < kB / kJC; ++jc) {
         __syncthreads();  // previous chunk's readers are done
-        for (int e = tid; e < kJC * kKT; e += kThreads) {
+        for (int e = tid; e < kJC * kKT; e += TPB) {
             const int jj = e / kKT, kl = e % kKT;
             const int jl = jc * kJC + jj;
             const int j = J0 + jl, k = K0 + kl;
@@ -215,7 +234,7 @@ __device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__res
             s.cq[jj][kl] = (T)pq;
             s.co[jj][kl] = (T)(0.375 * pia);
         }
-        for (int e = tid; e < kJC * 64; e += kThreads) s.pj[e / 64][e % 64] = 0.0;
+        for (int e = tid; e < kJC * 64; e += TPB) s.pj[e / 64][e % 64] = 0.0;
         __syncthreads();
 
         const TabPtr uc = up + (jc * kJC) * (IB * 3);
@@ -252,14 +271,13 @@ __device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__res
                     acc_i[ii] = fma(o.cq[kk], psi, acc_i[ii]);
                 }
             }
-            double pjv = 0.0;
+            T pj32 = T(0);
 #pragma unroll
             for (int kk = 0; kk < kKR; ++kk) {
-                const double v = (double)(o.cq[kk] * sk[kk]);
-                acck[kk] += v;
-                pjv += v;
+                pj32 = fma(o.cq[kk], sk[kk], pj32);
+                acck32[kk] = fma(o.cq[kk], sk[kk], acck32[kk]);
             }
-            atomicAdd(&s.pj[jj][lane], pjv);
+            atomicAdd(&s.pj[jj][lane], (double)pj32);
         };
         // Two operand sets: everything step jj + 1 reads is loaded while
         // step jj computes, so one wait per step covers loads issued a
@@ -298,10 +316,16 @@ __device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__res
                 acc_i[ii] = T(0);
             }
         }
+#pragma unroll
+        for (int kk = 0; kk < kKR; ++kk) {
+            acck[kk] += (double)acck32[kk];
+            acck32[kk] = T(0);
+        }
         __syncthreads();
-        {
-            // Phi_j of the chunk: 16 rows of 64 slots, 32 threads per row
-            const int row = tid >> 5, c = tid & 31;
+        // Phi_j of the chunk: 16 rows of 64 slots, 32 threads per row
+#pragma unroll
+        for (int r0 = 0; r0 < kJC; r0 += TPB / 32) {
+            const int row = r0 + (tid >> 5), c = tid & 31;
             double v = s.pj[row][c] + s.pj[row][c + 32];
 #pragma unroll
             for (int m = 16; m >= 1; m >>= 1) v += __shfl_xor(v, m);
@@ -318,12 +342,14 @@ __device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__res
 #pragma unroll
     for (int kk = 0; kk < kKR; ++kk) atomicAdd(&s.kacc[lane + 64 * kk], acck[kk]);
     __syncthreads();
-    if (tid < kKT) {
-        const int k = K0 + tid;
-        if (k < n) atomicAdd(&phi[k], s.kacc[tid] * out_scale);
-    } else if (tid < kKT + kB) {
-        const int j = J0 + tid - kKT;
-        if (j < n) atomicAdd(&phi[j], s.pjacc[tid - kKT] * out_scale);
+    for (int e = tid; e < kKT + kB; e += TPB) {
+        if (e < kKT) {
+            const int k = K0 + e;
+            if (k < n) atomicAdd(&phi[k], s.kacc[e] * out_scale);
+        } else {
+            const int j = J0 + e - kKT;
+            if (j < n) atomicAdd(&phi[j], s.pjacc[e - kKT] * out_scale);
+        }
     }
 }
 

@@ -70,6 +70,13 @@ struct ValidateOut {
 // Enqueue validation and wait for it.  n >= 0.
 mb_status validate_points(const double *x, int64_t n, hipStream_t s, ValidateOut *out);
 
+// The same without the wait: the result lands in *out (host) when the stream
+// reaches the copy; dev is device scratch of sizeof(ValidateOut).  Call
+// validate_decode on it afterwards.
+mb_status validate_enqueue(const double *x, int64_t n, hipStream_t s, ValidateOut *dev,
+                           ValidateOut *out);
+void validate_decode(ValidateOut *out, int64_t n);
+
 // Enqueue phi[0:n] = 0.
 mb_status zero_doubles(double *p, int64_t n, hipStream_t s);
 

@@ -7,11 +7,12 @@
 // and run the exhaustive-sum tile code on them.  A request finishes when
 // every one of its units has run; its Phi is then copied back to the host.
 //
-// Up to two slices are queued on the compute stream.  While they run the
-// thread copies back the results of finished requests and stages newly
-// admitted ones on a second stream, so the compute stream sees
-// back-to-back slices.  Every slice ends with a count check: each slot's
-// items run == items issued.
+// Up to two slices are queued on the compute stream.  Staging (copy in,
+// validation, tables) and finishing (binary64 repairs, copy out) of
+// requests run on a second stream and never block the scheduler thread: it
+// enqueues them and polls per-slot events between slices, so the compute
+// stream sees back-to-back slices.  Every slice ends with a count check:
+// each slot's items run == items issued.
 #include "direct_tile.hpp"
 #include "mb_internal.hpp"
 #include "serve_sched.hpp"
@@ -72,7 +73,7 @@ constexpr int kHeaderWords = 16;  // next-item counters (two used), padded to 64
 // the wave re-enter the barrier without the fetching lane, and the item
 // index is then never refreshed.
 template <typename T>
-__global__ __launch_bounds__(kThreads, 1) void serve_kernel(const ServeDesc *__restrict__ desc,
+__global__ __launch_bounds__(DirectLds<T>::TPB, 1) void serve_kernel(const ServeDesc *__restrict__ desc,
                                                             const ServeItem *__restrict__ items,
                                                             int n_items, unsigned *__restrict__ next,
                                                             unsigned *__restrict__ counts) {
@@ -170,8 +171,8 @@ public:
         int cus = 0;
         MB_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_));
         int occ_f = 0, occ_d = 0;
-        MB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_f, serve_kernel<float>, kThreads, 0));
-        MB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_d, serve_kernel<double>, kThreads, 0));
+        MB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_f, serve_kernel<float>, DirectLds<float>::TPB, 0));
+        MB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_d, serve_kernel<double>, DirectLds<double>::TPB, 0));
         grid_f_ = std::max(1, occ_f) * cus;
         grid_d_ = std::max(1, occ_d) * cus;
         sched_.set_slice_units(std::min<int64_t>(8 * (int64_t)grid_f_, kMaxSliceUnits));
@@ -195,6 +196,10 @@ public:
             MB_HIP(hipHostMalloc(&b.h_ring, ring_bytes_, hipHostMallocDefault));
             MB_HIP(hipHostMalloc(&b.h_counts, sizeof(unsigned) * max_slots_, hipHostMallocDefault));
         }
+        MB_HIP(hipHostMalloc(&slot_host_, sizeof(SlotHost) * max_slots_, hipHostMallocDefault));
+        std::memset(slot_host_, 0, sizeof(SlotHost) * max_slots_);
+        slot_ev_.assign(max_slots_, nullptr);
+        for (hipEvent_t &e : slot_ev_) MB_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         thread_ = std::thread([this] { loop(); });
         return MB_OK;
     }
@@ -216,6 +221,13 @@ public:
             if (b.ev_start) (void)hipEventDestroy(b.ev_start);
         }
         if (ev_adm_) (void)hipEventDestroy(ev_adm_);
+        for (hipEvent_t e : slot_ev_)
+            if (e) (void)hipEventDestroy(e);
+        if (slot_host_) {
+            for (int q = 0; q < max_slots_; ++q)
+                if (slot_host_[q].phi) (void)hipHostFree(slot_host_[q].phi);
+            (void)hipHostFree(slot_host_);
+        }
         if (as_) (void)hipStreamDestroy(as_);
         if (own_cs_) (void)hipStreamDestroy(own_cs_);
     }
@@ -358,12 +370,13 @@ private:
         cv_done_.notify_all();
     }
 
-    // Copy points in, validate, choose the tile type and build the (i, j)
-    // table.  Runs on the staging stream while the compute stream is busy.
-    mb_status stage(Request &r, int64_t &units, int64_t &keep, std::string &why) {
+    // Staging, first half: allocate, copy the points in, zero Phi and enqueue
+    // the validation whose result lands in the slot's pinned record.  No wait.
+    mb_status stage_begin(Request &r, int slot) {
         const int64_t n = r.n;
         if (hipMallocAsync(&r.chunk, footprint(n, true), as_) != hipSuccess) {
             r.chunk = nullptr;
+            (void)hipGetLastError();
             return fail(MB_ERR_OOM, "device allocation of " + std::to_string(footprint(n, true)) +
                                         " bytes failed");
         }
@@ -375,16 +388,31 @@ private:
         MB_HIP(hipMemcpyAsync(r.dx, r.x.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, as_));
         mb_status st = zero_doubles(r.dphi, n, as_);
         if (st != MB_OK) return st;
-        ValidateOut v{};
-        st = check_points(r.dx, n, as_, &v);
-        if (st == MB_ERR_DEGENERATE || st == MB_ERR_INVALID) {
-            why = st == MB_ERR_DEGENERATE ? "two points coincide" : "non-finite coordinate";
-            units = 0;
-            return st;
-        }
+        // the magnitude region (>= 256 bytes) holds the device record until the
+        // near-field refinement, enqueued after the record is read, zeroes it
+        st = validate_enqueue(r.dx, n, as_, reinterpret_cast<ValidateOut *>(r.dmag),
+                              &slot_host_[slot].v);
         if (st != MB_OK) return st;
+        MB_HIP(hipEventRecord(slot_ev_[slot], as_));
+        return MB_OK;
+    }
+
+    // Staging, second half (the validation record has landed): choose the tile
+    // type, build the (i, j) table and the binary32 refinement.
+    mb_status stage_end(Request &r, int slot, int64_t &units, int64_t &keep, std::string &why) {
+        const int64_t n = r.n;
+        ValidateOut v = slot_host_[slot].v;
+        validate_decode(&v, n);
         double md2;
         std::memcpy(&md2, &v.min_d2_bits, sizeof md2);
+        if (v.nonfinite) {
+            why = "non-finite coordinate";
+            return MB_ERR_INVALID;
+        }
+        if (!(md2 > 0.0)) {
+            why = "two points coincide";
+            return MB_ERR_DEGENERATE;
+        }
         r.prec = r.prec_req;
         r.scale = 1.0;
         if (r.prec == MB_FP32C) {
@@ -454,10 +482,10 @@ private:
                               hipMemcpyHostToDevice, cs_));
         MB_HIP(hipMemcpyAsync(b.d_ring, b.h_ring, bytes, hipMemcpyHostToDevice, cs_));
         if (nf)
-            serve_kernel<float><<<(unsigned)std::min(nf, grid_f_), kThreads, 0, cs_>>>(
+            serve_kernel<float><<<(unsigned)std::min(nf, grid_f_), DirectLds<float>::TPB, 0, cs_>>>(
                 b.d_desc, d_items(b), nf, d_header(b) + 0, d_counts(b));
         if (nd)
-            serve_kernel<double><<<(unsigned)std::min(nd, grid_d_), kThreads, 0, cs_>>>(
+            serve_kernel<double><<<(unsigned)std::min(nd, grid_d_), DirectLds<double>::TPB, 0, cs_>>>(
                 b.d_desc, d_items(b) + nf, nd, d_header(b) + 1, d_counts(b));
         MB_HIP(hipGetLastError());
         MB_HIP(hipMemcpyAsync(b.h_counts, d_counts(b), sizeof(unsigned) * max_slots_,
@@ -489,24 +517,40 @@ private:
         return MB_OK;
     }
 
-    mb_status finalize(int64_t id) {
-        Request &r = req(id);
-        int32_t flagged = 0;
+    // Finishing, first half: binary64 repairs of a binary32 result, copy of
+    // Phi into the slot's pinned buffer.  No wait.
+    mb_status finish_begin(Request &r, int slot) {
+        SlotHost &h = slot_host_[slot];
+        if (h.phi_cap < r.n) {
+            if (h.phi) (void)hipHostFree(h.phi);
+            h.phi = nullptr;
+            h.phi_cap = 0;
+            MB_HIP(hipHostMalloc(&h.phi, sizeof(double) * (size_t)r.n, hipHostMallocDefault));
+            h.phi_cap = r.n;
+        }
+        h.flagged = 0;
         if (r.prec == MB_FP32C) {
-            const mb_status st = point_fp64_enqueue(r.dx, r.n, r.dmag, r.dphi, as_, &flagged);
+            const mb_status st = point_fp64_enqueue(r.dx, r.n, r.dmag, r.dphi, as_, &h.flagged);
             if (st != MB_OK) return st;
         }
-        r.phi.resize(r.n);
-        MB_HIP(hipMemcpyAsync(r.phi.data(), r.dphi, sizeof(double) * r.n, hipMemcpyDeviceToHost, as_));
-        MB_HIP(hipStreamSynchronize(as_));
+        MB_HIP(hipMemcpyAsync(h.phi, r.dphi, sizeof(double) * r.n, hipMemcpyDeviceToHost, as_));
+        MB_HIP(hipEventRecord(slot_ev_[slot], as_));
+        return MB_OK;
+    }
+
+    // Finishing, second half (the copy has landed).
+    mb_status finish_end(int64_t id, int slot) {
+        Request &r = req(id);
+        SlotHost &h = slot_host_[slot];
+        int64_t flagged = h.flagged;
         if (flagged > point_fix_cap(r.n)) {  // rare: redo the request in binary64
-            const mb_status st = point_fp64_redo_all(r.dx, r.n, r.dphi, as_);
+            mb_status st = point_fp64_redo_all(r.dx, r.n, r.dphi, as_);
             if (st != MB_OK) return st;
-            MB_HIP(hipMemcpyAsync(r.phi.data(), r.dphi, sizeof(double) * r.n, hipMemcpyDeviceToHost,
-                                  as_));
+            MB_HIP(hipMemcpyAsync(h.phi, r.dphi, sizeof(double) * r.n, hipMemcpyDeviceToHost, as_));
             MB_HIP(hipStreamSynchronize(as_));
-            flagged = (int32_t)r.n;
+            flagged = r.n;
         }
+        r.phi.assign(h.phi, h.phi + r.n);
         if (flagged) {
             std::lock_guard<std::mutex> g(mu_);
             stats_.points_fp64 += flagged;
@@ -526,7 +570,7 @@ private:
         complete(r, st, msg);
     }
 
-    mb_status step(std::vector<int64_t> &to_finalize, bool &idle) {
+    mb_status step(std::vector<int64_t> &finished, bool &idle) {
         {
             std::lock_guard<std::mutex> g(mu_);
             if (slice_request_ > 0) {
@@ -536,8 +580,8 @@ private:
             for (int64_t id : inbox_) sched_.enqueue(id, footprint(reqs_.at(id)->n, true));
             inbox_.clear();
         }
-        // 1. keep up to two slices queued on the compute stream
         mb_status st;
+        // 1. keep up to two slices queued on the compute stream
         if (inflight_.size() < 2) {
             serve::Slice sl = sched_.next_slice();
             if (!sl.empty()) {
@@ -545,24 +589,56 @@ private:
                 inflight_.push_back(std::move(sl));
             }
         }
-        // 2. results of the previous slice come back meanwhile
-        const double t_fin = now_s();
-        for (int64_t id : to_finalize)
-            if ((st = finalize(id)) != MB_OK) return st;
-        if (!to_finalize.empty()) {
-            std::lock_guard<std::mutex> g(mu_);
-            stats_.finalize_ms += (now_s() - t_fin) * 1e3;
+        // 2. finished requests: enqueue their repairs and copies
+        const double t0 = now_s();
+        for (int64_t id : finished) {
+            const int slot = sched_.slot_of(id);
+            if ((st = finish_begin(req(id), slot)) != MB_OK) return st;
+            finishing_.push_back(id);
         }
-        to_finalize.clear();
-        // 3. admit and stage new requests on the staging stream
-        bool staged = false;
-        const double t_stage = now_s();
+        finished.clear();
+        // 3. copies that have landed complete their requests
+        for (size_t q = 0; q < finishing_.size();) {
+            const int64_t id = finishing_[q];
+            const int slot = sched_.slot_of(id);
+            const hipError_t e = hipEventQuery(slot_ev_[slot]);
+            if (e == hipErrorNotReady) {
+                ++q;
+                continue;
+            }
+            MB_HIP(e);
+            if ((st = finish_end(id, slot)) != MB_OK) return st;
+            finishing_.erase(finishing_.begin() + (long)q);
+        }
+        const double t1 = now_s();
+        // 4. admit new requests and enqueue their staging
         for (int64_t id : sched_.admit()) {
+            Request &r = req(id);
+            st = stage_begin(r, sched_.slot_of(id));
+            if (st == MB_ERR_OOM) {  // this request only; the server goes on
+                drop(id, st, last_error_cstr());
+                continue;
+            }
+            if (st != MB_OK) return st;
+            validating_.push_back(id);
+        }
+        // 5. validations that have landed: finish staging, then the request runs
+        bool staged = false;
+        for (size_t q = 0; q < validating_.size();) {
+            const int64_t id = validating_[q];
+            const int slot = sched_.slot_of(id);
+            const hipError_t e = hipEventQuery(slot_ev_[slot]);
+            if (e == hipErrorNotReady) {
+                ++q;
+                continue;
+            }
+            MB_HIP(e);
+            validating_.erase(validating_.begin() + (long)q);
             Request &r = req(id);
             int64_t units = 0, keep = 0;
             std::string why;
-            st = stage(r, units, keep, why);
-            if (st == MB_ERR_OOM) {  // this request only; the server goes on
+            st = stage_end(r, slot, units, keep, why);
+            if (st == MB_ERR_OOM) {
                 (void)hipGetLastError();
                 why = last_error_cstr();
             }
@@ -577,18 +653,25 @@ private:
         if (staged) {
             MB_HIP(hipEventRecord(ev_adm_, as_));
             MB_HIP(hipStreamWaitEvent(cs_, ev_adm_, 0));
-            std::lock_guard<std::mutex> g(mu_);
-            stats_.stage_ms += (now_s() - t_stage) * 1e3;
         }
-        // 4. wait for the oldest slice when two are queued or nothing else can
-        // be queued
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            stats_.finalize_ms += (t1 - t0) * 1e3;
+            stats_.stage_ms += (now_s() - t1) * 1e3;
+        }
+        // 6. wait for the oldest slice when two are queued or nothing else can
+        // be queued; with no slice in flight, report whether anything is pending
         idle = false;
         if (!inflight_.empty() && (inflight_.size() == 2 || !sched_.has_runnable())) {
             const serve::Slice &old = inflight_.front();
-            if ((st = finish_slice(old, buf_[old.seq & 1], to_finalize)) != MB_OK) return st;
+            if ((st = finish_slice(old, buf_[old.seq & 1], finished)) != MB_OK) return st;
             inflight_.pop_front();
-        } else if (inflight_.empty()) {
-            idle = to_finalize.empty() && !sched_.has_runnable();
+        } else if (inflight_.empty() && !sched_.has_runnable()) {
+            if (finishing_.empty() && validating_.empty() && finished.empty()) {
+                idle = true;
+            } else {
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+            }
         }
         {
             std::lock_guard<std::mutex> g(mu_);
@@ -603,10 +686,10 @@ private:
             break_all("hipSetDevice failed in the serving thread");
             return;
         }
-        std::vector<int64_t> to_finalize;
+        std::vector<int64_t> finished;
         for (;;) {
             bool idle = false;
-            mb_status st = step(to_finalize, idle);
+            mb_status st = step(finished, idle);
             if (st != MB_OK) {
                 break_all(last_error_cstr());
                 return;
@@ -644,6 +727,17 @@ private:
     hipEvent_t ev_adm_ = nullptr;
     int dev_ = 0, grid_f_ = 1, grid_d_ = 1;
     SliceBuf buf_[2];
+    // per slot: pinned validation record, repair count and result buffer, and
+    // an event marking when the staging or finishing copies have landed
+    struct SlotHost {
+        ValidateOut v;
+        int32_t flagged;
+        double *phi;
+        int64_t phi_cap;
+    };
+    SlotHost *slot_host_ = nullptr;
+    std::vector<hipEvent_t> slot_ev_;
+    std::vector<int64_t> validating_, finishing_;
     std::vector<ServeDesc> desc_table_;   // per slot, host master copy
     std::deque<serve::Slice> inflight_;   // slices queued on the compute stream
     size_t ring_bytes_ = 0;
