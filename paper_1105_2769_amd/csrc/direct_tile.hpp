@@ -214,11 +214,12 @@ __device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__res
     double acck[kKR];
 #pragma unroll
     for (int kk = 0; kk < kKR; ++kk) acck[kk] = 0.0;
-    // Phi_k partials of the current chunk in the tile type, folded into acck
-    // (binary64) once per chunk
-    T acck32[kKR];
+    // binary32 tiles: Phi_k partials of the current chunk, folded into acck
+    // once per chunk (binary64 tiles add into acck directly)
+    constexpr int KR32 = sizeof(T) == 4 ? kKR : 1;
+    T acck32[KR32];
 #pragma unroll
-    for (int kk = 0; kk < kKR; ++kk) acck32[kk] = T(0);
+    for (int kk = 0; kk < KR32; ++kk) acck32[kk] = T(0);
 
     for (int jc = 0; jc < kB / kJC; ++jc) {
         __syncthreads();  // previous chunk's readers are done
@@ -275,7 +276,10 @@ __device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__res
 #pragma unroll
             for (int kk = 0; kk < kKR; ++kk) {
                 pj32 = fma(o.cq[kk], sk[kk], pj32);
-                acck32[kk] = fma(o.cq[kk], sk[kk], acck32[kk]);
+                if constexpr (sizeof(T) == 4)
+                    acck32[kk % KR32] = fma(o.cq[kk], sk[kk], acck32[kk % KR32]);
+                else
+                    acck[kk] = fma((double)o.cq[kk], (double)sk[kk], acck[kk]);
             }
             atomicAdd(&s.pj[jj][lane], (double)pj32);
         };
@@ -316,10 +320,12 @@ __device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__res
                 acc_i[ii] = T(0);
             }
         }
+        if constexpr (sizeof(T) == 4) {
 #pragma unroll
-        for (int kk = 0; kk < kKR; ++kk) {
-            acck[kk] += (double)acck32[kk];
-            acck32[kk] = T(0);
+            for (int kk = 0; kk < kKR; ++kk) {
+                acck[kk] += (double)acck32[kk % KR32];
+                acck32[kk % KR32] = T(0);
+            }
         }
         __syncthreads();
         // Phi_j of the chunk: 16 rows of 64 slots, 32 threads per row
