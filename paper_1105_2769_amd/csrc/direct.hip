@@ -13,7 +13,7 @@ namespace mb {
 namespace {
 
 template <typename T>
-__global__ __launch_bounds__(DirectLds<T>::TPB, 1) void direct_kernel(
+__global__ __launch_bounds__(DirectLds<T>::TPB, DirectShape<T>::MINB) void direct_kernel(
     const double *__restrict__ x, int n, int na, int nb, int nt,
     const int64_t *__restrict__ unit_off, int64_t u_begin, int64_t u_end, int b0,
     const T *__restrict__ utab, double scale, double out_scale, double *__restrict__ phi) {
@@ -21,7 +21,7 @@ __global__ __launch_bounds__(DirectLds<T>::TPB, 1) void direct_kernel(
     __shared__ DirectLds<T> s;
     for (int64_t u = u_begin + blockIdx.x; u < u_end; u += gridDim.x) {
         int a, b, t;
-        decode_unit(u, unit_off, nb, nt, a, b, t);
+        decode_unit(u, unit_off, nb, nt, DirectLds<T>::KR, a, b, t);
         direct_unit<T>(s, x, n, a, b, t, utab + ((int64_t)(b - b0) * na + a) * (IB * kB * 3),
                        scale, out_scale, phi);
     }
@@ -211,13 +211,14 @@ __global__ void scatter_points_kernel(const int32_t *__restrict__ list, const in
     if (f < min(*count, cap)) phi[list[f]] = vals[f];
 }
 
-// Prefix offsets of the unit list, units of J block b: units_a(b) * (nt - b / 4).
-__global__ void unit_offsets_kernel(int nb, int nt, int ib, int na, int64_t *__restrict__ off) {
+// Prefix offsets of the unit list, units of J block b: units_a(b) * (nt - b / kr).
+__global__ void unit_offsets_kernel(int nb, int nt, int kr, int ib, int na,
+                                    int64_t *__restrict__ off) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     int64_t acc = 0;
     off[0] = 0;
     for (int b = 0; b < nb; ++b) {
-        acc += (int64_t)units_a(b, ib, na) * (nt - (b >> 2));
+        acc += (int64_t)units_a(b, ib, na) * (nt - b / kr);
         off[b + 1] = acc;
     }
 }
@@ -297,14 +298,15 @@ mb_status direct_launch_t(const double *x, int64_t n, double scale, double *phi,
     constexpr int IB = DirectLds<T>::IB;
     const int na = (int)((n + IB - 1) / IB);
     const int nb = (int)((n + kB - 1) / kB);
-    const int nt = (int)((n + kKT - 1) / kKT);
+    constexpr int KR = DirectLds<T>::KR, KT = DirectLds<T>::KT;
+    const int nt = (int)((n + KT - 1) / KT);
     std::vector<int64_t> off(nb + 1, 0);
     for (int b = 0; b < nb; ++b)
-        off[b + 1] = off[b] + (int64_t)units_a(b, IB, na) * (nt - (b >> 2));
+        off[b + 1] = off[b] + (int64_t)units_a(b, IB, na) * (nt - b / KR);
     mb_status st;
     Scratch unit_tab;
     if ((st = unit_tab.alloc(sizeof(int64_t) * (nb + 1), s)) != MB_OK) return st;
-    unit_offsets_kernel<<<1, 1, 0, s>>>(nb, nt, IB, na, unit_tab.as<int64_t>());
+    unit_offsets_kernel<<<1, 1, 0, s>>>(nb, nt, KR, IB, na, unit_tab.as<int64_t>());
     MB_HIP(hipGetLastError());
 
     // the (i, j) table is built for a stripe of J blocks at a time

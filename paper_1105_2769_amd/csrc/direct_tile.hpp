@@ -3,14 +3,14 @@
 // kernel and the serving kernel.
 //
 // Work decomposition.  A work unit is a block triple (I, J, K): an I block of
-// 8 * IPW points, a J block of 64 and a K tile of 256.  Units are enumerated
-// so that together they hold every unordered triple i < j < k exactly once;
-// inside a unit the global-index masks i < j < k < n drop the rest.  One
-// 512-thread workgroup (8 wave64s) runs one unit:
+// NW * IPW points, a J block of 64 and a K tile of 64 * KR.  Units are
+// enumerated so that together they hold every unordered triple i < j < k
+// exactly once; inside a unit the global-index masks i < j < k < n drop the
+// rest.  One workgroup of NW wave64s runs one unit:
 //
-//   * lane l owns the four points k = K0 + l + 64 m, m = 0..3;
+//   * lane l owns the KR points k = K0 + l + 64 m, m = 0..KR-1;
 //   * wave w owns IPW points i and keeps the (i, k) pair terms of its
-//     4 * IPW combinations in registers for the whole unit;
+//     KR * IPW combinations in registers for the whole unit;
 //   * the (i, j) pair terms do not depend on the lane.  A table kernel writes
 //     them to HBM per (I, J) block pair, and the triple kernel reads them
 //     with scalar loads into SGPRs, issued one j ahead of their use;
@@ -37,14 +37,13 @@ namespace mb {
 namespace {
 
 constexpr int kB = 64;              // points per J block
-constexpr int kKT = 256;            // points per K tile (four per lane)
-constexpr int kKR = kKT / 64;       // k points per lane
 constexpr int kJC = 16;             // j points per LDS chunk
 #ifndef MB_FOLD_J
 #define MB_FOLD_J 16                // j steps per binary32 partial of Phi_i
 #endif
 
-// Tile shape per arithmetic type: i points per wave, waves per workgroup.
+// Tile shape per arithmetic type: i points per wave, waves per workgroup,
+// k points per lane.
 template <typename T> struct DirectShape;
 #ifndef MB_IPW64
 #define MB_IPW64 4
@@ -52,34 +51,59 @@ template <typename T> struct DirectShape;
 #ifndef MB_NW64
 #define MB_NW64 8
 #endif
+#ifndef MB_KR64
+#define MB_KR64 4
+#endif
+#ifndef MB_IPW32
+#define MB_IPW32 8
+#endif
+#ifndef MB_NW32
+#define MB_NW32 8
+#endif
+#ifndef MB_KR32
+#define MB_KR32 4
+#endif
+#ifndef MB_MINB64
+#define MB_MINB64 1
+#endif
+#ifndef MB_MINB32
+#define MB_MINB32 1
+#endif
 template <> struct DirectShape<double> {
     static constexpr int IPW = MB_IPW64;
     static constexpr int NW = MB_NW64;
+    static constexpr int KR = MB_KR64;
+    static constexpr int MINB = MB_MINB64;  // workgroups per CU the registers must allow
 };
 template <> struct DirectShape<float> {
-    static constexpr int IPW = 8;
-    static constexpr int NW = 8;
+    static constexpr int IPW = MB_IPW32;
+    static constexpr int NW = MB_NW32;
+    static constexpr int KR = MB_KR32;
+    static constexpr int MINB = MB_MINB32;
 };
 
 template <typename T>
 struct DirectLds {
     static constexpr int TPB = DirectShape<T>::NW * 64;  // threads per workgroup
     static constexpr int IB = DirectShape<T>::NW * DirectShape<T>::IPW;
-    static constexpr int XS = IB + kB + kKT;
+    static constexpr int KR = DirectShape<T>::KR;
+    static constexpr int KT = 64 * KR;                   // points per K tile
+    static constexpr int XS = IB + kB + KT;
     double xs[3][XS];                              // coordinates of the I, J blocks and K tile
-    T cb[kJC][kKT], cq[kJC][kKT], co[kJC][kKT];    // (j, k) terms of the chunk
+    T cb[kJC][KT], cq[kJC][KT], co[kJC][KT];       // (j, k) terms of the chunk
     double pj[kJC][64];                            // Phi_j partials per (j, lane), all waves
     double pjacc[kB];                              // Phi_j of the unit
-    double kacc[kKT];                              // Phi_k of the unit
+    double kacc[KT];                               // Phi_k of the unit
 };
 
-// Units of J block b: a in [0, na_b) times t in [b / 4, nt).
+// Units of J block b: a in [0, na_b) times t in [b / kr, nt), where a K tile
+// holds kr J blocks (k > j >= 64 b puts k in tile b / kr or later).
 __host__ __device__ __forceinline__ int units_a(int b, int ib, int na) {
     return min(na, (64 * b + 62) / ib + 1);
 }
 
 __device__ __forceinline__ void decode_unit(int64_t u, const int64_t *__restrict__ off, int nb,
-                                            int nt, int &a, int &b, int &t) {
+                                            int nt, int kr, int &a, int &b, int &t) {
     int lo = 0, hi = nb;
     while (hi - lo > 1) {
         int mid = (lo + hi) >> 1;
@@ -87,9 +111,9 @@ __device__ __forceinline__ void decode_unit(int64_t u, const int64_t *__restrict
     }
     b = lo;
     const int64_t rem = u - off[b];
-    const int tc = nt - (b >> 2);
+    const int tc = nt - b / kr;
     a = (int)(rem / tc);
-    t = (b >> 2) + (int)(rem % tc);
+    t = b / kr + (int)(rem % tc);
 }
 
 // s_waitcnt lgkmcnt(0) (vmcnt and expcnt left at their maxima), with
@@ -170,6 +194,8 @@ __device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__res
     constexpr int IPW = DirectShape<T>::IPW;
     constexpr int IB = DirectLds<T>::IB;
     constexpr int TPB = DirectLds<T>::TPB;
+    constexpr int kKR = DirectLds<T>::KR;
+    constexpr int kKT = DirectLds<T>::KT;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -332,10 +358,14 @@ __device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__res
 #pragma unroll
         for (int r0 = 0; r0 < kJC; r0 += TPB / 32) {
             const int row = r0 + (tid >> 5), c = tid & 31;
-            double v = s.pj[row][c] + s.pj[row][c + 32];
+            // whole 32-lane groups drop out together, so the shuffles stay
+            // inside groups that are all active
+            if (row < kJC) {
+                double v = s.pj[row][c] + s.pj[row][c + 32];
 #pragma unroll
-            for (int m = 16; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-            if (c == 0) s.pjacc[jc * kJC + row] = v;
+                for (int m = 16; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+                if (c == 0) s.pjacc[jc * kJC + row] = v;
+            }
         }
     }
 

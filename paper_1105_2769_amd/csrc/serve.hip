@@ -111,23 +111,25 @@ int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 
 // Unit enumeration of the exhaustive sum for one request and tile type.
 struct UnitMap {
-    int ib = 0, na = 0, nb = 0, nt = 0;
+    int ib = 0, kr = 1, na = 0, nb = 0, nt = 0;
     std::vector<int64_t> off;  // units of J blocks < b
-    void build(int64_t n, int ib_) {
-        ib = ib_;
+    template <typename T>
+    void build(int64_t n) {
+        ib = DirectLds<T>::IB;
+        kr = DirectLds<T>::KR;
         na = (int)((n + ib - 1) / ib);
         nb = (int)((n + kB - 1) / kB);
-        nt = (int)((n + kKT - 1) / kKT);
+        nt = (int)((n + DirectLds<T>::KT - 1) / DirectLds<T>::KT);
         off.assign(nb + 1, 0);
-        for (int b = 0; b < nb; ++b) off[b + 1] = off[b] + (int64_t)units_a(b, ib, na) * (nt - (b >> 2));
+        for (int b = 0; b < nb; ++b) off[b + 1] = off[b] + (int64_t)units_a(b, ib, na) * (nt - b / kr);
     }
     int64_t units() const { return off.empty() ? 0 : off.back(); }
     void decode(int64_t u, int &a, int &b, int &t) const {
         b = (int)(std::upper_bound(off.begin(), off.end(), u) - off.begin()) - 1;
         const int64_t rem = u - off[b];
-        const int tc = nt - (b >> 2);
+        const int tc = nt - b / kr;
         a = (int)(rem / tc);
-        t = (b >> 2) + (int)(rem % tc);
+        t = b / kr + (int)(rem % tc);
     }
 };
 
@@ -427,7 +429,7 @@ private:
         const double s2 = r.scale * r.scale;
         r.out_scale = s2 * s2 * s2 * s2 * r.scale;
         const bool f64 = r.prec == MB_FP64;
-        r.um.build(n, f64 ? DirectLds<double>::IB : DirectLds<float>::IB);
+        if (f64) r.um.build<double>(n); else r.um.build<float>(n);
         dim3 g((unsigned)r.um.na, (unsigned)r.um.nb);
         if (f64)
             pair_table_kernel<double><<<g, 256, 0, as_>>>(r.dx, (int)n, r.um.na, 0, r.scale,
