@@ -44,6 +44,7 @@ namespace {
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTS = 64;    // scale tile and K chunk
 constexpr int kGT = 128;   // output tile of a workgroup
@@ -186,19 +187,65 @@ __global__ __launch_bounds__(256) void gemm_kernel(const H *__restrict__ planes,
 
     const H *pa = planes + (int64_t)ma * P * np * np;
     const H *pb = planes + (int64_t)mb * P * np * np;
-    for (int kc = 0; kc < nt; ++kc) {
-        const int K0 = kc * kTS;
-        __syncthreads();
-        // stage the A rows I0.. and B rows J0.. of this K chunk, all planes
+    // The A rows I0.. and B rows J0.. of a K chunk, all planes: four 16-byte
+    // pieces per thread and operand.  With one or two planes the next chunk's
+    // pieces are loaded into registers while this chunk's products run and
+    // stored to LDS after them; three planes have no registers to spare and
+    // load each chunk before its products.
+    constexpr int kPieces = kGT * (kTS / 8) / 256;
+    static_assert(kPieces * 256 == kGT * (kTS / 8), "whole pieces per thread");
+    constexpr bool kPrefetch = P <= 2;
+    constexpr int PR = kPrefetch ? P : 1;
+    u32x4 nextA[PR][kPieces], nextB[PR][kPieces];
+    // (written out rather than as a lambda: a captured array would be kept in
+    // scratch memory instead of registers)
+    if constexpr (kPrefetch) {
+#pragma unroll
         for (int p = 0; p < P; ++p)
-            for (int e = tid; e < kGT * (kTS / 8); e += 256) {
+#pragma unroll
+            for (int q = 0; q < kPieces; ++q) {
+                const int e = tid + 256 * q;
                 const int row = e / (kTS / 8), c8 = (e % (kTS / 8)) * 8;
-                *(uint4 *)&As[p][row][c8] =
-                    *(const uint4 *)&pa[((int64_t)p * np + I0 + row) * np + K0 + c8];
-                *(uint4 *)&Bs[p][row][c8] =
-                    *(const uint4 *)&pb[((int64_t)p * np + J0 + row) * np + K0 + c8];
+                nextA[p][q] = *(const u32x4 *)&pa[((int64_t)p * np + I0 + row) * np + c8];
+                nextB[p][q] = *(const u32x4 *)&pb[((int64_t)p * np + J0 + row) * np + c8];
+            }
+    }
+    for (int kc = 0; kc < nt; ++kc) {
+        __syncthreads();  // the previous chunk's products are done with the LDS
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int q = 0; q < kPieces; ++q) {
+                const int e = tid + 256 * q;
+                const int row = e / (kTS / 8), c8 = (e % (kTS / 8)) * 8;
+                if constexpr (kPrefetch) {
+                    *(u32x4 *)&As[p][row][c8] = nextA[p][q];
+                    *(u32x4 *)&Bs[p][row][c8] = nextB[p][q];
+                } else {
+                    const int K0 = kc * kTS;
+                    *(u32x4 *)&As[p][row][c8] =
+                        *(const u32x4 *)&pa[((int64_t)p * np + I0 + row) * np + K0 + c8];
+                    *(u32x4 *)&Bs[p][row][c8] =
+                        *(const u32x4 *)&pb[((int64_t)p * np + J0 + row) * np + K0 + c8];
+                }
             }
         __syncthreads();
+        if constexpr (kPrefetch) {
+            if (kc + 1 < nt) {
+                const int K1 = (kc + 1) * kTS;
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+#pragma unroll
+                    for (int q = 0; q < kPieces; ++q) {
+                        const int e = tid + 256 * q;
+                        const int row = e / (kTS / 8), c8 = (e % (kTS / 8)) * 8;
+                        nextA[p][q] =
+                            *(const u32x4 *)&pa[((int64_t)p * np + I0 + row) * np + K1 + c8];
+                        nextB[p][q] =
+                            *(const u32x4 *)&pb[((int64_t)p * np + J0 + row) * np + K1 + c8];
+                    }
+            }
+        }
         floatx16 acc[P][2][2];
 #pragma unroll
         for (int L = 0; L < P; ++L)
