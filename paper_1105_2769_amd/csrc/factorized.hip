@@ -173,7 +173,17 @@ __global__ __launch_bounds__(256) void gemm_kernel(const H *__restrict__ planes,
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr = wave >> 1, wc = wave & 1;
-    const int I0 = blockIdx.y * kGT, J0 = blockIdx.x * kGT;
+    // Grouped launch order: consecutive workgroups take the same column of
+    // tiles in groups of 8 tile rows, so a B strip is fetched from HBM once
+    // per group of rows rather than once per row.  Workgroups are dealt to
+    // the 8 XCDs in turn, so each XCD keeps one A strip in its L2.
+    constexpr int kGroup = 8;
+    const int n_i = gridDim.y, n_j = gridDim.x;
+    const int wg = blockIdx.y * n_j + blockIdx.x;
+    const int g_first = (wg / (kGroup * n_j)) * kGroup;
+    const int g_rows = min(n_i - g_first, kGroup);
+    const int g_local = wg - g_first * n_j;
+    const int I0 = (g_first + g_local % g_rows) * kGT, J0 = (g_local / g_rows) * kGT;
     const int nt = np / kTS;
     const int B = HalfFmt<H>::kBits;
 
