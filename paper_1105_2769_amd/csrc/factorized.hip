@@ -49,6 +49,7 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kTS = 64;    // scale tile and K chunk
 constexpr int kGT = 128;   // output tile of a workgroup
 constexpr int kLdsRow = kTS + 8;  // padded LDS row (halves)
+constexpr int kGemmWaves = 8;     // waves per GEMM workgroup (two per SIMD)
 
 // exponents of the four pair matrices, in storage order
 constexpr int kExp[4] = {-5, 1, -3, -1};
@@ -162,7 +163,7 @@ __device__ __forceinline__ floatx16 mfma<__bf16>(const __bf16 *a, const __bf16 *
 // the fused epilogue: rows of w (.) product into trow, and if tcol is set,
 // columns into tcol, where w = r^we (masked like the matrices).
 template <typename H, int P>
-__global__ __launch_bounds__(256) void gemm_kernel(const H *__restrict__ planes,
+__global__ __launch_bounds__(64 * kGemmWaves) void gemm_kernel(const H *__restrict__ planes,
                                                    const int *__restrict__ texp,
                                                    const double *__restrict__ xs, int n, int np,
                                                    int ma, int mb, int we, double r_near,
@@ -172,7 +173,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(const H *__restrict__ planes,
     __shared__ double xr[3][kGT], xc[3][kGT];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wr = wave >> 1, wc = wave & 1;
+    // waves as a 2 x (kGemmWaves / 2) grid over the 128 x 128 tile: wave
+    // (wr, wc) owns rows 64 wr.. and kWC columns from kWC wc, as 2 x kCB
+    // blocks of 32 x 32
+    constexpr int kThreads = 64 * kGemmWaves;
+    constexpr int kWC = kGT / (kGemmWaves / 2);
+    constexpr int kCB = kWC / 32;
+    const int wr = wave / (kGemmWaves / 2), wc = wave % (kGemmWaves / 2);
     // Grouped launch order: consecutive workgroups take the same column of
     // tiles in groups of 8 tile rows, so a B strip is fetched from HBM once
     // per group of rows rather than once per row.  Workgroups are dealt to
@@ -187,23 +194,23 @@ __global__ __launch_bounds__(256) void gemm_kernel(const H *__restrict__ planes,
     const int nt = np / kTS;
     const int B = HalfFmt<H>::kBits;
 
-    double acc64[2][2][16];
+    double acc64[2][kCB][16];
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb)
+        for (int cb = 0; cb < kCB; ++cb)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc64[rb][cb][r] = 0.0;
 
     const H *pa = planes + (int64_t)ma * P * np * np;
     const H *pb = planes + (int64_t)mb * P * np * np;
-    // The A rows I0.. and B rows J0.. of a K chunk, all planes: four 16-byte
-    // pieces per thread and operand.  With one or two planes the next chunk's
+    // The A rows I0.. and B rows J0.. of a K chunk, all planes: kPieces
+    // 16-byte pieces per thread and operand.  With one or two planes the next chunk's
     // pieces are loaded into registers while this chunk's products run and
     // stored to LDS after them; three planes have no registers to spare and
     // load each chunk before its products.
-    constexpr int kPieces = kGT * (kTS / 8) / 256;
-    static_assert(kPieces * 256 == kGT * (kTS / 8), "whole pieces per thread");
+    constexpr int kPieces = kGT * (kTS / 8) / kThreads;
+    static_assert(kPieces * kThreads == kGT * (kTS / 8), "whole pieces per thread");
     constexpr bool kPrefetch = P <= 2;
     constexpr int PR = kPrefetch ? P : 1;
     u32x4 nextA[PR][kPieces], nextB[PR][kPieces];
@@ -214,7 +221,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const H *__restrict__ planes,
         for (int p = 0; p < P; ++p)
 #pragma unroll
             for (int q = 0; q < kPieces; ++q) {
-                const int e = tid + 256 * q;
+                const int e = tid + kThreads * q;
                 const int row = e / (kTS / 8), c8 = (e % (kTS / 8)) * 8;
                 nextA[p][q] = *(const u32x4 *)&pa[((int64_t)p * np + I0 + row) * np + c8];
                 nextB[p][q] = *(const u32x4 *)&pb[((int64_t)p * np + J0 + row) * np + c8];
@@ -226,7 +233,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const H *__restrict__ planes,
         for (int p = 0; p < P; ++p)
 #pragma unroll
             for (int q = 0; q < kPieces; ++q) {
-                const int e = tid + 256 * q;
+                const int e = tid + kThreads * q;
                 const int row = e / (kTS / 8), c8 = (e % (kTS / 8)) * 8;
                 if constexpr (kPrefetch) {
                     *(u32x4 *)&As[p][row][c8] = nextA[p][q];
@@ -247,7 +254,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const H *__restrict__ planes,
                 for (int p = 0; p < P; ++p)
 #pragma unroll
                     for (int q = 0; q < kPieces; ++q) {
-                        const int e = tid + 256 * q;
+                        const int e = tid + kThreads * q;
                         const int row = e / (kTS / 8), c8 = (e % (kTS / 8)) * 8;
                         nextA[p][q] =
                             *(const u32x4 *)&pa[((int64_t)p * np + I0 + row) * np + K1 + c8];
@@ -256,13 +263,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(const H *__restrict__ planes,
                     }
             }
         }
-        floatx16 acc[P][2][2];
+        floatx16 acc[P][2][kCB];
 #pragma unroll
         for (int L = 0; L < P; ++L)
 #pragma unroll
             for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-                for (int cb = 0; cb < 2; ++cb)
+                for (int cb = 0; cb < kCB; ++cb)
 #pragma unroll
                     for (int r = 0; r < 16; ++r) acc[L][rb][cb][r] = 0.0f;
 #pragma unroll
@@ -275,20 +282,21 @@ __global__ __launch_bounds__(256) void gemm_kernel(const H *__restrict__ planes,
 #pragma unroll
                     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-                        for (int cb = 0; cb < 2; ++cb)
+                        for (int cb = 0; cb < kCB; ++cb)
                             acc[qa + qb][rb][cb] =
                                 mfma<H>(&As[qa][64 * wr + 32 * rb + (lane & 31)][kcol],
-                                        &Bs[qb][64 * wc + 32 * cb + (lane & 31)][kcol],
+                                        &Bs[qb][kWC * wc + 32 * cb + (lane & 31)][kcol],
                                         acc[qa + qb][rb][cb]);
         }
-        // scale of this wave's 64 x 64 block for this chunk, then into FP64
+        // scale of this wave's block (inside one 64 x 64 scale tile) for this
+        // chunk, then into FP64
         const int ex = texp[((int64_t)ma * nt + (I0 / kTS + wr)) * nt + kc] +
-                       texp[((int64_t)mb * nt + (J0 / kTS + wc)) * nt + kc];
+                       texp[((int64_t)mb * nt + (J0 + kWC * wc) / kTS) * nt + kc];
         const double sc = ldexp(1.0, ex);
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-            for (int cb = 0; cb < 2; ++cb)
+            for (int cb = 0; cb < kCB; ++cb)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     float v = acc[P - 1][rb][cb][r];
@@ -302,17 +310,19 @@ __global__ __launch_bounds__(256) void gemm_kernel(const H *__restrict__ planes,
     if (tid < kGT) {
         const int i = I0 + tid;
         for (int c = 0; c < 3; ++c) xr[c][tid] = i < n ? xs[3 * (int64_t)i + c] : 0.0;
-    } else {
+    } else if (tid < 2 * kGT) {
         const int j = J0 + tid - kGT;
         for (int c = 0; c < 3; ++c) xc[c][tid - kGT] = j < n ? xs[3 * (int64_t)j + c] : 0.0;
     }
     __syncthreads();
-    double colsum[2] = {0.0, 0.0};
+    double colsum[kCB];
+#pragma unroll
+    for (int cb = 0; cb < kCB; ++cb) colsum[cb] = 0.0;
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-            const int jl = 64 * wc + 32 * cb + (lane & 31);
+        for (int cb = 0; cb < kCB; ++cb) {
+            const int jl = kWC * wc + 32 * cb + (lane & 31);
             const int j = J0 + jl;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
@@ -333,9 +343,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(const H *__restrict__ planes,
         }
     if (tcol) {
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
+        for (int cb = 0; cb < kCB; ++cb) {
             const double v = colsum[cb] + __shfl_xor(colsum[cb], 32);
-            const int j = J0 + 64 * wc + 32 * cb + (lane & 31);
+            const int j = J0 + kWC * wc + 32 * cb + (lane & 31);
             if (lane < 32 && j < n) atomicAdd(&tcol[j], v);
         }
     }
@@ -472,15 +482,15 @@ mb_status factorized_run(const DeviceTree *tr, int n, double r_near, double *phi
     MB_HIP(hipEventRecord(e1, s));
     const dim3 g(np / kGT, np / kGT);
     // (A matrix, B matrix, weight exponent, row target, column target); storage order -5, +1, -3, -1
-    gemm_kernel<H, P><<<g, 256, 0, s>>>(s_planes.as<H>(), s_exp.as<int>(), tr->xs, n, np, 2, 2, -3,
+    gemm_kernel<H, P><<<g, 64 * kGemmWaves, 0, s>>>(s_planes.as<H>(), s_exp.as<int>(), tr->xs, n, np, 2, 2, -3,
                                         r_near, t + 0 * (int64_t)n, nullptr);
-    gemm_kernel<H, P><<<g, 256, 0, s>>>(s_planes.as<H>(), s_exp.as<int>(), tr->xs, n, np, 0, 0, 1,
+    gemm_kernel<H, P><<<g, 64 * kGemmWaves, 0, s>>>(s_planes.as<H>(), s_exp.as<int>(), tr->xs, n, np, 0, 0, 1,
                                         r_near, t + 1 * (int64_t)n, nullptr);
-    gemm_kernel<H, P><<<g, 256, 0, s>>>(s_planes.as<H>(), s_exp.as<int>(), tr->xs, n, np, 0, 1, -5,
+    gemm_kernel<H, P><<<g, 64 * kGemmWaves, 0, s>>>(s_planes.as<H>(), s_exp.as<int>(), tr->xs, n, np, 0, 1, -5,
                                         r_near, t + 2 * (int64_t)n, nullptr);
-    gemm_kernel<H, P><<<g, 256, 0, s>>>(s_planes.as<H>(), s_exp.as<int>(), tr->xs, n, np, 0, 2, -1,
+    gemm_kernel<H, P><<<g, 64 * kGemmWaves, 0, s>>>(s_planes.as<H>(), s_exp.as<int>(), tr->xs, n, np, 0, 2, -1,
                                         r_near, t + 4 * (int64_t)n, t + 3 * (int64_t)n);
-    gemm_kernel<H, P><<<g, 256, 0, s>>>(s_planes.as<H>(), s_exp.as<int>(), tr->xs, n, np, 0, 3, -3,
+    gemm_kernel<H, P><<<g, 64 * kGemmWaves, 0, s>>>(s_planes.as<H>(), s_exp.as<int>(), tr->xs, n, np, 0, 3, -3,
                                         r_near, t + 5 * (int64_t)n, nullptr);
     MB_HIP(hipGetLastError());
     MB_HIP(hipEventRecord(e2, s));
