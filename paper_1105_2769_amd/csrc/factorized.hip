@@ -202,6 +202,17 @@ __global__ __launch_bounds__(64 * kGemmWaves) void gemm_kernel(const H *__restri
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc64[rb][cb][r] = 0.0;
 
+    // binary32 partial sums over groups of chunks (see the fold below)
+    constexpr int kFoldChunks = 8;
+    float acc32[2][kCB][16];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < kCB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc32[rb][cb][r] = 0.0f;
+    int group = 0, ex_ref = 0;
+
     const H *pa = planes + (int64_t)ma * P * np * np;
     const H *pb = planes + (int64_t)mb * P * np * np;
     // The A rows I0.. and B rows J0.. of a K chunk, all planes: kPieces
@@ -288,11 +299,31 @@ __global__ __launch_bounds__(64 * kGemmWaves) void gemm_kernel(const H *__restri
                                         &Bs[qb][kWC * wc + 32 * cb + (lane & 31)][kcol],
                                         acc[qa + qb][rb][cb]);
         }
-        // scale of this wave's block (inside one 64 x 64 scale tile) for this
-        // chunk, then into FP64
+        // Scale of this wave's block (inside one 64 x 64 scale tile) for this
+        // chunk (wave-uniform).  Chunk sums are added in binary32 relative to
+        // the scale 2^ex_ref of the first chunk of a group; a group ends after
+        // kFoldChunks chunks or when a scale leaves [ex_ref - 24, ex_ref + 24],
+        // and its sum is then added to the binary64 accumulator.  Chunk sums
+        // are non-negative up to the small lower-plane corrections, so a
+        // group adds at most kFoldChunks roundings of 2^-24 relative.
         const int ex = texp[((int64_t)ma * nt + (I0 / kTS + wr)) * nt + kc] +
                        texp[((int64_t)mb * nt + (J0 + kWC * wc) / kTS) * nt + kc];
-        const double sc = ldexp(1.0, ex);
+        if (group == kFoldChunks || ex > ex_ref + 24 || ex < ex_ref - 24) {
+            const double sc = ldexp(1.0, ex_ref);
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < kCB; ++cb)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        acc64[rb][cb][r] = fma((double)acc32[rb][cb][r], sc, acc64[rb][cb][r]);
+                        acc32[rb][cb][r] = 0.0f;
+                    }
+            group = 0;
+        }
+        if (group == 0) ex_ref = ex;
+        ++group;
+        const float rs = ldexpf(1.0f, ex - ex_ref);  // a power of two in [2^-24, 2^24]
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
@@ -302,8 +333,18 @@ __global__ __launch_bounds__(64 * kGemmWaves) void gemm_kernel(const H *__restri
                     float v = acc[P - 1][rb][cb][r];
 #pragma unroll
                     for (int L = P - 2; L >= 0; --L) v = fmaf(v, 1.0f / (float)(1 << B), acc[L][rb][cb][r]);
-                    acc64[rb][cb][r] = fma((double)v, sc, acc64[rb][cb][r]);
+                    acc32[rb][cb][r] = fmaf(v, rs, acc32[rb][cb][r]);
                 }
+    }
+    {
+        const double sc = ldexp(1.0, ex_ref);
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < kCB; ++cb)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    acc64[rb][cb][r] = fma((double)acc32[rb][cb][r], sc, acc64[rb][cb][r]);
     }
     // epilogue: weights from coordinates
     __syncthreads();
