@@ -383,6 +383,8 @@ __device__ McPoint mc_point_wave(const Item &it, char cs, int slot, int64_t off,
     const double *xp = xs + 3 * xr;
     double f0 = 0.0, s1 = 0.0, s2 = 0.0;
     int drawn = 0;
+    // first points of the three nodes, in registers for the whole point
+    const int64_t nb0 = nv.begin[pn[0]], nb1 = nv.begin[pn[1]], nb2 = nv.begin[pn[2]];
     for (int base = 0; base < k.m_limit; base += 64) {
         if (failed && *failed) break;
         const int sidx = base + lane;
@@ -395,8 +397,9 @@ __device__ McPoint mc_point_wave(const Item &it, char cs, int slot, int64_t off,
             int64_t u, v;
             int su, sv;
             sample_partners(cs, slot, off, n1, n2, n3, rr, u, v, su, sv);
-            f = phi3(xp, xs + 3 * ((int64_t)nv.begin[pn[su]] + u),
-                     xs + 3 * ((int64_t)nv.begin[pn[sv]] + v));
+            const int64_t bu = su == 0 ? nb0 : (su == 1 ? nb1 : nb2);
+            const int64_t bv = sv == 0 ? nb0 : (sv == 1 ? nb1 : nb2);
+            f = phi3(xp, xs + 3 * (bu + u), xs + 3 * (bv + v));
         }
         if (base == 0) f0 = __shfl(f, 0);  // shift for numerically stable sums
         const double g = valid ? f - f0 : 0.0;
