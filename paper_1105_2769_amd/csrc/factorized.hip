@@ -180,13 +180,17 @@ __global__ __launch_bounds__(64 * kGemmWaves) void gemm_kernel(const H *__restri
     constexpr int kWC = kGT / (kGemmWaves / 2);
     constexpr int kCB = kWC / 32;
     const int wr = wave / (kGemmWaves / 2), wc = wave % (kGemmWaves / 2);
-    // Grouped launch order: consecutive workgroups take the same column of
-    // tiles in groups of 8 tile rows, so a B strip is fetched from HBM once
-    // per group of rows rather than once per row.  Workgroups are dealt to
-    // the 8 XCDs in turn, so each XCD keeps one A strip in its L2.
-    constexpr int kGroup = 8;
+    // Launch order.  Workgroups are dealt to the 8 XCDs in turn (workgroup w
+    // to XCD w mod 8), and each XCD has its own L2.  When the tile count is
+    // a multiple of 8, XCD x takes the x-th eighth of a grouped order (4 tile
+    // rows per column sweep): the 32 workgroups an XCD runs at once cover 4
+    // rows x 8 columns, so per K chunk its L2 fetches 12 tiles instead of
+    // one per workgroup.  Otherwise the grouped order is used directly.
+    constexpr int kGroup = 4;
     const int n_i = gridDim.y, n_j = gridDim.x;
-    const int wg = blockIdx.y * n_j + blockIdx.x;
+    const int n_wg = n_i * n_j;
+    int wg = blockIdx.y * n_j + blockIdx.x;
+    if (n_wg % 8 == 0) wg = (wg % 8) * (n_wg / 8) + wg / 8;
     const int g_first = (wg / (kGroup * n_j)) * kGroup;
     const int g_rows = min(n_i - g_first, kGroup);
     const int g_local = wg - g_first * n_j;
