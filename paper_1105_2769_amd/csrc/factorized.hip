@@ -169,7 +169,8 @@ __global__ __launch_bounds__(64 * kGemmWaves) void gemm_kernel(const H *__restri
                                                    int ma, int mb, int we, double r_near,
                                                    double *__restrict__ trow,
                                                    double *__restrict__ tcol) {
-    __shared__ H As[P][kGT][kLdsRow], Bs[P][kGT][kLdsRow];
+    constexpr int kBufs = P <= 2 ? 2 : 1;  // LDS buffers (two with register prefetch)
+    __shared__ H As[kBufs][P][kGT][kLdsRow], Bs[kBufs][P][kGT][kLdsRow];
     __shared__ double xr[3][kGT], xc[3][kGT];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -220,10 +221,11 @@ __global__ __launch_bounds__(64 * kGemmWaves) void gemm_kernel(const H *__restri
     const H *pa = planes + (int64_t)ma * P * np * np;
     const H *pb = planes + (int64_t)mb * P * np * np;
     // The A rows I0.. and B rows J0.. of a K chunk, all planes: kPieces
-    // 16-byte pieces per thread and operand.  With one or two planes the next chunk's
-    // pieces are loaded into registers while this chunk's products run and
-    // stored to LDS after them; three planes have no registers to spare and
-    // load each chunk before its products.
+    // 16-byte pieces per thread and operand.  With one or two planes the
+    // next chunk's pieces are loaded into registers while this chunk's
+    // products run and stored to the other LDS buffer after them; three
+    // planes have no registers or LDS to spare and load each chunk into the
+    // one buffer before its products.
     constexpr int kPieces = kGT * (kTS / 8) / kThreads;
     static_assert(kPieces * kThreads == kGT * (kTS / 8), "whole pieces per thread");
     constexpr bool kPrefetch = P <= 2;
@@ -232,51 +234,49 @@ __global__ __launch_bounds__(64 * kGemmWaves) void gemm_kernel(const H *__restri
     // (written out rather than as a lambda: a captured array would be kept in
     // scratch memory instead of registers)
     if constexpr (kPrefetch) {
+        // two LDS buffers: chunk kc is read from buffer kc & 1 while chunk
+        // kc + 1 is stored into the other one, one barrier per chunk
 #pragma unroll
         for (int p = 0; p < P; ++p)
 #pragma unroll
             for (int q = 0; q < kPieces; ++q) {
                 const int e = tid + kThreads * q;
                 const int row = e / (kTS / 8), c8 = (e % (kTS / 8)) * 8;
-                nextA[p][q] = *(const u32x4 *)&pa[((int64_t)p * np + I0 + row) * np + c8];
-                nextB[p][q] = *(const u32x4 *)&pb[((int64_t)p * np + J0 + row) * np + c8];
+                *(u32x4 *)&As[0][p][row][c8] =
+                    *(const u32x4 *)&pa[((int64_t)p * np + I0 + row) * np + c8];
+                *(u32x4 *)&Bs[0][p][row][c8] =
+                    *(const u32x4 *)&pb[((int64_t)p * np + J0 + row) * np + c8];
             }
+        if (nt > 1) {
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+                for (int q = 0; q < kPieces; ++q) {
+                    const int e = tid + kThreads * q;
+                    const int row = e / (kTS / 8), c8 = (e % (kTS / 8)) * 8;
+                    nextA[p][q] = *(const u32x4 *)&pa[((int64_t)p * np + I0 + row) * np + kTS + c8];
+                    nextB[p][q] = *(const u32x4 *)&pb[((int64_t)p * np + J0 + row) * np + kTS + c8];
+                }
+        }
+        __syncthreads();
     }
     for (int kc = 0; kc < nt; ++kc) {
-        __syncthreads();  // the previous chunk's products are done with the LDS
+        const int cur = kPrefetch ? (kc & 1) : 0;
+        if constexpr (!kPrefetch) {
+            __syncthreads();  // the previous chunk's products are done with the LDS
+            const int K0 = kc * kTS;
 #pragma unroll
-        for (int p = 0; p < P; ++p)
+            for (int p = 0; p < P; ++p)
 #pragma unroll
-            for (int q = 0; q < kPieces; ++q) {
-                const int e = tid + kThreads * q;
-                const int row = e / (kTS / 8), c8 = (e % (kTS / 8)) * 8;
-                if constexpr (kPrefetch) {
-                    *(u32x4 *)&As[p][row][c8] = nextA[p][q];
-                    *(u32x4 *)&Bs[p][row][c8] = nextB[p][q];
-                } else {
-                    const int K0 = kc * kTS;
-                    *(u32x4 *)&As[p][row][c8] =
+                for (int q = 0; q < kPieces; ++q) {
+                    const int e = tid + kThreads * q;
+                    const int row = e / (kTS / 8), c8 = (e % (kTS / 8)) * 8;
+                    *(u32x4 *)&As[0][p][row][c8] =
                         *(const u32x4 *)&pa[((int64_t)p * np + I0 + row) * np + K0 + c8];
-                    *(u32x4 *)&Bs[p][row][c8] =
+                    *(u32x4 *)&Bs[0][p][row][c8] =
                         *(const u32x4 *)&pb[((int64_t)p * np + J0 + row) * np + K0 + c8];
                 }
-            }
-        __syncthreads();
-        if constexpr (kPrefetch) {
-            if (kc + 1 < nt) {
-                const int K1 = (kc + 1) * kTS;
-#pragma unroll
-                for (int p = 0; p < P; ++p)
-#pragma unroll
-                    for (int q = 0; q < kPieces; ++q) {
-                        const int e = tid + kThreads * q;
-                        const int row = e / (kTS / 8), c8 = (e % (kTS / 8)) * 8;
-                        nextA[p][q] =
-                            *(const u32x4 *)&pa[((int64_t)p * np + I0 + row) * np + K1 + c8];
-                        nextB[p][q] =
-                            *(const u32x4 *)&pb[((int64_t)p * np + J0 + row) * np + K1 + c8];
-                    }
-            }
+            __syncthreads();
         }
         floatx16 acc[P][2][kCB];
 #pragma unroll
@@ -299,8 +299,8 @@ __global__ __launch_bounds__(64 * kGemmWaves) void gemm_kernel(const H *__restri
 #pragma unroll
                         for (int cb = 0; cb < kCB; ++cb)
                             acc[qa + qb][rb][cb] =
-                                mfma<H>(&As[qa][64 * wr + 32 * rb + (lane & 31)][kcol],
-                                        &Bs[qb][kWC * wc + 32 * cb + (lane & 31)][kcol],
+                                mfma<H>(&As[cur][qa][64 * wr + 32 * rb + (lane & 31)][kcol],
+                                        &Bs[cur][qb][kWC * wc + 32 * cb + (lane & 31)][kcol],
                                         acc[qa + qb][rb][cb]);
         }
         // Scale of this wave's block (inside one 64 x 64 scale tile) for this
@@ -339,6 +339,36 @@ __global__ __launch_bounds__(64 * kGemmWaves) void gemm_kernel(const H *__restri
                     for (int L = P - 2; L >= 0; --L) v = fmaf(v, 1.0f / (float)(1 << B), acc[L][rb][cb][r]);
                     acc32[rb][cb][r] = fmaf(v, rs, acc32[rb][cb][r]);
                 }
+        if constexpr (kPrefetch) {
+            if (kc + 1 < nt) {
+                // chunk kc + 1 into the other buffer (last read in chunk kc - 1,
+                // before the previous barrier), then fetch chunk kc + 2
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+#pragma unroll
+                    for (int q = 0; q < kPieces; ++q) {
+                        const int e = tid + kThreads * q;
+                        const int row = e / (kTS / 8), c8 = (e % (kTS / 8)) * 8;
+                        *(u32x4 *)&As[cur ^ 1][p][row][c8] = nextA[p][q];
+                        *(u32x4 *)&Bs[cur ^ 1][p][row][c8] = nextB[p][q];
+                    }
+                if (kc + 2 < nt) {
+                    const int K2 = (kc + 2) * kTS;
+#pragma unroll
+                    for (int p = 0; p < P; ++p)
+#pragma unroll
+                        for (int q = 0; q < kPieces; ++q) {
+                            const int e = tid + kThreads * q;
+                            const int row = e / (kTS / 8), c8 = (e % (kTS / 8)) * 8;
+                            nextA[p][q] = *(const u32x4 *)&pa[((int64_t)p * np + I0 + row) * np +
+                                                              K2 + c8];
+                            nextB[p][q] = *(const u32x4 *)&pb[((int64_t)p * np + J0 + row) * np +
+                                                              K2 + c8];
+                        }
+                }
+            }
+            __syncthreads();
+        }
     }
     {
         const double sc = ldexp(1.0, ex_ref);
