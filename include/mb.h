@@ -195,7 +195,7 @@ enum { MB_BOUND_SIGNED = 0, MB_BOUND_MAGNITUDE = 1 };
  * sampling pays only where it replaces far more tuples than the paper's
  * small zeta suggests; measured on the 65536-point mixture: 7.2 s at
  * zeta 4, 3.8 s at 128, 4.2 s without Monte Carlo),
- * seed 0, base_prec MB_FP32C, chunk 65536, bound MB_BOUND_SIGNED. */
+ * seed 0, base_prec MB_FP32C, chunk 1048576, bound MB_BOUND_SIGNED. */
 void mb_mt_params_default(mb_mt_params *p);
 
 typedef struct {
@@ -263,7 +263,8 @@ typedef struct {
  *   planes : 1..3 - each matrix entry is held as a sum of `planes` numbers of
  *            the format (a per-64x64-tile power of two keeps all in range);
  *            products of planes are kept while their level is < planes.
- *            Accumulation is binary32 inside 64-wide chunks, binary64 across.
+ *            Accumulation is binary32 inside 64-wide chunks and over groups
+ *            of up to 8 chunks at one reference scale, binary64 across groups.
  *   r_near : >= 0, in the units of x.
  *   stats  : host, nullable.
  * Device memory: 4 * planes * Np^2 * 2 bytes, Np = N rounded up to 128

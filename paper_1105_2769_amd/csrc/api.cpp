@@ -238,7 +238,7 @@ void mb_mt_params_default(mb_mt_params *p) {
     p->zeta = 128.0;
     p->seed = 0;
     p->base_prec = MB_FP32C;
-    p->chunk = 65536;
+    p->chunk = 1 << 20;  // fewer rounds: each round ends in a host wait for the stack size
     p->bound = MB_BOUND_SIGNED;
     p->pad = 0;
 }
