@@ -35,6 +35,9 @@ Extra fields:
   factorized   - the matrix-product form (FP16, two planes, r_near = 1.5)
                  on the N = 16384 lattice (seed 4) against the binary64 GPU
                  sum on all points.
+  paper_workloads - the traversal on the paper's own point sets (uniform
+                 cube, ball, shell; N = 1000..10000) at the settings of its
+                 Tables 1-3 and of its speedup statements.
 """
 from __future__ import annotations
 
@@ -97,6 +100,8 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=4096,
                     help="requests of the serving trace (0: skip the serving leg)")
     ap.add_argument("--no-factorized", action="store_true")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the paper's own workloads (Tables 1-3 settings) on the traversal")
     ap.add_argument("--multitree-n", type=int, default=262144,
                     help="points of the Gaussian-mixture traversal leg (0: skip); 262144 is "
                          "checked against stored oracle values, other sizes against the "
@@ -198,6 +203,7 @@ def main() -> int:
     latency = serve_leg(args.serve_requests, dev) if args.serve_requests else None
     multitree = multitree_leg(args.multitree_n, dev) if args.multitree_n else None
     factorized = None if args.no_factorized else factorized_leg(dev)
+    paper = None if args.no_paper else paper_leg(dev)
 
     def meets(p):
         errs = [v for v in (results[p]["rel"], results[p].get("rel_all")) if v is not None]
@@ -234,6 +240,7 @@ def main() -> int:
         "latency": latency,
         "multitree": multitree,
         "factorized": factorized,
+        "paper_workloads": paper,
         "accuracy": {p: {"max_rel_err_oracle_sampled": results[p]["rel"],
                          "max_rel_err_all_vs_fp64": results[p].get("rel_all"),
                          "frac_particles_above_1e-6": results[p].get("frac_above_1e6")}
@@ -362,6 +369,78 @@ def multitree_leg(n: int, dev) -> dict:
         })
         print(f"multitree: {dt:.1f} s, {comb3(n) / dt:.3e} effective triples/s, within eps "
               f"{out['within_eps_fraction']:.3f}", flush=True)
+    return out
+
+
+def paper_leg(dev) -> dict:
+    """The paper's own workloads (Section 6, Tables 1-3) on the traversal.
+
+    Uniform cube [0,1]^3, unit ball and the shell 0.9 <= r <= 1 (the paper
+    does not give its annulus radii), N = 1000..10000: the fraction of points
+    within relative eps = 1e-3 and the mean / max relative error at
+    alpha = 0.1 (the settings of Tables 1-3), against the binary64 GPU sum;
+    and at N = 10000 the end-to-end time (tree build included) against the
+    binary64 exhaustive GPU sum for eps = 0.1 with alpha = 0 and 0.1 (the
+    settings of the paper's speedup statements).  Both bounds (the paper's
+    signed one and the magnitude one), binary64 base cases, leaf 32.
+    """
+    import numpy as np
+    import torch
+
+    import paper_1105_2769_amd as mb
+    import workloads
+
+    gens = (("uniform", workloads.uniform_cube), ("ball", workloads.unit_ball),
+            ("annulus", workloads.annulus))
+    bounds = ("signed", "magnitude")
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    def run(x, ref, eps, alpha, bound):
+        kw = dict(eps=eps, alpha=alpha, leaf_size=32, base_prec="fp64", bound=bound)
+        (phi, st), dt = timed(lambda: mb.eval_multitree(x, **kw))
+        rel = np.abs(phi.cpu().numpy() - ref) / np.abs(ref)
+        n = x.shape[0]
+        return {"within_pct": 100.0 * float(np.mean(rel <= eps)), "mean_rel_err": float(rel.mean()),
+                "max_rel_err": float(rel.max()), "seconds": dt,
+                "exhaustive_fraction": st["base_triples"] / comb3(n)}
+
+    out = {"workload": "uniform [0,1]^3, unit ball, shell 0.9<=r<=1 (seed = N); leaf 32, "
+                       "binary64 base cases; reference: binary64 GPU sum",
+           "tables": {}, "speedups": {}}
+    for name, gen in gens:
+        rows = []
+        for n in range(1000, 10001, 1000):
+            x = torch.from_numpy(gen(n, n)).to(dev)
+            ref = mb.eval_direct(x, prec="fp64").cpu().numpy()
+            row = {"n": n}
+            for bound in bounds:
+                row[bound] = run(x, ref, 1e-3, 0.1, bound)
+            rows.append(row)
+        out["tables"][name] = rows
+        for bound in bounds:
+            print(f"paper {name} {bound}: within eps % " +
+                  " ".join(f"{r[bound]['within_pct']:.1f}" for r in rows), flush=True)
+        x = torch.from_numpy(gen(10000, 10000)).to(dev)
+        mb.eval_direct(x, prec="fp64")
+        ref, t_direct = timed(lambda: mb.eval_direct(x, prec="fp64"))
+        ref = ref.cpu().numpy()
+        sp = {"direct_fp64_s": t_direct}
+        for bound in bounds:
+            for alpha in (0.0, 0.1):
+                run(x, ref, 0.1, alpha, bound)  # warm
+                r = run(x, ref, 0.1, alpha, bound)
+                r["speedup"] = t_direct / r["seconds"]
+                sp[f"{bound}_alpha_{alpha}"] = r
+                print(f"paper {name} N=10000 eps 0.1 {bound} alpha {alpha}: "
+                      f"{r['seconds'] * 1e3:.1f} ms vs direct {t_direct * 1e3:.1f} ms, exhaustive "
+                      f"{r['exhaustive_fraction']:.3f}, within {r['within_pct']:.1f} %", flush=True)
+        out["speedups"][name] = sp
     return out
 
 

@@ -105,6 +105,27 @@ def test_deterministic_guarantee(cuda):
         assert np.all(cov.cpu().numpy() == (n - 1) * (n - 2) // 2)
 
 
+def test_absolute_and_hybrid_guarantee(cuda):
+    # absolute (eps = 0, tau > 0) and hybrid (both) bounds, deterministic:
+    # every point within eps |Phi| + tau (Definitions 2.1 and 2.3)
+    import paper_1105_2769_amd as mb
+
+    x = clustered(216, CENTERS8, seed=30)
+    n = x.shape[0]
+    idx = workloads.sample_indices(n, 96, seed=31)
+    ref = oracle_direct.phi(x, idx)
+    scale = float(np.abs(ref).max())
+    for eps, tau in ((0.0, 1e-2 * scale), (1e-2, 1e-3 * scale)):
+        print(f"eps={eps} tau={tau:.3e}", flush=True)
+        phi, st, cov = mb.eval_multitree(dev(x, cuda), eps=eps, tau_abs=tau, alpha=0.0,
+                                         leaf_size=16, coverage=True, base_prec="fp64")
+        err = np.abs(phi.cpu().numpy()[idx] - ref)
+        print(st, float((err / (eps * np.abs(ref) + tau)).max()))
+        assert st["det_prunes"] > 0
+        assert np.all(err <= eps * np.abs(ref) + tau)
+        assert np.all(cov.cpu().numpy() == (n - 1) * (n - 2) // 2)
+
+
 def test_monte_carlo_guarantee(cuda):
     import paper_1105_2769_amd as mb
 
