@@ -126,6 +126,27 @@ def test_absolute_and_hybrid_guarantee(cuda):
         assert np.all(cov.cpu().numpy() == (n - 1) * (n - 2) // 2)
 
 
+def test_partial_chunks(cuda):
+    # a round chunk far below the stack size: rounds pop part of the stack,
+    # and the result keeps its guarantee and its exact coverage
+    import paper_1105_2769_amd as mb
+
+    x = clustered(216, CENTERS8, seed=30)
+    n = x.shape[0]
+    idx = workloads.sample_indices(n, 96, seed=31)
+    ref = oracle_direct.phi(x, idx)
+    runs = {}
+    for chunk in (64, 1 << 20):
+        phi, st, cov = mb.eval_multitree(dev(x, cuda), eps=1e-2, alpha=0.0, leaf_size=16,
+                                         coverage=True, base_prec="fp64", chunk=chunk)
+        rel = np.abs(phi.cpu().numpy()[idx] - ref) / np.abs(ref)
+        print(chunk, st, rel.max())
+        assert rel.max() <= 1e-2
+        assert np.all(cov.cpu().numpy() == (n - 1) * (n - 2) // 2)
+        runs[chunk] = st
+    assert runs[64]["rounds"] > runs[1 << 20]["rounds"]
+
+
 def test_monte_carlo_guarantee(cuda):
     import paper_1105_2769_amd as mb
 
