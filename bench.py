@@ -112,8 +112,8 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the path has no multi-GPU implementation "
-              "(see the sharding notes in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the path has no multi-GPU implementation; "
+              "use --gpus 1", file=sys.stderr)
         return 2
 
     import numpy as np

@@ -39,7 +39,7 @@ typedef enum {
     MB_ERR_DEGENERATE = 2,  /* two coincident points: phi is undefined          */
     MB_ERR_OOM = 3,         /* device allocation failed or budget exceeded      */
     MB_ERR_DEVICE = 4,      /* a HIP call failed; see mb_last_error()           */
-    MB_ERR_UNSUPPORTED = 5  /* request outside what this build implements       */
+    MB_ERR_UNSUPPORTED = 5  /* request outside what the library implements      */
 } mb_status;
 
 /* Arithmetic of the exhaustive (direct) sum and of the tree's base cases. */
