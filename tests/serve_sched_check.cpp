@@ -90,7 +90,11 @@ int main(int argc, char **argv) {
         Slice sl = s.next_slice();
         CHECK(sl.units <= s.slice_units());
         int64_t prev_left = -1;
+        std::vector<int64_t> ids_in_slice;
         for (const Range &rg : sl.ranges) {
+            // a request appears at most once per slice
+            for (int64_t other : ids_in_slice) CHECK(other != rg.id);
+            ids_in_slice.push_back(rg.id);
             Rec &r = recs[rg.id];
             CHECK(r.started && !r.finished);
             CHECK(rg.slot == s.slot_of(rg.id));
