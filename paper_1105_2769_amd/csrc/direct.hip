@@ -39,6 +39,9 @@ __global__ __launch_bounds__(DirectLds<T>::TPB, DirectShape<T>::MINB) void direc
 // triples, each taken at most once, so the neighbour cap below only limits
 // how much is refined.
 constexpr int kNearMax = 64;  // forward neighbours kept per point
+constexpr int kPointGroup = 8;     // flagged points per workgroup of point_group_kernel
+constexpr int kPointGroupMin = 4;  // more flagged points than this go to point_group_kernel
+constexpr int kPointKChunk = 2048;  // k points per workgroup of the point-wise kernels
 
 // Forward neighbours v > u with |x_v - x_u| < r_c, in index order, at most
 // kNearMax per point.
@@ -142,18 +145,25 @@ __global__ void flag_kernel(const double *__restrict__ phi, const double *__rest
     }
 }
 
-// Phi of listed points in binary64, one workgroup per (point, tile of 256 j):
-// thread j sums phi(p, j, k) over k > j (k != p), with the (p, k) pair terms
-// staged in LDS per tile of k.
+// Phi of listed points in binary64, one workgroup per (tile of 256 j, point,
+// chunk of kPointKChunk k): thread j sums phi(p, j, k) over the chunk's
+// k > j (k != p), with the (p, k) pair terms staged in LDS per tile of k.
+// The k chunks spread the triangle j < k over many workgroups.
 __global__ __launch_bounds__(256) void point_fp64_kernel(const double *__restrict__ x, int n,
                                                          const int32_t *__restrict__ list,
                                                          const int32_t *__restrict__ count,
                                                          double *__restrict__ out) {
     const int f = blockIdx.y;
-    if (f >= *count) return;  // grid sized for the cap; the list may be shorter
+    // grid sized for the cap; the list may be shorter, and longer lists go to
+    // point_group_kernel
+    if (f >= *count || *count > kPointGroupMin) return;
     const int p = list[f];
     const int j0 = blockIdx.x * 256;
     const int j = j0 + threadIdx.x;
+    // k chunk z of kPointKChunk points; only k > j contribute
+    const int kbeg = max(j0, (int)blockIdx.z * kPointKChunk);
+    const int kend = min(n, ((int)blockIdx.z + 1) * kPointKChunk);
+    if (kbeg >= kend) return;
     __shared__ double xk[3][256], ak[256], qk[256], wk[256];
     const double xp0 = x[3 * (int64_t)p], xp1 = x[3 * (int64_t)p + 1], xp2 = x[3 * (int64_t)p + 2];
     const bool jok = j < n && j != p;
@@ -165,13 +175,13 @@ __global__ __launch_bounds__(256) void point_fp64_kernel(const double *__restric
         pair_terms(xj0 - xp0, xj1 - xp1, xj2 - xp2, true, a1, q1, w1, i1);
     }
     double acc = 0.0;
-    for (int k0 = j0; k0 < n; k0 += 256) {
+    for (int k0 = kbeg; k0 < kend; k0 += 256) {
         __syncthreads();
         {
             const int k = k0 + threadIdx.x;
-            const bool kok = k < n && k != p;
+            const bool kok = k < kend && k != p;
             double d0 = 0.0, d1 = 0.0, d2 = 0.0;
-            if (k < n) {
+            if (k < kend) {
                 d0 = x[3 * (int64_t)k];
                 d1 = x[3 * (int64_t)k + 1];
                 d2 = x[3 * (int64_t)k + 2];
@@ -187,7 +197,7 @@ __global__ __launch_bounds__(256) void point_fp64_kernel(const double *__restric
         }
         __syncthreads();
         if (jok) {
-            const int lim = min(256, n - k0);
+            const int lim = min(256, kend - k0);
             for (int t = 0; t < lim; ++t) {
                 const int k = k0 + t;
                 if (k <= j || qk[t] == 0.0) continue;
@@ -200,6 +210,97 @@ __global__ __launch_bounds__(256) void point_fp64_kernel(const double *__restric
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
     if ((threadIdx.x & 63) == 0) atomicAdd(&out[f], acc);
+}
+
+// The same sums for kPointGroup flagged points at a time, used when more
+// than kPointGroupMin points are flagged: the (j, k) pair terms, which do not
+// depend on the point, are formed once per (j, k) and serve the whole group.
+// Workgroup (x, y, z): j in tile x, points kPointGroup y .. kPointGroup y + 7,
+// k in chunk z.
+__global__ __launch_bounds__(256) void point_group_kernel(const double *__restrict__ x, int n,
+                                                          const int32_t *__restrict__ list,
+                                                          const int32_t *__restrict__ count,
+                                                          double *__restrict__ out) {
+    constexpr int G = kPointGroup;
+    const int cnt = *count;
+    const int f0 = blockIdx.y * G;
+    if (cnt <= kPointGroupMin || f0 >= cnt) return;
+    const int j0 = blockIdx.x * 256;
+    const int j = j0 + threadIdx.x;
+    const int kbeg = max(j0, (int)blockIdx.z * kPointKChunk);
+    const int kend = min(n, ((int)blockIdx.z + 1) * kPointKChunk);
+    if (kbeg >= kend) return;
+    __shared__ double xk[3][256];
+    __shared__ double ak[G][256], qk[G][256], wk[G][256];
+    __shared__ double xp[3][G];
+    __shared__ int pidx[G];
+    if (threadIdx.x < G) {
+        const int f = f0 + threadIdx.x;
+        const int p = f < cnt ? list[f] : -1;  // -1: an empty slot of the group
+        pidx[threadIdx.x] = p;
+        for (int c = 0; c < 3; ++c) xp[c][threadIdx.x] = p >= 0 ? x[3 * (int64_t)p + c] : 0.0;
+    }
+    __syncthreads();
+    double xj0 = 0.0, xj1 = 0.0, xj2 = 0.0;
+    if (j < n) {
+        xj0 = x[3 * (int64_t)j];
+        xj1 = x[3 * (int64_t)j + 1];
+        xj2 = x[3 * (int64_t)j + 2];
+    }
+    // (p, j) terms of the group's points; masked (zero) for j = p, j >= n and
+    // empty slots
+    double a1[G], q1[G], w1[G], acc[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        double i1;
+        pair_terms(xj0 - xp[0][g], xj1 - xp[1][g], xj2 - xp[2][g],
+                   j < n && pidx[g] >= 0 && j != pidx[g], a1[g], q1[g], w1[g], i1);
+        acc[g] = 0.0;
+    }
+    for (int k0 = kbeg; k0 < kend; k0 += 256) {
+        __syncthreads();
+        {
+            const int k = k0 + threadIdx.x;
+            double d0 = 0.0, d1 = 0.0, d2 = 0.0;
+            if (k < kend) {
+                d0 = x[3 * (int64_t)k];
+                d1 = x[3 * (int64_t)k + 1];
+                d2 = x[3 * (int64_t)k + 2];
+            }
+            xk[0][threadIdx.x] = d0;
+            xk[1][threadIdx.x] = d1;
+            xk[2][threadIdx.x] = d2;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                double a, q, w, ia;
+                pair_terms(d0 - xp[0][g], d1 - xp[1][g], d2 - xp[2][g],
+                           k < kend && pidx[g] >= 0 && k != pidx[g], a, q, w, ia);
+                ak[g][threadIdx.x] = a;
+                qk[g][threadIdx.x] = q;
+                wk[g][threadIdx.x] = w;
+            }
+        }
+        __syncthreads();
+        if (j < n) {
+            const int lim = min(256, kend - k0);
+            for (int t = 0; t < lim; ++t) {
+                if (k0 + t <= j) continue;
+                double a3, q3, w3, i3;
+                pair_terms(xk[0][t] - xj0, xk[1][t] - xj1, xk[2][t] - xj2, true, a3, q3, w3, i3);
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    acc[g] += phi_from_pairs<double>(a1[g], q1[g], w1[g], ak[g][t], qk[g][t],
+                                                     wk[g][t], a3, q3, w3);
+            }
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        double v = acc[g];
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+        if ((threadIdx.x & 63) == 0 && f0 + g < cnt) atomicAdd(&out[f0 + g], v);
+    }
 }
 
 __global__ void zero_i32_kernel(int32_t *p) { *p = 0; }
@@ -413,7 +514,12 @@ mb_status point_fp64_enqueue(const double *x, int64_t n, const double *mag, doub
     if ((st = zero_doubles(vals, cap, s)) != MB_OK) return st;
     const unsigned blocks = (unsigned)((n + 255) / 256);
     flag_kernel<<<blocks, 256, 0, s>>>(phi, mag, (int)n, kPointFixRatio, list, count, cap);
-    point_fp64_kernel<<<dim3(blocks, (unsigned)cap), 256, 0, s>>>(x, (int)n, list, count, vals);
+    // one of the two kernels does the work, depending on the device-side count
+    const unsigned kchunks = (unsigned)((n + kPointKChunk - 1) / kPointKChunk);
+    point_fp64_kernel<<<dim3(blocks, (unsigned)cap, kchunks), 256, 0, s>>>(x, (int)n, list, count,
+                                                                          vals);
+    point_group_kernel<<<dim3(blocks, (unsigned)((cap + kPointGroup - 1) / kPointGroup), kchunks),
+                         256, 0, s>>>(x, (int)n, list, count, vals);
     scatter_points_kernel<<<(unsigned)((cap + 255) / 256), 256, 0, s>>>(list, count, cap, vals, phi);
     MB_HIP(hipGetLastError());
     MB_HIP(hipMemcpyAsync(count_host, count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
