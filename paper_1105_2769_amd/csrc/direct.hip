@@ -77,58 +77,66 @@ __global__ __launch_bounds__(256) void near_list_kernel(const double *__restrict
 
 // One thread per point u: every triple u < v < w with v, w in u's list and
 // |x_w - x_v| < r_c (so each triple once, from its smallest index).
+// One wave per point u, lane l the l-th forward neighbour v of u: the lane
+// takes the pairs (v, w) with w a later neighbour in u's list.  (One thread
+// per point ran every pair of the list in sequence, which set the kernel's
+// duration for the small sets of a serving request.)
 __global__ __launch_bounds__(256) void near_fix_kernel(const double *__restrict__ x, int n,
                                                        double scale, double out_scale, double rc2,
                                                        const int32_t *__restrict__ cnt,
                                                        const int32_t *__restrict__ nbr,
                                                        double *__restrict__ phi,
                                                        double *__restrict__ mag) {
-    const int u = blockIdx.x * 256 + threadIdx.x;
-    if (u >= n) return;
+    static_assert(kNearMax == 64, "one lane per neighbour slot");
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int u = (int)(g >> 6), p = (int)(g & 63);
+    if (u >= n) return;  // whole waves: u is uniform in a wave
     const int c = cnt[u];
     const int32_t *list = nbr + (int64_t)u * kNearMax;
     double xu[3];
     for (int d = 0; d < 3; ++d) xu[d] = x[3 * (int64_t)u + d] * scale;
     double acc_u = 0.0, mag_u = 0.0;
-    for (int p = 0; p < c; ++p) {
-        for (int q = p + 1; q < c; ++q) {
-            int v = list[p], w = list[q];
-            if (v > w) {
-                const int t = v;
-                v = w;
-                w = t;
-            }
-            double xv[3], xw[3], r2 = 0.0;
-            for (int d = 0; d < 3; ++d) {
-                const double dv = x[3 * (int64_t)w + d] - x[3 * (int64_t)v + d];
-                r2 = fma(dv, dv, r2);
-                xv[d] = x[3 * (int64_t)v + d] * scale;
-                xw[d] = x[3 * (int64_t)w + d] * scale;
-            }
-            if (r2 >= rc2) continue;
-            // pair terms as the tiles form them: (i, j) = (u, v), (i, k) = (u, w),
-            // (j, k) = (v, w), each from the difference of scaled coordinates
-            double a1, q1, w1, i1, a2, q2, w2, i2, a3, q3, w3, i3;
-            pair_terms(xv[0] - xu[0], xv[1] - xu[1], xv[2] - xu[2], true, a1, q1, w1, i1);
-            pair_terms(xw[0] - xu[0], xw[1] - xu[1], xw[2] - xu[2], true, a2, q2, w2, i2);
-            pair_terms(xw[0] - xv[0], xw[1] - xv[1], xw[2] - xv[2], true, a3, q3, w3, i3);
-            const double f64 = phi_from_pairs<double>(a1, q1, w1, a2, q2, w2, a3, q3, w3);
-            const float cb = (float)a3;
-            const float psi = tile_psi<float>((float)a1, (float)q1, (float)w1, (float)a2, (float)q2,
-                                              (float)w2, cb, cb * cb, (float)(0.375 * i3));
-            const double f32 = (double)(float)q3 * (double)psi;
-            const double dlt = (f64 - f32) * out_scale;
-            const double m = fabs(f64) * out_scale;
-            acc_u += dlt;
-            mag_u += m;
-            atomicAdd(&phi[v], dlt);
-            atomicAdd(&phi[w], dlt);
-            atomicAdd(&mag[v], m);
-            atomicAdd(&mag[w], m);
+    for (int q = p + 1; q < c; ++q) {
+        int v = list[p], w = list[q];
+        if (v > w) {
+            const int tmp = v;
+            v = w;
+            w = tmp;
         }
+        double xv[3], xw[3], r2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            const double dv = x[3 * (int64_t)w + d] - x[3 * (int64_t)v + d];
+            r2 = fma(dv, dv, r2);
+            xv[d] = x[3 * (int64_t)v + d] * scale;
+            xw[d] = x[3 * (int64_t)w + d] * scale;
+        }
+        if (r2 >= rc2) continue;
+        // pair terms as the tiles form them: (i, j) = (u, v), (i, k) = (u, w),
+        // (j, k) = (v, w), each from the difference of scaled coordinates
+        double a1, q1, w1, i1, a2, q2, w2, i2, a3, q3, w3, i3;
+        pair_terms(xv[0] - xu[0], xv[1] - xu[1], xv[2] - xu[2], true, a1, q1, w1, i1);
+        pair_terms(xw[0] - xu[0], xw[1] - xu[1], xw[2] - xu[2], true, a2, q2, w2, i2);
+        pair_terms(xw[0] - xv[0], xw[1] - xv[1], xw[2] - xv[2], true, a3, q3, w3, i3);
+        const double f64 = phi_from_pairs<double>(a1, q1, w1, a2, q2, w2, a3, q3, w3);
+        const float cb = (float)a3;
+        const float psi = tile_psi<float>((float)a1, (float)q1, (float)w1, (float)a2, (float)q2,
+                                          (float)w2, cb, cb * cb, (float)(0.375 * i3));
+        const double f32 = (double)(float)q3 * (double)psi;
+        const double dlt = (f64 - f32) * out_scale;
+        const double m = fabs(f64) * out_scale;
+        acc_u += dlt;
+        mag_u += m;
+        atomicAdd(&phi[v], dlt);
+        atomicAdd(&phi[w], dlt);
+        atomicAdd(&mag[v], m);
+        atomicAdd(&mag[w], m);
     }
-    atomicAdd(&phi[u], acc_u);
-    atomicAdd(&mag[u], mag_u);
+    acc_u = wave_sum(acc_u);
+    mag_u = wave_sum(mag_u);
+    if (p == 0) {
+        atomicAdd(&phi[u], acc_u);
+        atomicAdd(&mag[u], mag_u);
+    }
 }
 
 // Points whose binary32 result may miss the relative bar: |Phi| small next
@@ -489,7 +497,8 @@ mb_status near_refine_launch(const double *x, int64_t n, double scale, double r_
     const double out_scale = s2 * s2 * s2 * s2 * scale;
     if ((st = zero_doubles(mag, n, s)) != MB_OK) return st;
     near_list_kernel<<<blocks, 256, 0, s>>>(x, (int)n, rc2, cnt, nbr);
-    near_fix_kernel<<<blocks, 256, 0, s>>>(x, (int)n, scale, out_scale, rc2, cnt, nbr, phi, mag);
+    near_fix_kernel<<<(unsigned)((n * (int64_t)kNearMax + 255) / 256), 256, 0, s>>>(
+        x, (int)n, scale, out_scale, rc2, cnt, nbr, phi, mag);
     MB_HIP(hipGetLastError());
     return MB_OK;
 }
