@@ -45,39 +45,37 @@ constexpr int kPointKChunk = 2048;  // k points per workgroup of the point-wise 
 
 // Forward neighbours v > u with |x_v - x_u| < r_c, in index order, at most
 // kNearMax per point.
+// One wave per point u: the lanes test 64 consecutive candidates v at a
+// time, in index order, and a ballot appends the hits in that order.
 __global__ __launch_bounds__(256) void near_list_kernel(const double *__restrict__ x, int n,
                                                         double rc2, int32_t *__restrict__ cnt,
                                                         int32_t *__restrict__ nbr) {
-    __shared__ double xv[3][256];
-    const int u = blockIdx.x * 256 + threadIdx.x;
-    double x0 = 0.0, x1 = 0.0, x2 = 0.0;
-    if (u < n) {
-        x0 = x[3 * (int64_t)u];
-        x1 = x[3 * (int64_t)u + 1];
-        x2 = x[3 * (int64_t)u + 2];
-    }
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int u = (int)(g >> 6), lane = (int)(g & 63);
+    if (u >= n) return;  // whole waves: u is uniform in a wave
+    const double x0 = x[3 * (int64_t)u], x1 = x[3 * (int64_t)u + 1], x2 = x[3 * (int64_t)u + 2];
     int c = 0;
-    for (int v0 = blockIdx.x * 256; v0 < n; v0 += 256) {
-        __syncthreads();
-        const int v = v0 + threadIdx.x;
-        for (int d = 0; d < 3; ++d) xv[d][threadIdx.x] = v < n ? x[3 * (int64_t)v + d] : 0.0;
-        __syncthreads();
-        if (u < n) {
-            const int lim = min(256, n - v0);
-            for (int q = 0; q < lim; ++q) {
-                const int vv = v0 + q;
-                if (vv <= u || c >= kNearMax) continue;
-                const double dx = xv[0][q] - x0, dy = xv[1][q] - x1, dz = xv[2][q] - x2;
-                if (fma(dx, dx, fma(dy, dy, dz * dz)) < rc2) nbr[(int64_t)u * kNearMax + c++] = vv;
-            }
+    for (int v0 = u + 1; v0 < n && c < kNearMax; v0 += 64) {
+        const int v = v0 + lane;
+        bool hit = false;
+        if (v < n) {
+            const double dx = x[3 * (int64_t)v] - x0, dy = x[3 * (int64_t)v + 1] - x1,
+                         dz = x[3 * (int64_t)v + 2] - x2;
+            hit = fma(dx, dx, fma(dy, dy, dz * dz)) < rc2;
         }
+        const unsigned long long mask = __ballot(hit);
+        if (hit) {
+            const int pos = c + __popcll(mask & ((1ull << lane) - 1ull));
+            if (pos < kNearMax) nbr[(int64_t)u * kNearMax + pos] = v;
+        }
+        c += __popcll(mask);
     }
-    if (u < n) cnt[u] = c;
+    if (lane == 0) cnt[u] = min(c, kNearMax);
 }
 
-// One thread per point u: every triple u < v < w with v, w in u's list and
-// |x_w - x_v| < r_c (so each triple once, from its smallest index).
-// One wave per point u, lane l the l-th forward neighbour v of u: the lane
+// Every triple u < v < w with v, w in u's list and |x_w - x_v| < r_c (so each
+// triple once, from its smallest index).  One wave per point u, lane l the
+// l-th forward neighbour v of u: the lane
 // takes the pairs (v, w) with w a later neighbour in u's list.  (One thread
 // per point ran every pair of the list in sequence, which set the kernel's
 // duration for the small sets of a serving request.)
@@ -491,14 +489,14 @@ mb_status near_refine_launch(const double *x, int64_t n, double scale, double r_
     if (st != MB_OK) return st;
     int32_t *cnt = lists.as<int32_t>();
     int32_t *nbr = cnt + n;
-    const unsigned blocks = (unsigned)((n + 255) / 256);
+    const unsigned wave_blocks = (unsigned)((n * (int64_t)kNearMax + 255) / 256);  // a wave per point
     const double rc2 = r_fix * r_fix;
     const double s2 = scale * scale;
     const double out_scale = s2 * s2 * s2 * s2 * scale;
     if ((st = zero_doubles(mag, n, s)) != MB_OK) return st;
-    near_list_kernel<<<blocks, 256, 0, s>>>(x, (int)n, rc2, cnt, nbr);
-    near_fix_kernel<<<(unsigned)((n * (int64_t)kNearMax + 255) / 256), 256, 0, s>>>(
-        x, (int)n, scale, out_scale, rc2, cnt, nbr, phi, mag);
+    near_list_kernel<<<wave_blocks, 256, 0, s>>>(x, (int)n, rc2, cnt, nbr);
+    near_fix_kernel<<<wave_blocks, 256, 0, s>>>(x, (int)n, scale, out_scale, rc2, cnt, nbr, phi,
+                                                 mag);
     MB_HIP(hipGetLastError());
     return MB_OK;
 }
