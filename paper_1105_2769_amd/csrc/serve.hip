@@ -661,13 +661,22 @@ private:
             stats_.finalize_ms += (t1 - t0) * 1e3;
             stats_.stage_ms += (now_s() - t1) * 1e3;
         }
-        // 6. wait for the oldest slice when two are queued or nothing else can
-        // be queued; with no slice in flight, report whether anything is pending
+        // 6. collect the oldest slice when two are queued or nothing else can
+        // be queued, once its end event has passed (polled, so that arrivals
+        // keep being staged meanwhile); with no slice in flight, report
+        // whether anything is pending
         idle = false;
         if (!inflight_.empty() && (inflight_.size() == 2 || !sched_.has_runnable())) {
             const serve::Slice &old = inflight_.front();
-            if ((st = finish_slice(old, buf_[old.seq & 1], finished)) != MB_OK) return st;
-            inflight_.pop_front();
+            const hipError_t q = hipEventQuery(buf_[old.seq & 1].ev_end);
+            if (q == hipSuccess) {
+                if ((st = finish_slice(old, buf_[old.seq & 1], finished)) != MB_OK) return st;
+                inflight_.pop_front();
+            } else if (q == hipErrorNotReady) {
+                std::this_thread::sleep_for(std::chrono::microseconds(10));
+            } else {
+                return fail(MB_ERR_DEVICE, std::string("hipEventQuery: ") + hipGetErrorString(q));
+            }
         } else if (inflight_.empty() && !sched_.has_runnable()) {
             if (finishing_.empty() && validating_.empty() && finished.empty()) {
                 idle = true;
