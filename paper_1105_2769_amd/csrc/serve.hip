@@ -140,10 +140,15 @@ int64_t table_bytes(int64_t n, bool f64) {
 }
 
 // Device bytes a request holds while admitted: points, Phi, the near-field
-// magnitudes of the binary32 refinement and the (i, j) table, for binary64
-// tiles when binary64 may be needed.
+// magnitudes of the binary32 refinement and the (i, j) table.  When binary64
+// may be needed the table region holds either tile type's table (the
+// binary32 table is the smaller one for the default shapes, but not for
+// every shape: an I block wider than twice the binary64 one outgrows it for
+// small N).
 int64_t footprint(int64_t n, bool f64) {
-    return align256(24 * n) + 2 * align256(8 * n) + align256(table_bytes(n, f64));
+    const int64_t tab = f64 ? std::max(table_bytes(n, true), table_bytes(n, false))
+                            : table_bytes(n, false);
+    return align256(24 * n) + 2 * align256(8 * n) + align256(tab);
 }
 
 struct Request {
