@@ -287,9 +287,10 @@ double mb_normal_quantile(double alpha_half);
  * point sets of different N as they arrive:
  *   - admission: requests are admitted in arrival order while a slot is free
  *     and their device footprint fits the HBM budget; the footprint of a
- *     request of N points is 24 N + 8 N bytes plus its (i, j) pair-term
- *     table (about 3 N^2 binary32 or binary64 numbers, each rounded up to
- *     256 B; binary64 is reserved until validation shows it is not needed);
+ *     request of N points is 24 N + 16 N bytes (points, Phi, near-field
+ *     magnitudes) plus its (i, j) pair-term table (about 3 N^2 binary32 or
+ *     binary64 numbers), each part rounded up to 256 B; room for either
+ *     table is reserved until validation shows binary64 is not needed;
  *   - continuous batching: the work units (block triples) of all admitted
  *     requests are drained together by a kernel whose resident workgroups
  *     pop (request, unit) items, in slices of a bounded number of units;
