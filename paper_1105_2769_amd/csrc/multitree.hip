@@ -351,7 +351,6 @@ __device__ __forceinline__ void sample_partners(char cs, int slot, int64_t xl, i
 }
 
 constexpr int kMcThreads = 256;
-constexpr int kMcWaves = kMcThreads / 64;
 constexpr int kMcCache = 2048;  // points whose (mu, lower bound) stay in LDS between passes
 
 struct McPoint {
@@ -360,34 +359,43 @@ struct McPoint {
     int drawn;
 };
 
-__device__ __forceinline__ double wave_incl_scan(double v, int lane) {
+// Inclusive prefix sum over each aligned group of W lanes (gl: lane in group).
+template <int W>
+__device__ __forceinline__ double group_incl_scan(double v, int gl) {
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const double u = __shfl_up(v, d);
-        if (lane >= d) v += u;
+    for (int d = 1; d < W; d <<= 1) {
+        const double u = __shfl_up(v, d, W);
+        if (gl >= d) v += u;
     }
     return v;
 }
 
-// Algorithm 4 for one point, by one wave: samples are drawn 64 at a time
-// (sample s by lane s mod 64); prefix sums give the running mean and
+// Algorithm 4 for one point, by a group of kMcGroup lanes of a wave (two
+// points per wave): samples are drawn kMcGroup at a time (sample s by lane
+// s mod kMcGroup of the group); prefix sums give the running mean and
 // unbiased variance after every sample, and the first sample count m at
 // which the sequential loop would stop - the termination rule holding with
-// m >= m_min, or m = m_limit - is found with a ballot.  Every lane returns
-// the same result.  `failed` (nullable) aborts between batches.
-__device__ McPoint mc_point_wave(const Item &it, char cs, int slot, int64_t off, int64_t xr,
-                                 int64_t n1, int64_t n2, int64_t n3, const int *pn,
-                                 const NodeView &nv, const double *__restrict__ xs, double t,
-                                 double plo, const MtConst &k, const volatile int *failed,
-                                 int lane) {
+// m >= m_min, or m = m_limit - is found with a ballot.  The decision depends
+// only on the sample sequence, not on the group width; the width sets how
+// many samples past the stop are drawn (a point that stops at m_min = 30
+// draws 32).  Every lane of the group returns the same result.  `failed`
+// (nullable) aborts between batches.  gl: lane in the group, g0: the
+// group's first lane in the wave.
+constexpr int kMcGroup = 32;
+__device__ McPoint mc_point_group(const Item &it, char cs, int slot, int64_t off, int64_t xr,
+                                  int64_t n1, int64_t n2, int64_t n3, const int *pn,
+                                  const NodeView &nv, const double *__restrict__ xs, double t,
+                                  double plo, const MtConst &k, const volatile int *failed,
+                                  int gl, int g0) {
+    constexpr int W = kMcGroup;
     const double *xp = xs + 3 * xr;
     double f0 = 0.0, s1 = 0.0, s2 = 0.0;
     int drawn = 0;
     // first points of the three nodes, in registers for the whole point
     const int64_t nb0 = nv.begin[pn[0]], nb1 = nv.begin[pn[1]], nb2 = nv.begin[pn[2]];
-    for (int base = 0; base < k.m_limit; base += 64) {
+    for (int base = 0; base < k.m_limit; base += W) {
         if (failed && *failed) break;
-        const int sidx = base + lane;
+        const int sidx = base + gl;
         const bool valid = sidx < k.m_limit;
         double f = 0.0;
         if (valid) {
@@ -401,9 +409,9 @@ __device__ McPoint mc_point_wave(const Item &it, char cs, int slot, int64_t off,
             const int64_t bv = sv == 0 ? nb0 : (sv == 1 ? nb1 : nb2);
             f = phi3(xp, xs + 3 * (bu + u), xs + 3 * (bv + v));
         }
-        if (base == 0) f0 = __shfl(f, 0);  // shift for numerically stable sums
+        if (base == 0) f0 = __shfl(f, g0);  // shift for numerically stable sums
         const double g = valid ? f - f0 : 0.0;
-        const double p1 = wave_incl_scan(g, lane), p2 = wave_incl_scan(g * g, lane);
+        const double p1 = group_incl_scan<W>(g, gl), p2 = group_incl_scan<W>(g * g, gl);
         const double t1 = s1 + p1, t2 = s2 + p2;
         const double m = (double)(sidx + 1);
         const double mean = f0 + t1 / m;
@@ -413,10 +421,11 @@ __device__ McPoint mc_point_wave(const Item &it, char cs, int slot, int64_t off,
         const bool cond = valid && sidx >= 1 && k.z * sig <= (k.eps * credit + k.tau) / k.t_root;
         const bool ok = cond && sidx + 1 >= k.m_min;
         const bool stop = valid && (ok || sidx + 1 == k.m_limit);
-        const unsigned long long bal = __ballot(stop);
-        drawn = min(base + 64, k.m_limit);
+        // this group's bits of the wave's ballot
+        const unsigned long long bal = (__ballot(stop) >> g0) & ((1ull << W) - 1ull);
+        drawn = min(base + W, k.m_limit);
         if (bal) {
-            const int L = __ffsll((long long)bal) - 1;
+            const int L = g0 + __ffsll((long long)bal) - 1;
             McPoint r;
             r.pass = __shfl((int)ok, L) != 0;
             r.mean = __shfl(mean, L);
@@ -424,8 +433,8 @@ __device__ McPoint mc_point_wave(const Item &it, char cs, int slot, int64_t off,
             r.drawn = drawn;
             return r;
         }
-        s1 += __shfl(p1, 63);
-        s2 += __shfl(p2, 63);
+        s1 += __shfl(p1, g0 + W - 1);
+        s2 += __shfl(p2, g0 + W - 1);
     }
     McPoint r;
     r.pass = false;
@@ -446,7 +455,10 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
     __shared__ int failed;
     __shared__ double c_mean[kMcCache], c_low[kMcCache];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    // groups of kMcGroup lanes, each sampling its own points
+    constexpr int kGroups = kMcThreads / kMcGroup;
+    const int grp = threadIdx.x / kMcGroup;
+    const int gl = lane % kMcGroup, g0 = lane - gl;
     const unsigned long long n_mc = ctr->n_mc;
     for (unsigned long long w = blockIdx.x; w < n_mc; w += gridDim.x) {
         const Item it = mc_list[w];
@@ -464,26 +476,26 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
         if (threadIdx.x == 0) failed = 0;
         __syncthreads();
         unsigned long long drawn = 0;
-        for (int64_t e = wave; e < total; e += kMcWaves) {
+        for (int64_t e = grp; e < total; e += kGroups) {
             if (failed) break;
             int q = 0;
             int64_t off = e;
             while (off >= sz[q]) off -= sz[q++];
             const int64_t xr = nv.begin[r.node[q]] + off;
-            const McPoint res = mc_point_wave(it, cs, r.slot[q], off, xr, n1, n2, n3, pn, nv, xs,
-                                              (double)r.t[q], node_phil[r.node[q]], k, &failed,
-                                              lane);
+            const McPoint res = mc_point_group(it, cs, r.slot[q], off, xr, n1, n2, n3, pn, nv, xs,
+                                               (double)r.t[q], node_phil[r.node[q]], k, &failed,
+                                               gl, g0);
             drawn += res.drawn;
             if (!res.pass) {
-                if (lane == 0) failed = 1;
+                if (gl == 0) failed = 1;
                 break;
             }
-            if (e < kMcCache && lane == 0) {
+            if (e < kMcCache && gl == 0) {
                 c_mean[e] = res.mean;
                 c_low[e] = res.mean - k.z * res.sig;
             }
         }
-        if (lane == 0) atomicAdd(&ctr->mc_samples, drawn);
+        if (gl == 0) atomicAdd(&ctr->mc_samples, drawn);
         __syncthreads();
         if (failed) {
             if (threadIdx.x == 0) {
@@ -495,7 +507,7 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
             }
             continue;
         }
-        for (int64_t e = wave; e < total; e += kMcWaves) {
+        for (int64_t e = grp; e < total; e += kGroups) {
             int q = 0;
             int64_t off = e;
             while (off >= sz[q]) off -= sz[q++];
@@ -506,12 +518,12 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
                 mean = c_mean[e];
                 low = c_low[e];
             } else {
-                const McPoint res = mc_point_wave(it, cs, r.slot[q], off, xr, n1, n2, n3, pn, nv, xs,
-                                                  t, node_phil[r.node[q]], k, nullptr, lane);
+                const McPoint res = mc_point_group(it, cs, r.slot[q], off, xr, n1, n2, n3, pn, nv,
+                                                   xs, t, node_phil[r.node[q]], k, nullptr, gl, g0);
                 mean = res.mean;
                 low = res.mean - k.z * res.sig;
             }
-            if (lane == 0) {
+            if (gl == 0) {
                 atomicAdd(&est[xr], t * mean);
                 atomicAdd(&lb[xr], t * low);
             }
