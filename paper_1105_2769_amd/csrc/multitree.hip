@@ -460,6 +460,8 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
     const int grp = threadIdx.x / kMcGroup;
     const int gl = lane % kMcGroup, g0 = lane - gl;
     const unsigned long long n_mc = ctr->n_mc;
+    // counters, summed over this workgroup's triples and added once at the end
+    unsigned long long drawn = 0, my_failed = 0, my_prunes = 0;
     for (unsigned long long w = blockIdx.x; w < n_mc; w += gridDim.x) {
         const Item it = mc_list[w];
         const int pn[3] = {it.p1, it.p2, it.p3};
@@ -475,7 +477,6 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
         __syncthreads();
         if (threadIdx.x == 0) failed = 0;
         __syncthreads();
-        unsigned long long drawn = 0;
         for (int64_t e = grp; e < total; e += kGroups) {
             if (failed) break;
             int q = 0;
@@ -495,11 +496,10 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
                 c_low[e] = res.mean - k.z * res.sig;
             }
         }
-        if (gl == 0) atomicAdd(&ctr->mc_samples, drawn);
         __syncthreads();
         if (failed) {
             if (threadIdx.x == 0) {
-                atomicAdd(&ctr->mc_failed, 1ull);
+                ++my_failed;
                 if (nv.left[it.p1] < 0 && nv.left[it.p2] < 0 && nv.left[it.p3] < 0)
                     base_list[atomicAdd(&ctr->n_base, 1ull)] = it;
                 else
@@ -529,11 +529,16 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
             }
         }
         if (threadIdx.x == 0) {
-            atomicAdd(&ctr->mc_prunes, 1ull);
+            ++my_prunes;
             if (k.want_cov)
                 for (int q = 0; q < r.n_roles; ++q)
                     atomicAdd(&node_cov[r.node[q]], (unsigned long long)r.t[q]);
         }
+    }
+    if (gl == 0 && drawn) atomicAdd(&ctr->mc_samples, drawn);
+    if (threadIdx.x == 0) {
+        if (my_failed) atomicAdd(&ctr->mc_failed, my_failed);
+        if (my_prunes) atomicAdd(&ctr->mc_prunes, my_prunes);
     }
 }
 
@@ -542,14 +547,50 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
 // workgroup per leaf triple; leaves hold at most kLeafMax points.
 constexpr int kLeafMax = 32;
 constexpr int kBaseThreads = 256;
+constexpr int kBaseJU = 4;     // j values per step, read as one LDS vector
+constexpr int kBaseSlots = 8;  // LDS accumulator slots per Phi_j (one slot per 8 lanes)
+static_assert(kLeafMax % kBaseJU == 0, "j steps must tile a leaf");
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// N consecutive table entries (16-byte aligned when N * sizeof(T) >= 16) in
+// as few LDS reads as the vector width allows.
+template <int N, typename T>
+__device__ __forceinline__ void lds_row(const T *p, T *o) {
+    if constexpr (N == 1) {
+        o[0] = p[0];
+    } else if constexpr (sizeof(T) == 4 && N == 2) {
+        const f32x2 v = *reinterpret_cast<const f32x2 *>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+    } else if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int h = 0; h < N; h += 4) {
+            const f32x4 v = *reinterpret_cast<const f32x4 *>(p + h);
+            o[h] = v.x;
+            o[h + 1] = v.y;
+            o[h + 2] = v.z;
+            o[h + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int h = 0; h < N; h += 2) {
+            const f64x2 v = *reinterpret_cast<const f64x2 *>(p + h);
+            o[h] = v.x;
+            o[h + 1] = v.y;
+        }
+    }
+}
 
 template <typename T>
-struct BaseLds {
-    double x[3][3][kLeafMax];                    // coordinates of P1, P2, P3
+struct alignas(16) BaseLds {
+    double x[3][3][kLeafMax];         // coordinates of P1, P2, P3
+    double pj[kLeafMax][kBaseSlots];  // Phi_j partials
+    double pk[kLeafMax];              // Phi_k partials
     T ua[kLeafMax][kLeafMax], uq[kLeafMax][kLeafMax], uw[kLeafMax][kLeafMax];  // (i, j)
     T cb[kLeafMax][kLeafMax], cq[kLeafMax][kLeafMax], co[kLeafMax][kLeafMax];  // (j, k)
-    double pj[kLeafMax][8];                      // Phi_j partials
-    double pk[kLeafMax];                         // Phi_k partials
 };
 
 template <typename T>
@@ -562,6 +603,7 @@ __global__ __launch_bounds__(kBaseThreads) void base_kernel(
     const int lane = tid & 63, wave = tid >> 6;
     const int kl = lane & 31, ih = lane >> 5;  // this lane's k and its half of the i points
     const unsigned long long n_base = ctr->n_base;
+    unsigned long long my_cases = 0, my_tri = 0;  // counters, kept by thread tid == 2 kLeafMax
     for (unsigned long long w = blockIdx.x; w < n_base; w += gridDim.x) {
         const Item it = base_list[w];
         const int b1 = nv.begin[it.p1], b2 = nv.begin[it.p2], b3 = nv.begin[it.p3];
@@ -574,7 +616,8 @@ __global__ __launch_bounds__(kBaseThreads) void base_kernel(
             for (int c = 0; c < 3; ++c) s.x[set][c][o] = o < cnt ? xs[3 * (int64_t)(b + o) + c] : 0.0;
         }
         if (tid < kLeafMax) s.pk[tid] = 0.0;
-        for (int e = tid; e < kLeafMax * 8; e += kBaseThreads) s.pj[e / 8][e % 8] = 0.0;
+        for (int e = tid; e < kLeafMax * kBaseSlots; e += kBaseThreads)
+            s.pj[e / kBaseSlots][e % kBaseSlots] = 0.0;
         __syncthreads();
         // pair tables: (i, j) and (j, k), masked by rank order and size
         for (int e = tid; e < kLeafMax * kLeafMax; e += kBaseThreads) {
@@ -610,27 +653,45 @@ __global__ __launch_bounds__(kBaseThreads) void base_kernel(
             acc_i[m] = T(0);
         }
         __syncthreads();
+        // j in steps of kBaseJU; entries past n2 are masked pairs, which
+        // contribute exact zeros
         double acck = 0.0;
-        for (int j = 0; j < n2; ++j) {
-            const T bj = s.cb[j][kl], qj = s.cq[j][kl], oj = s.co[j][kl];
-            const T bb = bj * bj;
-            T sk = T(0);
+        const int n2r = (n2 + kBaseJU - 1) / kBaseJU * kBaseJU;
+        for (int j0 = 0; j0 < n2r; j0 += kBaseJU) {
+            T bj[kBaseJU], qj[kBaseJU], oj[kBaseJU], bb[kBaseJU], sk[kBaseJU];
+#pragma unroll
+            for (int u = 0; u < kBaseJU; ++u) {
+                bj[u] = s.cb[j0 + u][kl];
+                qj[u] = s.cq[j0 + u][kl];
+                oj[u] = s.co[j0 + u][kl];
+                bb[u] = bj[u] * bj[u];
+                sk[u] = T(0);
+            }
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 const int il = 8 * m + 2 * wave + ih;
-                const T al = s.ua[il][j], qa = s.uq[il][j], wa = s.uw[il][j];
-                const T d = al - ag[m];
-                const T tt = (al + ag[m]) - bj;
-                const T mm = fma(-d, d, bb);
-                const T X = qa * aq[m];
-                const T Y = (wa * aw[m]) * (tt * mm);
-                const T psi = fma(oj, Y, X);
-                sk += psi;
-                acc_i[m] = fma(qj, psi, acc_i[m]);
+                T al[kBaseJU], qa[kBaseJU], wa[kBaseJU];
+                lds_row<kBaseJU>(&s.ua[il][j0], al);
+                lds_row<kBaseJU>(&s.uq[il][j0], qa);
+                lds_row<kBaseJU>(&s.uw[il][j0], wa);
+#pragma unroll
+                for (int u = 0; u < kBaseJU; ++u) {
+                    const T d = al[u] - ag[m];
+                    const T tt = (al[u] + ag[m]) - bj[u];
+                    const T mm = fma(-d, d, bb[u]);
+                    const T X = qa[u] * aq[m];
+                    const T Y = (wa[u] * aw[m]) * (tt * mm);
+                    const T psi = fma(oj[u], Y, X);
+                    sk[u] += psi;
+                    acc_i[m] = fma(qj[u], psi, acc_i[m]);
+                }
             }
-            const double v = (double)(qj * sk);
-            acck += v;
-            atomicAdd(&s.pj[j][lane & 7], v);
+#pragma unroll
+            for (int u = 0; u < kBaseJU; ++u) {
+                const double v = (double)(qj[u] * sk[u]);
+                acck += v;
+                atomicAdd(&s.pj[j0 + u][lane % kBaseSlots], v);
+            }
         }
         // Phi_i: sum over the 32 k lanes of each half-wave
         double vi[4];
@@ -662,12 +723,12 @@ __global__ __launch_bounds__(kBaseThreads) void base_kernel(
             const int j = tid - kLeafMax;
             if (j < n2) {
                 double v = 0.0;
-                for (int q = 0; q < 8; ++q) v += s.pj[j][q];
+                for (int q = 0; q < kBaseSlots; ++q) v += s.pj[j][q];
                 atomicAdd(&est[b2 + j], v);
                 atomicAdd(&lb[b2 + j], v);
             }
         } else if (tid == 2 * kLeafMax) {
-            atomicAdd(&ctr->base_cases, 1ull);
+            ++my_cases;
             const Roles r = roles_of(it.p1, it.p2, it.p3, n1, n2, n3);
             unsigned long long tri = 0;
             const char cs = canonical_case(it.p1, it.p2, it.p3);
@@ -675,11 +736,17 @@ __global__ __launch_bounds__(kBaseThreads) void base_kernel(
             else if (cs == 'b') tri = (unsigned long long)(comb2(n1) * n3);
             else if (cs == 'c') tri = (unsigned long long)(n1 * comb2(n2));
             else tri = (unsigned long long)n1 * n2 * n3;
-            atomicAdd(&ctr->base_triples, tri);
+            my_tri += tri;
             if (k.want_cov)
                 for (int q = 0; q < r.n_roles; ++q)
                     atomicAdd(&node_cov[r.node[q]], (unsigned long long)r.t[q]);
         }
+    }
+    // one update of the global counters per workgroup: the same-address
+    // atomics of every leaf triple serialized the whole kernel
+    if (tid == 2 * kLeafMax && my_cases) {
+        atomicAdd(&ctr->base_cases, my_cases);
+        atomicAdd(&ctr->base_triples, my_tri);
     }
 }
 
