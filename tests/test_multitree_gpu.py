@@ -76,6 +76,10 @@ def test_eps0_is_exhaustive(n, leaf, prec, tol, cuda):
     np.testing.assert_allclose(got, ref, rtol=tol, atol=tol * np.abs(ref).max())
     assert np.all(cov.cpu().numpy() == (n - 1) * (n - 2) // 2)
     assert st["det_prunes"] == 0 and st["mc_prunes"] == 0
+    # nothing pruned: the base cases hold every triple exactly once, and the
+    # statistics counters (summed per workgroup on the device) say so
+    assert st["base_triples"] == n * (n - 1) * (n - 2) // 6
+    assert st["visited"] >= st["base_cases"] > 0
 
 
 def test_small_n(cuda):
@@ -163,6 +167,8 @@ def test_monte_carlo_guarantee(cuda):
     frac = float(np.mean(rel <= eps))
     print("mc", st, "fraction within eps", frac, "max", rel.max())
     assert st["mc_prunes"] > 0
+    # every point of a pruned node triple drew at least m_min = 30 samples
+    assert st["mc_samples"] >= 30 * st["mc_prunes"]
     assert frac >= 1 - alpha
     assert np.all(cov.cpu().numpy() == (n - 1) * (n - 2) // 2)
 
