@@ -547,9 +547,10 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
 // workgroup per leaf triple; leaves hold at most kLeafMax points.
 constexpr int kLeafMax = 32;
 constexpr int kBaseThreads = 256;
-constexpr int kBaseJU = 4;     // j values per step, read as one LDS vector
+constexpr int kBaseJU = 4;     // j values per step, read as one LDS vector (binary32)
+constexpr int kBaseJU64 = 2;   // the same for binary64 tables (one 16-byte read)
 constexpr int kBaseSlots = 8;  // LDS accumulator slots per Phi_j (one slot per 8 lanes)
-static_assert(kLeafMax % kBaseJU == 0, "j steps must tile a leaf");
+static_assert(kLeafMax % kBaseJU == 0 && kLeafMax % kBaseJU64 == 0, "j steps must tile a leaf");
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -653,14 +654,15 @@ __global__ __launch_bounds__(kBaseThreads) void base_kernel(
             acc_i[m] = T(0);
         }
         __syncthreads();
-        // j in steps of kBaseJU; entries past n2 are masked pairs, which
+        constexpr int kJU = sizeof(T) == 4 ? kBaseJU : kBaseJU64;
+        // j in steps of kJU; entries past n2 are masked pairs, which
         // contribute exact zeros
         double acck = 0.0;
-        const int n2r = (n2 + kBaseJU - 1) / kBaseJU * kBaseJU;
-        for (int j0 = 0; j0 < n2r; j0 += kBaseJU) {
-            T bj[kBaseJU], qj[kBaseJU], oj[kBaseJU], bb[kBaseJU], sk[kBaseJU];
+        const int n2r = (n2 + kJU - 1) / kJU * kJU;
+        for (int j0 = 0; j0 < n2r; j0 += kJU) {
+            T bj[kJU], qj[kJU], oj[kJU], bb[kJU], sk[kJU];
 #pragma unroll
-            for (int u = 0; u < kBaseJU; ++u) {
+            for (int u = 0; u < kJU; ++u) {
                 bj[u] = s.cb[j0 + u][kl];
                 qj[u] = s.cq[j0 + u][kl];
                 oj[u] = s.co[j0 + u][kl];
@@ -670,12 +672,12 @@ __global__ __launch_bounds__(kBaseThreads) void base_kernel(
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 const int il = 8 * m + 2 * wave + ih;
-                T al[kBaseJU], qa[kBaseJU], wa[kBaseJU];
-                lds_row<kBaseJU>(&s.ua[il][j0], al);
-                lds_row<kBaseJU>(&s.uq[il][j0], qa);
-                lds_row<kBaseJU>(&s.uw[il][j0], wa);
+                T al[kJU], qa[kJU], wa[kJU];
+                lds_row<kJU>(&s.ua[il][j0], al);
+                lds_row<kJU>(&s.uq[il][j0], qa);
+                lds_row<kJU>(&s.uw[il][j0], wa);
 #pragma unroll
-                for (int u = 0; u < kBaseJU; ++u) {
+                for (int u = 0; u < kJU; ++u) {
                     const T d = al[u] - ag[m];
                     const T tt = (al[u] + ag[m]) - bj[u];
                     const T mm = fma(-d, d, bb[u]);
@@ -687,7 +689,7 @@ __global__ __launch_bounds__(kBaseThreads) void base_kernel(
                 }
             }
 #pragma unroll
-            for (int u = 0; u < kBaseJU; ++u) {
+            for (int u = 0; u < kJU; ++u) {
                 const double v = (double)(qj[u] * sk[u]);
                 acck += v;
                 atomicAdd(&s.pj[j0 + u][lane % kBaseSlots], v);
