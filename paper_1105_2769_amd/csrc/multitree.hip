@@ -444,9 +444,10 @@ __device__ McPoint mc_point_group(const Item &it, char cs, int slot, int64_t off
 }
 
 // 2. Monte Carlo test and commit (Algorithms 3-5), one workgroup per triple.
-// Waves take the points of the distinct nodes in turn; the triple is
-// summarized only if every point passes (any failure ends the test), in
-// which case the points are credited T_i mu and T_i (mu - z sigma_mu).
+// Groups of kMcGroup lanes take the points of the distinct nodes in turn;
+// the triple is summarized only if every point passes (any failure ends the
+// test), in which case the points are credited T_i mu and
+// T_i (mu - z sigma_mu).
 __global__ __launch_bounds__(kMcThreads) void mc_kernel(
     const Item *__restrict__ mc_list, NodeView nv, const double *__restrict__ xs,
     const double *__restrict__ node_phil, double *__restrict__ est, double *__restrict__ lb,
