@@ -557,8 +557,8 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
-// N consecutive table entries (16-byte aligned when N * sizeof(T) >= 16) in
-// as few LDS reads as the vector width allows.
+// N consecutive table entries in as few LDS reads as the vector width
+// allows; p is aligned to the read width (N * sizeof(T) bytes, at most 16).
 template <int N, typename T>
 __device__ __forceinline__ void lds_row(const T *p, T *o) {
     if constexpr (N == 1) {
@@ -605,7 +605,7 @@ __global__ __launch_bounds__(kBaseThreads) void base_kernel(
     const int lane = tid & 63, wave = tid >> 6;
     const int kl = lane & 31, ih = lane >> 5;  // this lane's k and its half of the i points
     const unsigned long long n_base = ctr->n_base;
-    unsigned long long my_cases = 0, my_tri = 0;  // counters, kept by thread tid == 2 kLeafMax
+    unsigned long long my_cases = 0, my_tri = 0;  // statistics; thread 2 * kLeafMax counts
     for (unsigned long long w = blockIdx.x; w < n_base; w += gridDim.x) {
         const Item it = base_list[w];
         const int b1 = nv.begin[it.p1], b2 = nv.begin[it.p2], b3 = nv.begin[it.p3];
