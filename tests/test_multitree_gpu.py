@@ -238,3 +238,32 @@ def test_eps0_exact_either_bound(bound, cuda):
     # whose Phi nearly cancels to zero
     np.testing.assert_allclose(phi.cpu().numpy(), ref, rtol=1e-11, atol=1e-14 * np.abs(ref).max())
     assert np.all(cov.cpu().numpy() == (1500 - 1) * (1500 - 2) // 2)
+
+
+def test_mixture_262144_oracle_samples(cuda):
+    """Full-size parity: the N = 262144 saturated Gaussian mixture at the
+    settings the benchmark times (relative eps 1e-2, alpha 0.05, leaf 32,
+    FP32C base cases, magnitude bound), against the oracle's Phi at 64
+    seeded-sampled points stored in tests/golden (Theorem 5.2: at least a
+    1 - alpha fraction within eps)."""
+    import json
+    import os
+
+    import paper_1105_2769_amd as mb
+
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                    "c3_direct_samples.json")))
+    n = g["n"]
+    print(f"mixture n={n}: generating", flush=True)
+    x = workloads.saturated_gaussian_mixture(n, seed=3)
+    idx = np.array(g["indices"])
+    ref = np.array([float(v) for v in g["phi"]])
+    print(f"mixture n={n}: traversal", flush=True)
+    phi, st = mb.eval_multitree(dev(x, cuda), eps=1e-2, alpha=0.05, leaf_size=32,
+                                bound="magnitude", base_prec="fp32c")
+    rel = np.abs(phi.cpu().numpy()[idx] - ref) / np.abs(ref)
+    frac = float(np.mean(rel <= 1e-2))
+    print("mixture", st, "fraction within eps", frac, "max", rel.max(), flush=True)
+    assert frac >= 0.95
+    assert st["det_prunes"] > 0 and st["mc_prunes"] > 0
+    assert 0 < st["base_triples"] < n * (n - 1) * (n - 2) // 6
