@@ -171,3 +171,31 @@ def test_poisson_arrivals_latency(cuda):
     print(f"p50 {np.percentile(lat, 50) * 1e3:.2f} ms  p99 {np.percentile(lat, 99) * 1e3:.2f} ms")
     for k in (0, len(pts) // 2, len(pts) - 1):
         oracle_check(pts[k], res[k], 1e-6)
+
+
+def test_full_trace_4096_requests(cuda):
+    """Full-size parity of the serving loop: the 4096-request Poisson trace
+    (200 requests/s, N log-uniform in [64, 8192], seed 5) replayed in real
+    time through a server configured as the benchmark's, with every result
+    finite and 8 seeded-sampled requests checked against the oracle."""
+    import time
+
+    t, sizes = workloads.poisson_trace(4096, seed=5, rate_hz=200.0, n_min=64, n_max=8192)
+    pts = [workloads.jittered_lattice(int(n), seed=1_000_000 + r) for r, n in enumerate(sizes)]
+    print("trace: replaying 4096 requests", flush=True)
+    with server(hbm_budget_bytes=64 << 30, max_slots=512) as srv:
+        t0 = time.perf_counter()
+        ids = []
+        for ta, x in zip(t, pts):
+            while time.perf_counter() - t0 < ta:
+                time.sleep(5e-4)
+            ids.append(srv.submit(x))
+        assert srv.wait(-1, 120_000)
+        lat = np.array([srv.latency(r) for r in ids])
+        res = [srv.result(r) for r in ids]
+    assert np.all(lat > 0) and np.all(np.isfinite(lat))
+    assert all(np.all(np.isfinite(v)) and v.shape == (x.shape[0],) for v, x in zip(res, pts))
+    print(f"trace: p50 {np.percentile(lat, 50) * 1e3:.2f} ms  p99 "
+          f"{np.percentile(lat, 99) * 1e3:.2f} ms", flush=True)
+    for k in workloads.sample_indices(len(pts), 8, seed=56):
+        oracle_check(pts[k], res[k], 1e-6, n_sample=16, seed=int(k))
