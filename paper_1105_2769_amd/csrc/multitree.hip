@@ -475,14 +475,26 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
             sz[q] = nv.end[r.node[q]] - nv.begin[r.node[q]];
             total += sz[q];
         }
+        // points of the node with the smallest Phi^l (the tightest allowance)
+        // first: a triple that fails usually fails there, and the test ends at
+        // the first failure.  The order changes no point's samples or result.
+        int qo[3] = {0, 1, 2};
+        for (int a = 1; a < r.n_roles; ++a)
+            for (int b = a; b > 0 && node_phil[r.node[qo[b]]] < node_phil[r.node[qo[b - 1]]]; --b) {
+                const int tmp = qo[b];
+                qo[b] = qo[b - 1];
+                qo[b - 1] = tmp;
+            }
+        const int64_t szo[3] = {sz[qo[0]], sz[qo[1]], sz[qo[2]]};
         __syncthreads();
         if (threadIdx.x == 0) failed = 0;
         __syncthreads();
         for (int64_t e = grp; e < total; e += kGroups) {
             if (failed) break;
-            int q = 0;
+            int qq = 0;
             int64_t off = e;
-            while (off >= sz[q]) off -= sz[q++];
+            while (off >= szo[qq]) off -= szo[qq++];
+            const int q = qo[qq];
             const int64_t xr = nv.begin[r.node[q]] + off;
             const McPoint res = mc_point_group(it, cs, r.slot[q], off, xr, n1, n2, n3, pn, nv, xs,
                                                (double)r.t[q], node_phil[r.node[q]], k, &failed,
@@ -509,9 +521,10 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
             continue;
         }
         for (int64_t e = grp; e < total; e += kGroups) {
-            int q = 0;
+            int qq = 0;
             int64_t off = e;
-            while (off >= sz[q]) off -= sz[q++];
+            while (off >= szo[qq]) off -= szo[qq++];
+            const int q = qo[qq];
             const int64_t xr = nv.begin[r.node[q]] + off;
             const double t = (double)r.t[q];
             double mean, low;
