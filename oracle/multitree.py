@@ -37,12 +37,18 @@ Axilrod-Teller potential:
         (c) x in A: C(n_B, 2), x in B: n_A (n_B - 1);
         (d) the product of the other two counts;
     T_root = C(N - 1, 2).
-  * Bounds for Axilrod-Teller.  The paper's bound assumes a monotone
-    potential; Axilrod-Teller is sign-indefinite.  Its angular factor
-    1 + 3 cos cos cos lies in [-2, 11/8] (collinear, equilateral), so with
-    R^u = 1 / (d^l_12 d^l_13 d^l_23)^3 every phi of the triple, and phi at
-    the centroids, lies in [-2 R^u, 11/8 R^u]: span = 27/8 R^u and
-    phi_lo = -2 R^u.  Only case (d) with all d^l > 0 can be pruned this way.
+  * Bounds for Axilrod-Teller.  The paper's bound (Section 4) takes a
+    monotone potential at the largest and smallest node distances d^u, d^l;
+    Axilrod-Teller is neither monotone nor of one sign.  ``at_bounds``
+    bounds phi = R g over all triangles whose sides lie between d^l and d^u
+    of the three node pairs: R = (r_12 r_13 r_23)^-3 between its values at
+    d^u and d^l, and the angular factor g = 1 + 3 cos cos cos from the exact
+    range of each cosine over the box of squared sides, clipped to
+    [-2, 11/8] (collinear, equilateral).  phi_lo takes the role of the
+    paper's phi(d^u) and phi_hi that of phi(d^l): the prune test compares
+    phi_hi - phi_lo with the allowance and delta^l_i = T_i phi_lo.  Every
+    d^l is raised to the closest-pair distance of the set.  Only case (d)
+    is tested (a node paired with itself has d^l = 0).
   * Running lower bound Phi^l.  LB(x) accumulates the lower bounds of
     everything already credited to x (exact base-case values, delta^l of
     deterministic prunes, T_i (mu - z sigma_mu) of Monte Carlo prunes);
@@ -65,10 +71,14 @@ Axilrod-Teller potential:
     numbers.  A 64-bit uniform integer r is (w1 << 32 | w0); an index in
     [0, M) is floor(r * M / 2^64).
   * Test order: deterministic, then Monte Carlo, then base case or split.
-  * Sign-indefinite potentials (optional reading, not in the paper): with
-    bound="magnitude" the node statistic is min over x in P of the magnitude
-    of x's running estimate, since the running lower bound of a potential
-    that is negative for many points stays negative and nothing prunes.
+  * Sign-indefinite potentials.  The running lower bound of a point whose
+    Phi is negative stays negative, and the paper's relative rule then never
+    prunes a triple holding that point.  With bound="two_sided" a running
+    upper bound UB(x) is kept beside LB(x) (same credits with the upper ends
+    of the intervals) and the allowance bounds max(LB, -UB) from below: the
+    relative bound of Definition 2.2 is on |Phi|, and once the sign of a
+    point's running total is settled either side certifies its size.  For a
+    non-negative potential it is the paper's rule.
 """
 from __future__ import annotations
 
@@ -78,7 +88,7 @@ from statistics import NormalDist
 
 import numpy as np
 
-from .kdtree import KdTree, box_min_dist, build_kdtree
+from .kdtree import KdTree, box_max_dist, box_min_dist, build_kdtree
 from .philox import philox4x32_10_np
 
 
@@ -238,21 +248,127 @@ def sample_partners(case: str, slot: int, x_local: np.ndarray, n: tuple[int, int
     return t // nb, t % nb, others[0], others[1]
 
 
-def det_bounds(d12: float, d13: float, d23: float) -> tuple[float, float]:
-    """(phi_lo, span) over all triangles whose sides are at least d12, d13, d23.
+def cos_range(a: tuple[float, float], b: tuple[float, float],
+              c: tuple[float, float]) -> tuple[float, float]:
+    """Range of the cosine of a triangle's angle over boxes of squared sides.
 
-    With R^u = 1 / (d12 d13 d23)^3 the distance factor is at most R^u and the
-    angular factor 1 + 3 cos cos cos lies in [-2, 11/8] (collinear,
-    equilateral), so phi lies in [-2 R^u, 11/8 R^u]: phi_lo = -2 R^u and
-    span = 27/8 R^u (the bound of Section 4 for a sign-indefinite potential).
+    The angle lies between the sides of squared lengths a and b; c is the
+    squared length of the side opposite it; each is given as an interval
+    (lower, upper).  By the law of cosines cos = h(a, b, c) with
+    h = (a + b - c) / (2 sqrt(a b)).
+
+    * h falls as c grows, so the largest value has c at its lower end and the
+      smallest has c at its upper end.
+    * For fixed c, with s = sqrt(a), t = sqrt(b): dh/dt = (t^2 - s^2 + c) /
+      (2 s t^2), so along an edge of the (a, b) box h first falls, then rises
+      (a single minimum at b = a - c, when a > c, where h = sqrt(1 - c/a):
+      the angle facing the side a is right); by symmetry the same holds in a.
+      Both derivatives vanish together only if c = 0, so for c > 0 there is
+      no critical point inside the box.
+    * Hence the maximum is at one of the four corners (c low), and the
+      minimum at a corner or at an edge point b = a - c or a = b - c (c high).
+
+    The box may hold (a, b, c) that are not triangles; cosines of real
+    triangles lie in [-1, 1], so the range is clipped there.
     """
-    ru = 1.0 / (d12 * d13 * d23) ** 3
-    return -2.0 * ru, 3.375 * ru
+    def h(a_, b_, c_):
+        return (a_ + b_ - c_) / (2.0 * math.sqrt(a_ * b_))
+
+    top = max(h(a_, b_, c[0]) for a_ in a for b_ in b)
+    cands = [h(a_, b_, c[1]) for a_ in a for b_ in b]
+    for a_ in a:  # edge a fixed, b free
+        bs = a_ - c[1]
+        if b[0] < bs < b[1]:
+            cands.append(math.sqrt(1.0 - c[1] / a_))
+    for b_ in b:  # edge b fixed, a free
+        as_ = b_ - c[1]
+        if a[0] < as_ < a[1]:
+            cands.append(math.sqrt(1.0 - c[1] / b_))
+    return max(-1.0, min(cands)), min(1.0, top)
+
+
+def at_bounds(lo: tuple[float, float, float], up: tuple[float, float, float]) -> tuple[float, float]:
+    """(phi_lo, phi_hi) over every triangle whose sides lie between lo and up.
+
+    lo = (d^l_12, d^l_13, d^l_23) and up = (d^u_12, d^u_13, d^u_23), the
+    smallest and largest distances between the three node pairs (the
+    distance bounds of Section 3).  Section 4 bounds a monotone potential by
+    its values at d^u and d^l; the Axilrod-Teller phi is neither monotone nor
+    of one sign, so it is bounded as the product of two factors,
+
+        phi = R * g,  R = (r_12 r_13 r_23)^-3,  g = 1 + 3 cos t_1 cos t_2 cos t_3,
+
+    each over its own range: R lies in [R(d^u), R(d^l)]; each cosine lies in
+    the range of ``cos_range`` (t_1 is the angle at node 1, between sides 12
+    and 13, facing side 23); the product of three intervals is taken over
+    its eight corners; and g is clipped to [-2, 11/8], its values at a
+    collinear and an equilateral triangle, the extremes over all triangles.
+    phi_lo pairs the lower end of g with the R that makes it smallest, and
+    phi_hi likewise.  The result never lies outside [-2 R(d^l), 11/8 R(d^l)].
+    """
+    a = (lo[0] ** 2, up[0] ** 2)  # side 12
+    b = (lo[1] ** 2, up[1] ** 2)  # side 13
+    c = (lo[2] ** 2, up[2] ** 2)  # side 23
+    r_hi = 1.0 / (lo[0] * lo[1] * lo[2]) ** 3
+    r_lo = 1.0 / (up[0] * up[1] * up[2]) ** 3
+    c1 = cos_range(a, b, c)  # at node 1: sides 12, 13; opposite 23
+    c2 = cos_range(a, c, b)  # at node 2: sides 12, 23; opposite 13
+    c3 = cos_range(b, c, a)  # at node 3: sides 13, 23; opposite 12
+    prods = [u * v * w for u in c1 for v in c2 for w in c3]
+    g_lo = max(-2.0, 1.0 + 3.0 * min(prods))
+    g_hi = min(1.375, 1.0 + 3.0 * max(prods))
+    phi_lo = g_lo * (r_lo if g_lo >= 0.0 else r_hi)
+    phi_hi = g_hi * (r_hi if g_hi >= 0.0 else r_lo)
+    return phi_lo, phi_hi
+
+
+def closest_pair(x: np.ndarray) -> float:
+    """Smallest distance between two points of the set (brute force over all pairs)."""
+    best = math.inf
+    for i in range(x.shape[0] - 1):
+        d = x[i + 1:] - x[i]
+        best = min(best, float(np.einsum("ij,ij->i", d, d).min()))
+    return math.sqrt(best)
+
+
+def node_triple_bounds(tree: KdTree, p: tuple[int, int, int], r_min: float) -> tuple[float, float]:
+    """at_bounds of a node triple; every d^l is raised to the closest-pair
+    distance r_min of the whole set (no two points are closer)."""
+    p1, p2, p3 = p
+    pairs = ((p1, p2), (p1, p3), (p2, p3))
+    lo = tuple(max(box_min_dist(tree.lo[u], tree.hi[u], tree.lo[v], tree.hi[v]), r_min)
+               for u, v in pairs)
+    up = tuple(max(box_max_dist(tree.lo[u], tree.hi[u], tree.lo[v], tree.hi[v]), l_)
+               for (u, v), l_ in zip(pairs, lo))
+    return at_bounds(lo, up)
+
+
+def certified(bound: str, stat, t, lo, hi):
+    """Lower bound on |Phi(x)| for every x of a node after it is credited t
+    tuples whose values lie in [lo, hi] (numbers or arrays).
+
+    ``stat`` holds the node's statistics before the credit:
+      "signed"    (the paper, Section 4.1): stat = Phi^l(P) = min_x LB(x);
+                  the result is Phi^l(P) + t lo (lo plays delta^l / t);
+      "two_sided" (a reading for sign-indefinite potentials): stat =
+                  (min_x LB(x), min_x -UB(x), min_x max(LB(x), -UB(x))) with
+                  UB the running upper bound; after the credit
+                  max(LB + t lo, -(UB + t hi)) is at least each of
+                  min LB + t lo, min(-UB) - t hi and
+                  min max(LB, -UB) + min(t lo, -t hi), so their largest is a
+                  lower bound.  When every LB is positive the first term
+                  wins and this is the paper's rule.
+    """
+    if bound == "signed":
+        return stat + t * lo
+    a_pos, a_neg, a_mix = stat
+    return np.maximum(np.maximum(a_pos + t * lo, a_neg - t * hi),
+                      a_mix + np.minimum(t * lo, -t * hi))
 
 
 def mc_try(tree: KdTree, xs: np.ndarray, p: tuple[int, int, int], roles, cnt, phil,
            eps: float, tau: float, t_root: int, z: float, seed: int, m_limit: int, m_min: int,
-           magnitude: bool = False):
+           bound: str = "signed"):
     """Monte Carlo test of one node triple (Algorithm 3, Algorithm 4 per point).
 
     For every point x of every distinct node P_i (``roles`` = (node, T_i,
@@ -260,8 +376,10 @@ def mc_try(tree: KdTree, xs: np.ndarray, p: tuple[int, int, int], roles, cnt, ph
     running mean and unbiased variance updated; x stops at the first m with
     m >= m_min and
         z sigma_mu <= (eps (Phi^l(P_i) + T_i (mu - z sigma_mu)) + tau) / T_root,
-    and passes if that holds, else fails at m = m_limit.  With ``magnitude``
-    the credit is Phi^l(P_i) alone (the magnitude reading, see ``multitree``).  Points are scanned
+    and passes if that holds, else fails at m = m_limit.  ``phil`` holds
+    the node statistics of ``bound`` and the credit is ``certified`` with the
+    interval [mu - z sigma_mu, mu + z sigma_mu] per tuple (for "signed" the
+    printed rule above).  Points are scanned
     in order and the scan ends at the first failure.  Returns (all passed,
     [(first rank, T_i, mu per point, sigma_mu per point)], samples used).
     """
@@ -291,7 +409,7 @@ def mc_try(tree: KdTree, xs: np.ndarray, p: tuple[int, int, int], roles, cnt, ph
             if m < 2:
                 continue
             sig_mu = np.sqrt(m2 / (m - 1) / m)
-            credit = plo if magnitude else plo + t * (mean - z * sig_mu)
+            credit = certified(bound, plo, t, mean - z * sig_mu, mean + z * sig_mu)
             cond = z * sig_mu <= (eps * credit + tau) / t_root
             fresh = (stop_m < 0) & ((cond & (m >= m_min)) | (m == m_limit))
             stop_m[fresh] = m
@@ -322,25 +440,25 @@ def multitree(x, eps: float, alpha: float, leaf_size: int, tau: float = 0.0, see
     """The traversal.  ``bound`` chooses the node statistic of the prune rules:
 
     * "signed": the paper's running lower bound Phi^l (Section 4.1);
-    * "magnitude" (a reading for sign-indefinite potentials, not in the
-      paper): min over x in P of |running estimate of Phi(x)| - exact and
-      pruned contributions credited so far - used without the delta^l and
-      T_i (mu - z sigma) terms.
+    * "two_sided" (a reading for sign-indefinite potentials): running lower
+      and upper bounds LB, UB per point, and the allowance is a lower bound
+      on max(LB, -UB), i.e. on |Phi| when its sign is settled (see
+      ``certified``); for potentials >= 0 it is the paper's rule.
     """
     x = np.asarray(x, dtype=np.float64)
     n = x.shape[0]
     if eps < 0 or tau < 0 or not (0.0 <= alpha < 1.0) or leaf_size < 1:
         raise ValueError("bad multitree parameters")
-    if bound not in ("signed", "magnitude"):
-        raise ValueError("bound must be 'signed' or 'magnitude'")
-    magnitude = bound == "magnitude"
+    if bound not in ("signed", "two_sided"):
+        raise ValueError("bound must be 'signed' or 'two_sided'")
     tree = build_kdtree(x, leaf_size)
     xs = x[tree.perm]  # depth-first order
+    r_min = closest_pair(x)
     t_root = comb2(n - 1) if n >= 1 else 0
     z = NormalDist().inv_cdf(1.0 - alpha / 2.0) if alpha > 0 else math.inf
     est = np.zeros(n)
     lb = np.zeros(n)
-    run = np.zeros(n)  # running estimate: est plus pruned node estimates so far
+    ub = np.zeros(n)   # running upper bound (two_sided)
     cov = np.zeros(n, dtype=np.int64)
     node_acc = np.zeros(tree.n_nodes)
     st = dict(visited=0, det_prunes=0, mc_prunes=0, mc_failed=0, base_cases=0, base_triples=0,
@@ -351,10 +469,11 @@ def multitree(x, eps: float, alpha: float, leaf_size: int, tau: float = 0.0, see
     def pts(node):
         return slice(int(tree.begin[node]), int(tree.end[node]))
 
-    def phi_l(node) -> float:
-        if magnitude:
-            return float(np.abs(run[pts(node)]).min())
-        return float(lb[pts(node)].min())
+    def phi_l(node):
+        if bound == "signed":
+            return float(lb[pts(node)].min())
+        lo_, up_ = lb[pts(node)], ub[pts(node)]
+        return float(lo_.min()), float((-up_).min()), float(np.maximum(lo_, -up_).min())
 
     stack = [(0, 0, 0)]
     while stack:
@@ -367,34 +486,29 @@ def multitree(x, eps: float, alpha: float, leaf_size: int, tau: float = 0.0, see
 
         # (a) deterministic prune, case (d) only
         if case == "d":
-            d12 = box_min_dist(tree.lo[p1], tree.hi[p1], tree.lo[p2], tree.hi[p2])
-            d13 = box_min_dist(tree.lo[p1], tree.hi[p1], tree.lo[p3], tree.hi[p3])
-            d23 = box_min_dist(tree.lo[p2], tree.hi[p2], tree.lo[p3], tree.hi[p3])
-            if d12 > 0 and d13 > 0 and d23 > 0:
-                phi_lo, span = det_bounds(d12, d13, d23)
-                allow = min(phi_l(node) + (0.0 if magnitude else t * phi_lo)
-                            for node, t, _ in roles)
-                if span <= (eps * allow + tau) / t_root:
-                    phic = float(at_phi_np(tree.centroid[p1], tree.centroid[p2], tree.centroid[p3]))
-                    for node, t, _ in roles:
-                        node_acc[node] += t * phic
-                        run[pts(node)] += t * phic
-                        lb[pts(node)] += t * phi_lo
-                        cov[pts(node)] += t
-                    st["det_prunes"] += 1
-                    continue
+            phi_lo, phi_hi = node_triple_bounds(tree, p, r_min)
+            allow = min(certified(bound, phi_l(node), t, phi_lo, phi_hi) for node, t, _ in roles)
+            if phi_hi - phi_lo <= (eps * allow + tau) / t_root:
+                phic = float(at_phi_np(tree.centroid[p1], tree.centroid[p2], tree.centroid[p3]))
+                for node, t, _ in roles:
+                    node_acc[node] += t * phic
+                    lb[pts(node)] += t * phi_lo
+                    ub[pts(node)] += t * phi_hi
+                    cov[pts(node)] += t
+                st["det_prunes"] += 1
+                continue
 
         # (b) Monte Carlo prune (Algorithm 3 over the distinct nodes, Algorithm 4 per point)
         if alpha > 0 and zeta * m_limit <= min(t for _, t, _ in roles):
             ok, commits, used = mc_try(tree, xs, p, roles, cnt, [phi_l(node) for node, _, _ in roles],
-                                       eps, tau, t_root, z, seed, m_limit, m_min, magnitude)
+                                       eps, tau, t_root, z, seed, m_limit, m_min, bound)
             st["mc_samples"] += used
             if ok:
                 for base, t, mu_s, sg_s in commits:
                     sl = slice(base, base + mu_s.shape[0])
                     est[sl] += t * mu_s
-                    run[sl] += t * mu_s
                     lb[sl] += t * (mu_s - z * sg_s)
+                    ub[sl] += t * (mu_s + z * sg_s)
                     cov[sl] += t
                 st["mc_prunes"] += 1
                 continue
@@ -409,8 +523,8 @@ def multitree(x, eps: float, alpha: float, leaf_size: int, tau: float = 0.0, see
                 f = at_phi_np(xs[ri], xs[rj], xs[rk])
                 for r_ in (ri, rj, rk):
                     np.add.at(est, r_, f)
-                    np.add.at(run, r_, f)
                     np.add.at(lb, r_, f)
+                    np.add.at(ub, r_, f)
                     np.add.at(cov, r_, 1)
             st["base_cases"] += 1
             st["base_triples"] += int(ri.size)

@@ -54,6 +54,50 @@ def c3_samples(threads: int = 0):
         json.dump(out, f, indent=1)
 
 
+def c3_extra_samples(threads: int = 0, batch: int = 8):
+    """Direct Phi at 192 more particles of the 262144-point saturated mixture.
+
+    Together with the 64 of ``c3_samples`` they make 256 sampled particles.
+    The extra indices are drawn with seed 2003 from the particles that the
+    first 64 do not already hold.  The file is rewritten after every batch of
+    ``batch`` particles, so an interrupted run keeps what it has finished and
+    a new run continues from there.
+    """
+    x = workloads.saturated_gaussian_mixture(262144, seed=3)
+    first = set(workloads.sample_indices(262144, 64, seed=1003).tolist())
+    pool = workloads.sample_indices(262144, 512, seed=2003)
+    idx = [int(i) for i in pool if int(i) not in first][:192]
+    path = os.path.join(HERE, "c3_direct_samples_extra.json")
+    done_i, done_phi, secs = [], [], 0.0
+    if os.path.exists(path):
+        with open(path) as f:
+            old = json.load(f)
+        if old.get("planned") == idx:
+            done_i, done_phi, secs = old["indices"], old["phi"], old["oracle_seconds"]
+    for b in range(len(done_i), len(idx), batch):
+        part = idx[b:b + batch]
+        t = time.time()
+        vals = direct.phi(x, part, threads=threads)
+        secs += time.time() - t
+        done_i += part
+        done_phi += [repr(float(v)) for v in vals]
+        out = {
+            "workload": "saturated Gaussian mixture: 32 components, means U[0,100]^3, sigma 2.0, "
+                        "min separation 0.3, seed 3",
+            "n": 262144,
+            "sample_rule": "sample_indices(262144, 512, seed=2003) minus the 64 of seed 1003, "
+                           "first 192",
+            "planned": idx,
+            "indices": done_i,
+            "phi": done_phi,
+            "oracle_seconds": secs,
+        }
+        with open(path + ".tmp", "w") as f:
+            json.dump(out, f, indent=1)
+        os.replace(path + ".tmp", path)
+        print(f"c3 extra: {len(done_i)}/{len(idx)} particles, {secs:.0f} s", flush=True)
+
+
 def c4_samples(threads: int = 0):
     """Direct Phi at 64 sampled particles of the 16384-point jittered lattice."""
     x = workloads.jittered_lattice(16384, seed=4)
@@ -79,5 +123,7 @@ if __name__ == "__main__":
         c2_samples()
     elif which == "c3":
         c3_samples(int(sys.argv[2]) if len(sys.argv) > 2 else 0)
+    elif which == "c3x":
+        c3_extra_samples(int(sys.argv[2]) if len(sys.argv) > 2 else 0)
     elif which == "c4":
         c4_samples(int(sys.argv[2]) if len(sys.argv) > 2 else 0)

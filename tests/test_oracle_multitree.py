@@ -188,30 +188,129 @@ def test_monte_carlo_mode_fraction_within_eps():
     assert np.mean(rel <= eps) >= 1.0 - alpha
 
 
-def test_det_bounds_enclose_and_are_attained():
-    # points drawn in three separated boxes stay inside [phi_lo, phi_lo + span]
-    rng = workloads.rng(31)
-    for _ in range(40):
-        c = rng.uniform(0, 12, size=(3, 3))
-        w = rng.uniform(0.05, 1.0, size=(3, 3))
-        lo, hi = c - w / 2, c + w / 2
-        d12 = okd.box_min_dist(lo[0], hi[0], lo[1], hi[1])
-        d13 = okd.box_min_dist(lo[0], hi[0], lo[2], hi[2])
-        d23 = okd.box_min_dist(lo[1], hi[1], lo[2], hi[2])
-        if min(d12, d13, d23) <= 0:
+def _cos_grid(a, b, c, m=161):
+    """Extremes of (a + b - c) / (2 sqrt(ab)) on a dense grid of the box (brute force)."""
+    ga = np.linspace(a[0], a[1], m)[:, None, None]
+    gb = np.linspace(b[0], b[1], m)[None, :, None]
+    gc = np.linspace(c[0], c[1], 7)[None, None, :]
+    h = (ga + gb - gc) / (2.0 * np.sqrt(ga * gb))
+    return float(h.min()), float(h.max())
+
+
+@pytest.mark.parametrize("a,b,c", [
+    ((4.0, 9.0), (0.5, 6.0), (1.0, 2.0)),     # minimum inside the edge a = 4 (b = a - c)
+    ((0.5, 6.0), (4.0, 9.0), (1.0, 2.0)),     # the same with a and b exchanged
+    ((1.0, 1.2), (1.1, 1.3), (0.9, 1.05)),    # small box near the equilateral triangle
+    ((9.0, 10.0), (0.2, 0.3), (8.0, 9.5)),    # thin triangle, cosines near +-1
+    ((2.0, 50.0), (3.0, 40.0), (0.5, 60.0)),  # wide box: both clips are active
+])
+def test_cos_range_is_the_exact_range_over_the_box(a, b, c):
+    lo, hi = omt.cos_range(a, b, c)
+    glo, ghi = _cos_grid(a, b, c)
+    # every grid value inside, and the ends attained to within the grid step
+    assert lo <= max(glo, -1.0) + 1e-15 and hi >= min(ghi, 1.0) - 1e-15
+    assert lo == pytest.approx(max(glo, -1.0), abs=2e-4)
+    assert hi == pytest.approx(min(ghi, 1.0), abs=2e-4)
+
+
+def _box_triple(rng, spread, width):
+    c = rng.uniform(0, spread, size=(3, 3))
+    w = rng.uniform(0.05, 1.0, size=(3, 3)) * width
+    return c - w / 2, c + w / 2
+
+
+def _dist_bounds(lo, hi):
+    pairs = ((0, 1), (0, 2), (1, 2))
+    dl = tuple(okd.box_min_dist(lo[u], hi[u], lo[v], hi[v]) for u, v in pairs)
+    du = tuple(okd.box_max_dist(lo[u], hi[u], lo[v], hi[v]) for u, v in pairs)
+    return dl, du
+
+
+def test_box_max_dist_is_the_farthest_corner_pair():
+    rng = workloads.rng(30)
+    for _ in range(50):
+        lo, hi = _box_triple(rng, 10.0, 2.0)
+        corners = [np.array([(hi if (m >> d) & 1 else lo)[q][d] for d in range(3)])
+                   for q in range(2) for m in range(8)]
+        far = max(np.linalg.norm(corners[i] - corners[8 + j]) for i in range(8) for j in range(8))
+        assert okd.box_max_dist(lo[0], hi[0], lo[1], hi[1]) == pytest.approx(far, rel=1e-14)
+        p = rng.uniform(lo[0], hi[0], size=(300, 3))
+        q = rng.uniform(lo[1], hi[1], size=(300, 3))
+        assert np.linalg.norm(p - q, axis=1).max() <= far
+
+
+@pytest.mark.parametrize("layout", ["random", "collinear", "equilateral", "close"])
+def test_at_bounds_enclose_phi_of_points_in_the_boxes(layout):
+    rng = workloads.rng({"random": 31, "collinear": 32, "equilateral": 33, "close": 34}[layout])
+    checked = 0
+    for _ in range(60):
+        if layout == "random":
+            lo, hi = _box_triple(rng, 12.0, rng.choice([0.02, 0.2, 1.0]))
+        else:
+            if layout == "collinear":  # boxes along a line: near-collinear triangles
+                t = np.sort(rng.uniform(0, 10, size=3))
+                c = np.outer(t, rng.normal(size=3)) + rng.normal(size=3)
+            elif layout == "equilateral":
+                s = rng.uniform(1, 5)
+                c = np.array([[0, 0, 0], [s, 0, 0], [s / 2, s * math.sqrt(0.75), 0]])
+            else:  # two boxes almost touching, the third farther
+                c = np.array([[0, 0, 0], [1.0, 0, 0], rng.uniform(2, 6, size=3)])
+            w = rng.uniform(0.02, 0.6, size=(3, 3))
+            lo, hi = c - w / 2, c + w / 2
+        dl, du = _dist_bounds(lo, hi)
+        if min(dl) <= 0:
             continue
-        plo, span = omt.det_bounds(d12, d13, d23)
-        p = [rng.uniform(lo[q], hi[q], size=(500, 3)) for q in range(3)]
+        plo, phi_ = omt.at_bounds(dl, du)
+        p = [rng.uniform(lo[q], hi[q], size=(3000, 3)) for q in range(3)]
+        # the box corners too, where the extremes of the distances sit
         f = omt.at_phi_np(p[0], p[1], p[2])
-        assert f.min() >= plo and f.max() <= plo + span
-    # degenerate boxes: equilateral triangle attains the top, collinear the bottom
-    s = math.sqrt(3.0) / 2.0
-    tri = np.array([[0.0, 0, 0], [2.0, 0, 0], [1.0, 2 * s, 0]])
-    plo, span = omt.det_bounds(2.0, 2.0, 2.0)
-    assert omt.at_phi_np(tri[0], tri[1], tri[2]) == pytest.approx(plo + span, rel=1e-14)
-    line = np.array([[0.0, 0, 0], [1.0, 0, 0], [2.5, 0, 0]])
-    plo, _ = omt.det_bounds(1.0, 2.5, 1.5)
-    assert omt.at_phi_np(line[0], line[1], line[2]) == pytest.approx(plo, rel=1e-14)
+        assert plo <= f.min() and f.max() <= phi_
+        # never looser than the envelope [-2 R, 11/8 R] at the smallest distances
+        ru = 1.0 / (dl[0] * dl[1] * dl[2]) ** 3
+        assert plo >= -2.0 * ru * (1 + 1e-14) and phi_ <= 1.375 * ru * (1 + 1e-14)
+        checked += 1
+    assert checked >= 20
+
+
+def test_at_bounds_attained_for_point_boxes():
+    # boxes shrunk to points: both ends equal phi of that triangle
+    d = 1.7
+    lo, hi = omt.at_bounds((d, d, d), (d, d, d))
+    assert lo == pytest.approx(11.0 / (8.0 * d ** 9), rel=1e-14)
+    assert hi == pytest.approx(11.0 / (8.0 * d ** 9), rel=1e-14)
+    lo, hi = omt.at_bounds((1.0, 2.5, 1.5), (1.0, 2.5, 1.5))  # collinear 0, 1, 2.5
+    assert lo == pytest.approx(-2.0 / (1.0 * 2.5 * 1.5) ** 3, rel=1e-14)
+    assert hi == pytest.approx(lo, rel=1e-14)
+    r = (3.0, 4.0, 5.0)  # right angle at node 1 (sides 12 = 3, 13 = 4, 23 = 5)
+    lo, hi = omt.at_bounds(r, r)
+    assert lo == pytest.approx(1.0 / (3.0 * 4.0 * 5.0) ** 3, rel=1e-14)
+    assert hi == pytest.approx(lo, rel=1e-14)
+    rng = workloads.rng(35)
+    for _ in range(20):
+        x = rng.normal(size=(3, 3))
+        s = (np.linalg.norm(x[0] - x[1]), np.linalg.norm(x[0] - x[2]), np.linalg.norm(x[1] - x[2]))
+        lo, hi = omt.at_bounds(s, s)
+        f = oracle_direct.at_phi(x[0], x[1], x[2])
+        assert lo == pytest.approx(f, rel=1e-9, abs=1e-12 * abs(f) + 1e-300)
+        assert hi == pytest.approx(f, rel=1e-9, abs=1e-12 * abs(f) + 1e-300)
+
+
+def test_at_bounds_tighten_as_the_boxes_shrink():
+    # the span of the bound goes to zero with the box size (linearly), and
+    # children's boxes never give a wider interval than their parent's
+    rng = workloads.rng(36)
+    c = rng.uniform(0, 8, size=(3, 3))
+    prev = None
+    for width in [2.0 ** -k for k in range(12)]:
+        lo, hi = c - width / 2, c + width / 2
+        plo, phi_ = omt.at_bounds(*_dist_bounds(lo, hi))
+        if prev is not None:
+            assert prev[0] <= plo and phi_ <= prev[1]
+            if width <= 2.0 ** -4:
+                assert (phi_ - plo) <= 0.6 * (prev[1] - prev[0])
+        prev = (plo, phi_)
+    f = oracle_direct.at_phi(c[0], c[1], c[2])
+    assert prev[0] <= f <= prev[1] and (prev[1] - prev[0]) < 0.05 * abs(f)
 
 
 def test_mc_try_meets_the_clt_bound():
@@ -256,19 +355,55 @@ def test_mc_try_meets_the_clt_bound():
     assert frac >= 1 - alpha - 4 * math.sqrt(alpha * (1 - alpha) / total), frac
 
 
-def test_magnitude_mode_exact_at_eps0_and_within_eps():
-    # the magnitude reading changes only which triples prune: eps = 0 is still
-    # the exhaustive sum, and on five separated clusters every point stays
+def test_two_sided_mode_exact_at_eps0_and_within_eps():
+    # the two-sided statistic changes only which triples prune: eps = 0 is
+    # still the exhaustive sum, and on separated clusters every point stays
     # within eps
     x = workloads.jittered_lattice(60, seed=4)
-    res = omt.multitree(x, eps=0.0, alpha=0.0, leaf_size=4, bound="magnitude")
+    res = omt.multitree(x, eps=0.0, alpha=0.0, leaf_size=4, bound="two_sided")
     np.testing.assert_allclose(res.phi, oracle_direct.phi(x), rtol=1e-12)
     x = blobs(24, [(0, 0, 0), (40, 0, 0), (0, 40, 0), (0, 0, 40), (40, 40, 40)], seed=11)
     eps = 0.05
-    res = omt.multitree(x, eps=eps, alpha=0.0, leaf_size=4, bound="magnitude")
+    res = omt.multitree(x, eps=eps, alpha=0.0, leaf_size=4, bound="two_sided")
     rel = np.abs(res.phi - oracle_direct.phi(x)) / np.abs(oracle_direct.phi(x))
     assert res.stats["det_prunes"] > 0
     assert np.all(res.coverage == math.comb(x.shape[0] - 1, 2))
     assert rel.max() <= eps
     with pytest.raises(ValueError):
-        omt.multitree(x, eps=eps, alpha=0.0, leaf_size=4, bound="other")
+        omt.multitree(x, eps=eps, alpha=0.0, leaf_size=4, bound="magnitude")
+
+
+def test_certified_reduces_to_the_paper_for_positive_bounds():
+    # with every running lower bound positive (a non-negative potential) the
+    # two-sided allowance is the paper's Phi^l(P) + T_i phi_lo, for the
+    # deterministic interval and for a Monte Carlo interval alike
+    rng = workloads.rng(41)
+    for _ in range(200):
+        lb = rng.uniform(0.1, 5.0, size=7)
+        ub = lb + rng.uniform(0.0, 3.0, size=7)
+        t = float(rng.integers(1, 1000))
+        lo = rng.uniform(0.0, 1e-3)
+        hi = lo + rng.uniform(0.0, 1e-3)
+        stat = (lb.min(), (-ub).min(), np.maximum(lb, -ub).min())
+        assert omt.certified("two_sided", stat, t, lo, hi) == omt.certified("signed", lb.min(), t, lo, hi)
+
+
+def test_certified_is_a_lower_bound_on_the_new_magnitude():
+    # brute force: after crediting t tuples with values in [lo, hi] to every
+    # point of a node, max(LB', -UB') of every point is at least the allowance
+    rng = workloads.rng(42)
+    for _ in range(500):
+        lb = rng.normal(size=9) * 3
+        ub = lb + rng.uniform(0.0, 4.0, size=9)
+        t = float(rng.integers(1, 50))
+        lo = rng.normal() * 0.05
+        hi = lo + rng.uniform(0.0, 0.1)
+        stat = (lb.min(), (-ub).min(), np.maximum(lb, -ub).min())
+        allow = omt.certified("two_sided", stat, t, lo, hi)
+        for v in rng.uniform(lo, hi, size=(20, 9)):  # any credited values
+            new_lb = lb + t * lo
+            new_ub = ub + t * hi
+            assert np.all(np.maximum(new_lb, -new_ub) >= allow - 1e-12)
+            # and the exact running total, which lies between them
+            tot = (lb + ub) / 2 + t * v
+            assert np.all(np.abs(tot) >= allow - 1e-12) or allow <= 0
