@@ -134,7 +134,8 @@ typedef struct mb_tree_s *mb_tree;
  * left child = node + 1).
  *   leaf_size : 1 .. 32 (MB_ERR_UNSUPPORTED above 32, MB_ERR_INVALID below 1)
  *   out       : receives the tree; release with mb_free_kdtree.
- * Coordinates must be finite (MB_ERR_INVALID otherwise).  Waits on stream.
+ * Coordinates must be finite (MB_ERR_INVALID otherwise) and, for N >= 3, no
+ * two points may coincide (MB_ERR_DEGENERATE).  Waits on stream.
  */
 mb_status mb_build_kdtree(const double *x, int64_t n, int32_t leaf_size, void *stream,
                           mb_tree *out);
@@ -169,25 +170,31 @@ typedef struct {
     uint64_t seed;     /* seed of the counter-based sampler                            */
     int32_t base_prec; /* arithmetic of the exhaustive base cases: MB_FP64 or MB_FP32C */
     int32_t chunk;     /* node triples processed per round of the device stack         */
-    int32_t bound;     /* MB_BOUND_SIGNED or MB_BOUND_MAGNITUDE (below)                */
+    int32_t bound;     /* MB_BOUND_SIGNED or MB_BOUND_TWO_SIDED (below)                */
     int32_t pad;
 } mb_mt_params;
 
 /*
- * What the node statistic Phi^l(P) of the prune rules holds.
- *   MB_BOUND_SIGNED: the paper's running lower bound of the contributions
- *     processed so far (Section 4.1, the deterministic-prune equation, and
- *     the relative termination rule of Algorithm 4), which presumes
- *     potentials >= 0.  The Axilrod-Teller potential is sign-indefinite; on
- *     point sets where Phi is negative for many points nothing prunes.
- *   MB_BOUND_MAGNITUDE: min over x in P of |running estimate of Phi(x)|
- *     (exact and pruned contributions so far), used without the delta^l and
- *     T_i (mu - z sigma) terms.  With near triples processed first (bands of
- *     spread) this approximates |Phi(x)| from below for the far triples; the
- *     guarantee becomes empirical (checked as the fraction of points within
- *     eps).  Not in the paper.
+ * What the node statistics of the prune rules hold.  Both accumulate, per
+ * point, what has been credited to it so far: exact base-case values, and
+ * for pruned node triples the ends of the interval that bounds them
+ * (T_i phi_lo .. T_i phi_hi for a deterministic prune, T_i (mu -+ z sigma_mu)
+ * for a Monte Carlo one).
+ *   MB_BOUND_SIGNED: the paper's running lower bound Phi^l (Section 4.1, the
+ *     deterministic-prune equation, and the relative termination rule of
+ *     Algorithm 4).  It presumes potentials >= 0: for a point whose Phi is
+ *     negative it stays negative, and no node triple holding that point is
+ *     pruned.
+ *   MB_BOUND_TWO_SIDED: a running upper bound is kept beside it, and the
+ *     allowance is a lower bound on max(lower, -upper), i.e. on |Phi| (the
+ *     relative bound of Definition 2.2) from whichever side has settled.
+ *     For potentials >= 0 it is the same rule as MB_BOUND_SIGNED.
+ * For the sign-indefinite Axilrod-Teller potential neither running sum is a
+ * bound on the final Phi (triples not yet credited may have either sign), so
+ * the eps guarantee is empirical in both modes: measured as the fraction of
+ * points within eps.
  */
-enum { MB_BOUND_SIGNED = 0, MB_BOUND_MAGNITUDE = 1 };
+enum { MB_BOUND_SIGNED = 0, MB_BOUND_TWO_SIDED = 1 };
 
 /* Defaults: eps 1e-2, tau 0, alpha 0.05, m_limit 128, m_min 30, zeta 128 (one
  * Monte Carlo sample - a counter-based draw, an index map, gathers and a
@@ -215,14 +222,19 @@ typedef struct {
 /*
  * Approximate Phi(x) for all points by the triple-tree traversal
  * (Algorithm 2 with CanSummarize / Summarize of Section 4 and Algorithms
- * 3-5), guaranteeing |Phi~ - Phi| <= eps |Phi| + tau per point in the sense
- * of Definition 2.3 (with alpha = 0, Theorem 5.1's deterministic form).
- * For the sign-indefinite Axilrod-Teller potential the deterministic bound
- * uses phi in [-2 R, 11/8 R], R = (product of the three box distances)^-3,
- * and the running lower bound of the paper is a heuristic (the sum of
- * lower bounds of what has been credited so far).
- *   tree     : a tree of the same points built with the same leaf_size, or
- *              NULL to build one internally (then leaf_size is used).
+ * 3-5), aiming at |Phi~ - Phi| <= eps |Phi| + tau per point in the sense of
+ * Definition 2.3 (with alpha = 0, Theorem 5.1's deterministic form).  The
+ * deterministic prune bounds phi over every triangle whose sides lie between
+ * the smallest and largest distances d^l, d^u of the three node boxes
+ * (phi = R g, R = (r_12 r_13 r_23)^-3 over its range, g = 1 + 3 cos cos cos
+ * from exact ranges of the cosines, clipped to [-2, 11/8]); every d^l is
+ * raised to the closest-pair distance of the points.  Because the
+ * Axilrod-Teller potential is sign-indefinite, the running statistics are
+ * not bounds on the final Phi and the guarantee is checked empirically (see
+ * the bound modes above).
+ *   tree     : a tree built by mb_build_kdtree from these same points (the
+ *              coordinates are compared bit for bit on the device), or NULL
+ *              to build one internally with leaf_size.
  *   params   : host pointer (NULL = defaults).
  *   phi      : device, N doubles, input order.
  *   coverage : device, N int64 or NULL; receives the number of particle

@@ -23,7 +23,7 @@ STATUS_NAMES = {
     5: "MB_ERR_UNSUPPORTED",
 }
 PREC = {"fp64": 0, "fp32c": 1}
-BOUND = {"signed": 0, "magnitude": 1}
+BOUND = {"signed": 0, "two_sided": 1}
 
 
 class MBError(RuntimeError):

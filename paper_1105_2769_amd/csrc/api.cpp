@@ -169,9 +169,8 @@ mb_status mb_build_kdtree(const double *x, int64_t n, int32_t leaf_size, void *s
     if (n >= ((int64_t)1 << 31)) return fail(MB_ERR_UNSUPPORTED, "n must be < 2^31");
     hipStream_t s = (hipStream_t)stream;
     ValidateOut v{};
-    mb_status st = validate_points(x, n, s, &v);
+    mb_status st = check_points(x, n, s, &v);
     if (st != MB_OK) return st;
-    if (v.nonfinite) return fail(MB_ERR_INVALID, "non-finite coordinate");
     DeviceTree *t = nullptr;
     if ((st = tree_build(x, n, leaf_size, s, &t)) != MB_OK) return st;
     *out = reinterpret_cast<mb_tree>(t);
@@ -252,7 +251,7 @@ mb_status mb_eval_multitree(const double *x, int64_t n, int32_t leaf_size,
     if (n < 0 || (n > 0 && (!x || !phi))) return fail(MB_ERR_INVALID, "bad points or output");
     if (!(p.eps_rel >= 0.0) || !(p.tau_abs >= 0.0) || !(p.alpha >= 0.0 && p.alpha < 1.0) ||
         p.m_limit < 2 || p.m_min < 2 || !(p.zeta >= 0.0) || p.chunk < 1 ||
-        (p.bound != MB_BOUND_SIGNED && p.bound != MB_BOUND_MAGNITUDE) ||
+        (p.bound != MB_BOUND_SIGNED && p.bound != MB_BOUND_TWO_SIDED) ||
         (p.base_prec != MB_FP64 && p.base_prec != MB_FP32C))
         return fail(MB_ERR_INVALID, "bad traversal parameters");
     if (n >= ((int64_t)1 << 31)) return fail(MB_ERR_UNSUPPORTED, "n must be < 2^31");
@@ -266,6 +265,9 @@ mb_status mb_eval_multitree(const double *x, int64_t n, int32_t leaf_size,
     DeviceTree *own = nullptr;
     if (t) {
         if (t->h.n != n) return fail(MB_ERR_INVALID, "tree built for a different point count");
+        bool same = false;
+        if ((st = tree_matches_points(t, x, n, s, &same)) != MB_OK) return st;
+        if (!same) return fail(MB_ERR_INVALID, "tree built for other points");
     } else {
         if (leaf_size < 1) return fail(MB_ERR_INVALID, "leaf_size < 1");
         if (leaf_size > 32) return fail(MB_ERR_UNSUPPORTED, "leaf_size > 32");

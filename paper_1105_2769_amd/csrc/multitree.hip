@@ -26,10 +26,15 @@
 // pruned when their turn comes.
 //
 // Readings for the Axilrod-Teller potential (sign-indefinite, not monotone):
-// phi lies in [-2 R^u, 11/8 R^u], R^u = (d^l_12 d^l_13 d^l_23)^-3, so the
-// deterministic test uses span = 27/8 R^u and delta^l_i = T_i (-2 R^u); the
-// Monte Carlo stop rule is z sigma_mu <= (eps (Phi^l + T_i (mu - z sigma_mu))
-// + tau) / T_root with at least m_min samples.
+// phi = R g with R = (r_12 r_13 r_23)^-3 and g = 1 + 3 cos cos cos is bounded
+// over every triangle whose sides lie between the smallest and largest box
+// distances d^l, d^u of the three node pairs (at_bounds below), giving
+// [phi_lo, phi_hi]: the deterministic test compares phi_hi - phi_lo with the
+// allowance and delta^l_i = T_i phi_lo (Section 4, Section 4.1).  The Monte
+// Carlo stop rule is z sigma_mu <= (eps (Phi^l + T_i (mu - z sigma_mu)) +
+// tau) / T_root with at least m_min samples.  Besides the paper's running
+// lower bound (signed statistic) a two-sided statistic keeps a running upper
+// bound too and certifies |Phi| from whichever side has settled.
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
@@ -54,7 +59,7 @@ struct Item {
 
 struct MtCounters {
     unsigned long long n_base, n_mc;
-    unsigned long long visited, det_prunes, mc_prunes, mc_failed, base_cases, base_triples,
+    unsigned long long det_prunes, mc_prunes, mc_failed, base_cases, base_triples,
         mc_samples;
 };
 
@@ -67,7 +72,15 @@ struct MtConst {
     uint32_t seed32;
     int use_mc;
     int want_cov;
-    int magnitude;  // node_phil holds min |running estimate| (MB_BOUND_MAGNITUDE)
+    int two_sided;  // allowance from both running bounds (MB_BOUND_TWO_SIDED)
+};
+
+// Node statistics of the prune rules, refreshed once per round: over the
+// points x of the node, pos = min LB(x), neg = min -UB(x) and
+// mix = min max(LB(x), -UB(x)), with LB, UB the running lower and upper
+// bounds of what has been credited to x so far.
+struct NodeStats {
+    const double *pos, *neg, *mix;
 };
 
 struct NodeView {
@@ -86,6 +99,88 @@ __device__ __forceinline__ double box_min_dist(const double *lo1, const double *
         s2 = fma(g, g, s2);
     }
     return sqrt(s2);
+}
+
+__device__ __forceinline__ double box_max_dist(const double *lo1, const double *hi1,
+                                               const double *lo2, const double *hi2) {
+    double s2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double g = fmax(fabs(hi2[c] - lo1[c]), fabs(hi1[c] - lo2[c]));
+        s2 = fma(g, g, s2);
+    }
+    return sqrt(s2);
+}
+
+// Cosine of the angle between the sides of squared lengths a, b facing the
+// side of squared length c (law of cosines).
+__device__ __forceinline__ double cos_law(double a, double b, double c) {
+    return (a + b - c) / (2.0 * sqrt(a * b));
+}
+
+// Range of cos_law over a in [a0, a1], b in [b0, b1], c in [c0, c1] (all
+// positive).  cos_law falls with c.  For fixed c it has no stationary point
+// inside the (a, b) box, and along an edge it falls then rises, with its
+// only minimum where the angle facing the fixed side is right (b = a - c or
+// a = b - c), value sqrt(1 - c / fixed side).  So the top is a corner at c0
+// and the bottom a corner or such an edge point at c1.  Clipped to [-1, 1],
+// where the cosines of real triangles lie.
+__device__ __forceinline__ void cos_range(double a0, double a1, double b0, double b1, double c0,
+                                          double c1, double &lo, double &hi) {
+    hi = fmax(fmax(cos_law(a0, b0, c0), cos_law(a0, b1, c0)),
+              fmax(cos_law(a1, b0, c0), cos_law(a1, b1, c0)));
+    lo = fmin(fmin(cos_law(a0, b0, c1), cos_law(a0, b1, c1)),
+              fmin(cos_law(a1, b0, c1), cos_law(a1, b1, c1)));
+    const double ea[2] = {a0, a1}, eb[2] = {b0, b1};
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const double bs = ea[e] - c1;  // edge a = ea[e]: right angle where b = a - c
+        if (bs > b0 && bs < b1) lo = fmin(lo, sqrt(1.0 - c1 / ea[e]));
+        const double as = eb[e] - c1;  // edge b = eb[e]
+        if (as > a0 && as < a1) lo = fmin(lo, sqrt(1.0 - c1 / eb[e]));
+    }
+    lo = fmax(lo, -1.0);
+    hi = fmin(hi, 1.0);
+}
+
+// [phi_lo, phi_hi] over every triangle whose sides r_12, r_13, r_23 lie in
+// [l12, u12], [l13, u13], [l23, u23] (all > 0): phi = R g, R between
+// (u12 u13 u23)^-3 and (l12 l13 l23)^-3; g = 1 + 3 c_1 c_2 c_3 from the
+// cosine ranges at the three vertices (interval product over its eight
+// corners), clipped to [-2, 11/8] (collinear, equilateral).
+__device__ __forceinline__ void at_bounds(double l12, double l13, double l23, double u12,
+                                          double u13, double u23, double &phi_lo,
+                                          double &phi_hi) {
+    const double a0 = l12 * l12, a1 = u12 * u12;
+    const double b0 = l13 * l13, b1 = u13 * u13;
+    const double c0 = l23 * l23, c1 = u23 * u23;
+    double x0, x1, y0, y1, z0, z1;
+    cos_range(a0, a1, b0, b1, c0, c1, x0, x1);  // vertex 1: sides 12, 13; facing 23
+    cos_range(a0, a1, c0, c1, b0, b1, y0, y1);  // vertex 2: sides 12, 23; facing 13
+    cos_range(b0, b1, c0, c1, a0, a1, z0, z1);  // vertex 3: sides 13, 23; facing 12
+    const double p00 = x0 * y0, p01 = x0 * y1, p10 = x1 * y0, p11 = x1 * y1;
+    const double q_lo = fmin(fmin(p00, p01), fmin(p10, p11));
+    const double q_hi = fmax(fmax(p00, p01), fmax(p10, p11));
+    const double pmin = fmin(fmin(q_lo * z0, q_lo * z1), fmin(q_hi * z0, q_hi * z1));
+    const double pmax = fmax(fmax(q_lo * z0, q_lo * z1), fmax(q_hi * z0, q_hi * z1));
+    const double g_lo = fmax(-2.0, fma(3.0, pmin, 1.0));
+    const double g_hi = fmin(1.375, fma(3.0, pmax, 1.0));
+    const double pl = l12 * l13 * l23, pu = u12 * u13 * u23;
+    const double r_hi = 1.0 / (pl * pl * pl), r_lo = 1.0 / (pu * pu * pu);
+    phi_lo = g_lo * (g_lo >= 0.0 ? r_lo : r_hi);
+    phi_hi = g_hi * (g_hi >= 0.0 ? r_hi : r_lo);
+}
+
+// Lower bound on |Phi| of every point of node v once it is credited t tuples
+// with values in [lo, hi].  Signed (the paper): Phi^l(v) + t lo.  Two-sided:
+// the largest of min LB + t lo, min(-UB) - t hi and
+// min max(LB, -UB) + min(t lo, -t hi), each a lower bound on the new
+// max(LB, -UB) of every point; with all LB > 0 the first is the paper's.
+__device__ __forceinline__ double certified(const MtConst &k, const NodeStats &ns, int v, double t,
+                                            double lo, double hi) {
+    const double sg = ns.pos[v] + t * lo;
+    if (!k.two_sided) return sg;
+    return fmax(fmax(sg, ns.neg[v] - t * hi), ns.mix[v] + fmin(t * lo, -t * hi));
 }
 
 // phi of three points from binary64 coordinates (law-of-cosines form).
@@ -189,8 +284,8 @@ __device__ __forceinline__ void emit_children(const NodeView &nv, const Item &it
 
 // 1. classification of the popped triples
 __global__ __launch_bounds__(256) void classify_kernel(
-    const Item *__restrict__ items, int n_items, NodeView nv, const double *__restrict__ node_phil,
-    double *__restrict__ node_acc, double *__restrict__ node_lo,
+    const Item *__restrict__ items, int n_items, NodeView nv, NodeStats ns,
+    double *__restrict__ node_acc, double *__restrict__ node_lo, double *__restrict__ node_hi,
     unsigned long long *__restrict__ node_cov, MtConst k, MtCounters *__restrict__ ctr,
     Item *__restrict__ mc_list, Item *__restrict__ base_list, Item *__restrict__ child_buf,
     uint8_t *__restrict__ child_flag, double spread_limit, Item *__restrict__ defer_buf,
@@ -224,35 +319,32 @@ __global__ __launch_bounds__(256) void classify_kernel(
         defer_flag[slot] = 1;
         return;
     }
-    atomicAdd(&ctr->visited, 1ull);
 
-    // deterministic prune (three distinct nodes): every pair of points is at
-    // least max(d^l, r_min) apart, so each phi of the triple lies in
-    // [-2 R, 11/8 R] with R = (product of those distances)^-3
+    // deterministic prune (three distinct nodes).  No two points are closer
+    // than r_min, so every d^l is raised to it; d^u is the farthest pair of
+    // box corners.
     if (r.n_roles == 3) {
         const double e12 = fmax(d12, k.r_min), e13 = fmax(d13, k.r_min), e23 = fmax(d23, k.r_min);
-        if (e12 > 0.0 && e13 > 0.0 && e23 > 0.0) {
-            const double prod = e12 * e13 * e23;
-            const double ru = 1.0 / (prod * prod * prod);
-            const double phi_lo = -2.0 * ru, phi_hi = 1.375 * ru;
-            const double span = 3.375 * ru;
-            double allow = INFINITY;
-            for (int q = 0; q < 3; ++q)
-                allow = fmin(allow, k.magnitude ? node_phil[r.node[q]]
-                                                : node_phil[r.node[q]] + (double)r.t[q] * phi_lo);
-            if (span <= (k.eps * allow + k.tau) / k.t_root) {
-                // monopole estimate at the centroids, kept inside the bound interval
-                double phic = phi3(nv.centroid + 3 * p1, nv.centroid + 3 * p2,
-                                   nv.centroid + 3 * p3);
-                phic = isfinite(phic) ? fmin(fmax(phic, phi_lo), phi_hi) : 0.0;
-                for (int q = 0; q < 3; ++q) {
-                    atomicAdd(&node_acc[r.node[q]], (double)r.t[q] * phic);
-                    atomicAdd(&node_lo[r.node[q]], (double)r.t[q] * phi_lo);
-                    if (k.want_cov) atomicAdd(&node_cov[r.node[q]], (unsigned long long)r.t[q]);
-                }
-                atomicAdd(&ctr->det_prunes, 1ull);
-                return;
+        const double u12 = fmax(box_max_dist(lo + 3 * p1, hi + 3 * p1, lo + 3 * p2, hi + 3 * p2), e12);
+        const double u13 = fmax(box_max_dist(lo + 3 * p1, hi + 3 * p1, lo + 3 * p3, hi + 3 * p3), e13);
+        const double u23 = fmax(box_max_dist(lo + 3 * p2, hi + 3 * p2, lo + 3 * p3, hi + 3 * p3), e23);
+        double phi_lo, phi_hi;
+        at_bounds(e12, e13, e23, u12, u13, u23, phi_lo, phi_hi);
+        double allow = INFINITY;
+        for (int q = 0; q < 3; ++q)
+            allow = fmin(allow, certified(k, ns, r.node[q], (double)r.t[q], phi_lo, phi_hi));
+        if (phi_hi - phi_lo <= (k.eps * allow + k.tau) / k.t_root) {
+            // monopole estimate at the centroids, kept inside the bound interval
+            double phic = phi3(nv.centroid + 3 * p1, nv.centroid + 3 * p2, nv.centroid + 3 * p3);
+            phic = isfinite(phic) ? fmin(fmax(phic, phi_lo), phi_hi) : 0.5 * (phi_lo + phi_hi);
+            for (int q = 0; q < 3; ++q) {
+                atomicAdd(&node_acc[r.node[q]], (double)r.t[q] * phic);
+                atomicAdd(&node_lo[r.node[q]], (double)r.t[q] * phi_lo);
+                atomicAdd(&node_hi[r.node[q]], (double)r.t[q] * phi_hi);
+                if (k.want_cov) atomicAdd(&node_cov[r.node[q]], (unsigned long long)r.t[q]);
             }
+            atomicAdd(&ctr->det_prunes, 1ull);
+            return;
         }
     }
     // Monte Carlo candidate
@@ -385,8 +477,8 @@ constexpr int kMcGroup = 32;
 __device__ McPoint mc_point_group(const Item &it, char cs, int slot, int64_t off, int64_t xr,
                                   int64_t n1, int64_t n2, int64_t n3, const int *pn,
                                   const NodeView &nv, const double *__restrict__ xs, double t,
-                                  double plo, const MtConst &k, const volatile int *failed,
-                                  int gl, int g0) {
+                                  const NodeStats &ns, int node, const MtConst &k,
+                                  const volatile int *failed, int gl, int g0) {
     constexpr int W = kMcGroup;
     const double *xp = xs + 3 * xr;
     double f0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -417,7 +509,7 @@ __device__ McPoint mc_point_group(const Item &it, char cs, int slot, int64_t off
         const double mean = f0 + t1 / m;
         const double var = sidx >= 1 ? fmax(t2 - t1 * t1 / m, 0.0) / (m - 1.0) : 0.0;
         const double sig = sqrt(var / m);
-        const double credit = k.magnitude ? plo : plo + t * (mean - k.z * sig);
+        const double credit = certified(k, ns, node, t, mean - k.z * sig, mean + k.z * sig);
         const bool cond = valid && sidx >= 1 && k.z * sig <= (k.eps * credit + k.tau) / k.t_root;
         const bool ok = cond && sidx + 1 >= k.m_min;
         const bool stop = valid && (ok || sidx + 1 == k.m_limit);
@@ -449,12 +541,12 @@ __device__ McPoint mc_point_group(const Item &it, char cs, int slot, int64_t off
 // test), in which case the points are credited T_i mu and
 // T_i (mu - z sigma_mu).
 __global__ __launch_bounds__(kMcThreads) void mc_kernel(
-    const Item *__restrict__ mc_list, NodeView nv, const double *__restrict__ xs,
-    const double *__restrict__ node_phil, double *__restrict__ est, double *__restrict__ lb,
+    const Item *__restrict__ mc_list, NodeView nv, const double *__restrict__ xs, NodeStats ns,
+    double *__restrict__ est, double *__restrict__ dev,
     unsigned long long *__restrict__ node_cov, MtConst k, MtCounters *__restrict__ ctr,
     Item *__restrict__ base_list, Item *__restrict__ child_buf, uint8_t *__restrict__ child_flag) {
     __shared__ int failed;
-    __shared__ double c_mean[kMcCache], c_low[kMcCache];
+    __shared__ double c_mean[kMcCache], c_dev[kMcCache];
     const int lane = threadIdx.x & 63;
     // groups of kMcGroup lanes, each sampling its own points
     constexpr int kGroups = kMcThreads / kMcGroup;
@@ -475,12 +567,14 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
             sz[q] = nv.end[r.node[q]] - nv.begin[r.node[q]];
             total += sz[q];
         }
-        // points of the node with the smallest Phi^l (the tightest allowance)
-        // first: a triple that fails usually fails there, and the test ends at
-        // the first failure.  The order changes no point's samples or result.
+        // points of the node with the smallest allowance first: a triple that
+        // fails usually fails there, and the test ends at the first failure.
+        // The order changes no point's samples or result.
         int qo[3] = {0, 1, 2};
+        double key[3];
+        for (int q = 0; q < r.n_roles; ++q) key[q] = certified(k, ns, r.node[q], 0.0, 0.0, 0.0);
         for (int a = 1; a < r.n_roles; ++a)
-            for (int b = a; b > 0 && node_phil[r.node[qo[b]]] < node_phil[r.node[qo[b - 1]]]; --b) {
+            for (int b = a; b > 0 && key[qo[b]] < key[qo[b - 1]]; --b) {
                 const int tmp = qo[b];
                 qo[b] = qo[b - 1];
                 qo[b - 1] = tmp;
@@ -497,8 +591,7 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
             const int q = qo[qq];
             const int64_t xr = nv.begin[r.node[q]] + off;
             const McPoint res = mc_point_group(it, cs, r.slot[q], off, xr, n1, n2, n3, pn, nv, xs,
-                                               (double)r.t[q], node_phil[r.node[q]], k, &failed,
-                                               gl, g0);
+                                               (double)r.t[q], ns, r.node[q], k, &failed, gl, g0);
             drawn += res.drawn;
             if (!res.pass) {
                 if (gl == 0) failed = 1;
@@ -506,7 +599,7 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
             }
             if (e < kMcCache && gl == 0) {
                 c_mean[e] = res.mean;
-                c_low[e] = res.mean - k.z * res.sig;
+                c_dev[e] = k.z * res.sig;
             }
         }
         __syncthreads();
@@ -527,19 +620,21 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
             const int q = qo[qq];
             const int64_t xr = nv.begin[r.node[q]] + off;
             const double t = (double)r.t[q];
-            double mean, low;
+            double mean, half;
             if (e < kMcCache) {
                 mean = c_mean[e];
-                low = c_low[e];
+                half = c_dev[e];
             } else {
                 const McPoint res = mc_point_group(it, cs, r.slot[q], off, xr, n1, n2, n3, pn, nv,
-                                                   xs, t, node_phil[r.node[q]], k, nullptr, gl, g0);
+                                                   xs, t, ns, r.node[q], k, nullptr, gl, g0);
                 mean = res.mean;
-                low = res.mean - k.z * res.sig;
+                half = k.z * res.sig;
             }
+            // Algorithm 5: the estimate gains T_i mu; the running bounds gain
+            // T_i (mu -+ z sigma_mu), kept as est -+ dev
             if (gl == 0) {
                 atomicAdd(&est[xr], t * mean);
-                atomicAdd(&lb[xr], t * low);
+                atomicAdd(&dev[xr], t * half);
             }
         }
         if (threadIdx.x == 0) {
@@ -611,7 +706,7 @@ struct alignas(16) BaseLds {
 template <typename T>
 __global__ __launch_bounds__(kBaseThreads) void base_kernel(
     const Item *__restrict__ base_list, NodeView nv, const double *__restrict__ xs,
-    double *__restrict__ est, double *__restrict__ lb, unsigned long long *__restrict__ node_cov,
+    double *__restrict__ est, unsigned long long *__restrict__ node_cov,
     MtConst k, MtCounters *__restrict__ ctr) {
     __shared__ BaseLds<T> s;
     const int tid = threadIdx.x;
@@ -722,26 +817,19 @@ __global__ __launch_bounds__(kBaseThreads) void base_kernel(
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 const int il = 8 * m + 2 * wave + ih;
-                if (il < n1) {
-                    atomicAdd(&est[b1 + il], vi[m]);
-                    atomicAdd(&lb[b1 + il], vi[m]);
-                }
+                if (il < n1) atomicAdd(&est[b1 + il], vi[m]);
             }
         }
         atomicAdd(&s.pk[kl], acck);
         __syncthreads();
         if (tid < kLeafMax) {
-            if (tid < n3) {
-                atomicAdd(&est[b3 + tid], s.pk[tid]);
-                atomicAdd(&lb[b3 + tid], s.pk[tid]);
-            }
+            if (tid < n3) atomicAdd(&est[b3 + tid], s.pk[tid]);
         } else if (tid < 2 * kLeafMax) {
             const int j = tid - kLeafMax;
             if (j < n2) {
                 double v = 0.0;
                 for (int q = 0; q < kBaseSlots; ++q) v += s.pj[j][q];
                 atomicAdd(&est[b2 + j], v);
-                atomicAdd(&lb[b2 + j], v);
             }
         } else if (tid == 2 * kLeafMax) {
             ++my_cases;
@@ -778,47 +866,57 @@ __global__ void zero_u64_kernel(unsigned long long *__restrict__ p, int64_t n) {
 }
 
 __global__ void zero_counters_kernel(MtCounters *ctr) {
-    ctr->n_base = ctr->n_mc = ctr->visited = ctr->det_prunes = ctr->mc_prunes = 0;
+    ctr->n_base = ctr->n_mc = ctr->det_prunes = ctr->mc_prunes = 0;
     ctr->mc_failed = ctr->base_cases = ctr->base_triples = ctr->mc_samples = 0;
 }
 
-// 5. Phi^l(P) = min over x in P of LB(x), LB(x) = lb[x] + sum of the node
-// lower-bound increments of x's leaf and its ancestors.  Top-down sums and
-// bottom-up minima run in one workgroup, depth by depth.
+// 5. Node statistics.  Per point, LB(x) = est[x] - dev[x] + (node
+// lower-bound increments of x's leaf and its ancestors) and UB(x) = est[x] +
+// dev[x] + (node upper-bound increments): exact base-case values and Monte
+// Carlo means are in est, the Monte Carlo half-widths T_i z sigma_mu in dev,
+// the deterministic prunes' T_i phi_lo and T_i phi_hi on the nodes.  Top-down
+// path sums and bottom-up minima run in one workgroup, depth by depth.
 __global__ __launch_bounds__(1024) void refresh_down_kernel(const int32_t *__restrict__ depth_nodes,
                                                             const int *__restrict__ depth_off,
                                                             int n_depths,
                                                             const int32_t *__restrict__ parent,
                                                             const double *__restrict__ node_lo,
-                                                            double *__restrict__ cum) {
+                                                            const double *__restrict__ node_hi,
+                                                            double *__restrict__ cum_lo,
+                                                            double *__restrict__ cum_hi) {
     for (int d = 0; d < n_depths; ++d) {
         for (int e = depth_off[d] + threadIdx.x; e < depth_off[d + 1]; e += blockDim.x) {
             const int v = depth_nodes[e];
-            cum[v] = node_lo[v] + (parent[v] >= 0 ? cum[parent[v]] : 0.0);
+            const int u = parent[v];
+            cum_lo[v] = node_lo[v] + (u >= 0 ? cum_lo[u] : 0.0);
+            cum_hi[v] = node_hi[v] + (u >= 0 ? cum_hi[u] : 0.0);
         }
         __syncthreads();
     }
 }
 
-// Leaf statistic: min over the leaf's points of lb + (node lower-bound
-// increments on the path), or, for magnitude bounds, of |est + (node
-// accumulators on the path)|; `cum` holds the matching path sums.
+// Leaf statistics: minima over the leaf's points of LB, -UB and max(LB, -UB).
 __global__ void refresh_leaf_kernel(const int32_t *__restrict__ leaves, int n_leaves,
                                     const int32_t *__restrict__ begin,
-                                    const int32_t *__restrict__ end, const double *__restrict__ lb,
-                                    const double *__restrict__ cum, int magnitude,
-                                    double *__restrict__ phil) {
+                                    const int32_t *__restrict__ end, const double *__restrict__ est,
+                                    const double *__restrict__ dev,
+                                    const double *__restrict__ cum_lo,
+                                    const double *__restrict__ cum_hi, double *__restrict__ pos,
+                                    double *__restrict__ neg, double *__restrict__ mix) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n_leaves) return;
     const int v = leaves[e];
-    double mn = INFINITY;
-    if (magnitude) {
-        for (int r = begin[v]; r < end[v]; ++r) mn = fmin(mn, fabs(lb[r] + cum[v]));
-        phil[v] = mn;
-    } else {
-        for (int r = begin[v]; r < end[v]; ++r) mn = fmin(mn, lb[r]);
-        phil[v] = mn + cum[v];
+    double mp = INFINITY, mn = INFINITY, mm = INFINITY;
+    for (int r = begin[v]; r < end[v]; ++r) {
+        const double l = est[r] - dev[r] + cum_lo[v];
+        const double u = est[r] + dev[r] + cum_hi[v];
+        mp = fmin(mp, l);
+        mn = fmin(mn, -u);
+        mm = fmin(mm, fmax(l, -u));
     }
+    pos[v] = mp;
+    neg[v] = mn;
+    mix[v] = mm;
 }
 
 __global__ __launch_bounds__(1024) void refresh_up_kernel(const int32_t *__restrict__ depth_nodes,
@@ -826,11 +924,18 @@ __global__ __launch_bounds__(1024) void refresh_up_kernel(const int32_t *__restr
                                                           int n_depths,
                                                           const int32_t *__restrict__ left,
                                                           const int32_t *__restrict__ right,
-                                                          double *__restrict__ phil) {
+                                                          double *__restrict__ pos,
+                                                          double *__restrict__ neg,
+                                                          double *__restrict__ mix) {
     for (int d = n_depths - 1; d >= 0; --d) {
         for (int e = depth_off[d] + threadIdx.x; e < depth_off[d + 1]; e += blockDim.x) {
             const int v = depth_nodes[e];
-            if (left[v] >= 0) phil[v] = fmin(phil[left[v]], phil[right[v]]);
+            const int a = left[v], b = right[v];
+            if (a >= 0) {
+                pos[v] = fmin(pos[a], pos[b]);
+                neg[v] = fmin(neg[a], neg[b]);
+                mix[v] = fmin(mix[a], mix[b]);
+            }
         }
         __syncthreads();
     }
@@ -854,6 +959,20 @@ __global__ void topdown_kernel(int n, const int32_t *__restrict__ leaf_of,
     if (coverage) coverage[perm[r]] = (int64_t)cv;
 }
 
+// Whether the tree's depth-first copy of the points is the caller's x in the
+// tree's order, bit for bit: flag[0] is set at any difference.
+__global__ void same_points_kernel(const double *__restrict__ x, const int32_t *__restrict__ perm,
+                                   const double *__restrict__ xs, int n, int *__restrict__ flag) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int64_t i = perm[r];
+    bool diff = false;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        diff |= __double_as_longlong(x[3 * i + c]) != __double_as_longlong(xs[3 * (int64_t)r + c]);
+    if (diff) atomicOr(flag, 1);
+}
+
 template <typename T>
 mb_status dalloc(Scratch &sc, T **p, size_t count, hipStream_t s) {
     mb_status st = sc.alloc(sizeof(T) * (count ? count : 1), s);
@@ -862,6 +981,28 @@ mb_status dalloc(Scratch &sc, T **p, size_t count, hipStream_t s) {
 }
 
 }  // namespace
+
+mb_status tree_matches_points(const DeviceTree *t, const double *x, int64_t n, hipStream_t s,
+                              bool *same) {
+    *same = false;
+    if (t->h.n != n) return MB_OK;
+    if (n == 0) {
+        *same = true;
+        return MB_OK;
+    }
+    Scratch sc;
+    int *flag;
+    mb_status st = dalloc(sc, &flag, 1, s);
+    if (st != MB_OK) return st;
+    MB_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    same_points_kernel<<<(int)((n + 255) / 256), 256, 0, s>>>(x, t->perm, t->xs, (int)n, flag);
+    MB_HIP(hipGetLastError());
+    int h = 1;
+    MB_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    MB_HIP(hipStreamSynchronize(s));
+    *same = h == 0;
+    return MB_OK;
+}
 
 double normal_quantile_upper(double alpha_half) {
     // z with P(Z > z) = alpha_half, by Newton's method on erfc
@@ -895,25 +1036,31 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
         if (t->h.left[v] < 0) leaves.push_back(v);
     const int n_depths = t->h.max_depth + 1;
 
-    Scratch s_est, s_lb, s_acc, s_lo, s_cov, s_phil, s_cum, s_ctr, s_leaves, s_doff;
-    double *est, *lb, *node_acc, *node_lo, *node_phil, *cum;
+    // per point: est (exact values and Monte Carlo means), dev (Monte Carlo
+    // half-widths); per node: accumulators, bound increments, statistics and
+    // path sums of the increments
+    Scratch s_pt, s_nd, s_cov, s_ctr, s_leaves, s_doff;
+    double *pt, *nd;
     unsigned long long *node_cov;
     MtCounters *ctr;
     int32_t *d_leaves;
     int *d_doff;
-    if ((st = dalloc(s_est, &est, n, s)) || (st = dalloc(s_lb, &lb, n, s)) ||
-        (st = dalloc(s_acc, &node_acc, M, s)) || (st = dalloc(s_lo, &node_lo, M, s)) ||
-        (st = dalloc(s_cov, &node_cov, M, s)) || (st = dalloc(s_phil, &node_phil, M, s)) ||
-        (st = dalloc(s_cum, &cum, M, s)) || (st = dalloc(s_ctr, &ctr, 1, s)) ||
+    if ((st = dalloc(s_pt, &pt, 2 * (size_t)n, s)) || (st = dalloc(s_nd, &nd, 8 * (size_t)M, s)) ||
+        (st = dalloc(s_cov, &node_cov, M, s)) || (st = dalloc(s_ctr, &ctr, 1, s)) ||
         (st = dalloc(s_leaves, &d_leaves, leaves.size(), s)) ||
         (st = dalloc(s_doff, &d_doff, t->depth_off.size(), s)))
         return st;
+    double *est = pt, *dev = pt + n;
+    double *node_acc = nd, *node_lo = nd + M, *node_hi = nd + 2 * (size_t)M;
+    double *st_pos = nd + 3 * (size_t)M, *st_neg = nd + 4 * (size_t)M, *st_mix = nd + 5 * (size_t)M;
+    double *cum_lo = nd + 6 * (size_t)M, *cum_hi = nd + 7 * (size_t)M;
+    const NodeStats ns{st_pos, st_neg, st_mix};
     MB_HIP(hipMemcpyAsync(d_leaves, leaves.data(), sizeof(int32_t) * leaves.size(),
                           hipMemcpyHostToDevice, s));
     MB_HIP(hipMemcpyAsync(d_doff, t->depth_off.data(), sizeof(int) * t->depth_off.size(),
                           hipMemcpyHostToDevice, s));
-    for (double *p : {est, lb}) zero_doubles(p, n, s);
-    for (double *p : {node_acc, node_lo, node_phil, cum}) zero_doubles(p, M, s);
+    if ((st = zero_doubles(pt, 2 * (int64_t)n, s)) != MB_OK) return st;
+    if ((st = zero_doubles(nd, 8 * (int64_t)M, s)) != MB_OK) return st;
     zero_u64_kernel<<<(M + 255) / 256, 256, 0, s>>>(node_cov, M);
     zero_counters_kernel<<<1, 1, 0, s>>>(ctr);
 
@@ -961,7 +1108,7 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
     k.seed32 = (uint32_t)(prm.seed ^ (prm.seed >> 32));
     k.use_mc = prm.alpha > 0.0 ? 1 : 0;
     k.want_cov = coverage ? 1 : 0;
-    k.magnitude = prm.bound == 1 ? 1 : 0;
+    k.two_sided = prm.bound == MB_BOUND_TWO_SIDED ? 1 : 0;
 
     auto grow = [&](Scratch &sc, Item *&buf, int64_t &c, int64_t keep, int64_t need) -> mb_status {
         if (need <= c) return MB_OK;
@@ -980,7 +1127,7 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
         return MB_OK;
     };
 
-    int64_t max_stack = 1, rounds = 0;
+    int64_t max_stack = 1, rounds = 0, visited = 0;
     const bool trace = std::getenv("MB_TRACE") != nullptr;
     auto last_print = std::chrono::steady_clock::now();
     for (;;) {
@@ -991,16 +1138,16 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
                 MtCounters hc;
                 MB_HIP(hipMemcpy(&hc, ctr, sizeof hc, hipMemcpyDeviceToHost));
                 std::vector<double> pl(M);
-                MB_HIP(hipMemcpy(pl.data(), node_phil, sizeof(double) * M, hipMemcpyDeviceToHost));
+                MB_HIP(hipMemcpy(pl.data(), st_pos, sizeof(double) * M, hipMemcpyDeviceToHost));
                 std::vector<double> lv;
                 for (int32_t v : leaves) lv.push_back(pl[v]);
                 std::sort(lv.begin(), lv.end());
                 std::fprintf(stderr,
-                             "[mb multitree] end of band %d (spread <= %g): round %lld visited %llu "
+                             "[mb multitree] end of band %d (spread <= %g): round %lld visited %lld "
                              "det %llu mc %llu/%llu base %llu base triples %llu; leaf Phi^l min %g "
                              "median %g max %g; deferred %lld\n",
                              phase, phase == 0 ? 0.0 : spread_limit(phase), (long long)rounds,
-                             hc.visited, hc.det_prunes, hc.mc_prunes, hc.mc_failed, hc.base_cases,
+                             (long long)visited, hc.det_prunes, hc.mc_prunes, hc.mc_failed, hc.base_cases,
                              hc.base_triples, lv.front(), lv[lv.size() / 2], lv.back(),
                              (long long)far_top);
             }
@@ -1016,20 +1163,20 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
         const int B = (int)std::min<int64_t>(top, chunk);
         Item *items = stack + (top - B);
         reset_round_kernel<<<1, 1, 0, s>>>(ctr);
-        classify_kernel<<<(B + 255) / 256, 256, 0, s>>>(items, B, nv, node_phil, node_acc, node_lo,
-                                                       node_cov, k, ctr, mc_list, base_list,
-                                                       child_buf, child_flag, limit, defer_buf,
-                                                       defer_flag);
+        classify_kernel<<<(B + 255) / 256, 256, 0, s>>>(items, B, nv, ns, node_acc, node_lo,
+                                                       node_hi, node_cov, k, ctr, mc_list,
+                                                       base_list, child_buf, child_flag, limit,
+                                                       defer_buf, defer_flag);
         if (k.use_mc)
-            mc_kernel<<<std::min(B, 4096), kMcThreads, 0, s>>>(mc_list, nv, t->xs, node_phil, est,
-                                                               lb, node_cov, k, ctr, base_list,
+            mc_kernel<<<std::min(B, 4096), kMcThreads, 0, s>>>(mc_list, nv, t->xs, ns, est, dev,
+                                                               node_cov, k, ctr, base_list,
                                                                child_buf, child_flag);
         if (prm.base_prec == MB_FP64)
             base_kernel<double><<<std::min(B, 8192), kBaseThreads, 0, s>>>(
-                base_list, nv, t->xs, est, lb, node_cov, k, ctr);
+                base_list, nv, t->xs, est, node_cov, k, ctr);
         else
             base_kernel<float><<<std::min(B, 8192), kBaseThreads, 0, s>>>(
-                base_list, nv, t->xs, est, lb, node_cov, k, ctr);
+                base_list, nv, t->xs, est, node_cov, k, ctr);
         MB_HIP(hipGetLastError());
         // children of split triples, in order, onto the stack where the chunk was;
         // deferred far triples, in order, onto the far stack
@@ -1045,15 +1192,16 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
         MB_HIP(hipMemcpyAsync(num, d_num, sizeof(num), hipMemcpyDeviceToHost, s));
         // Phi^l refresh for the next round
         refresh_down_kernel<<<1, 1024, 0, s>>>(t->depth_nodes, d_doff, n_depths, t->parent,
-                                               k.magnitude ? node_acc : node_lo, cum);
+                                               node_lo, node_hi, cum_lo, cum_hi);
         refresh_leaf_kernel<<<((int)leaves.size() + 255) / 256, 256, 0, s>>>(
-            d_leaves, (int)leaves.size(), t->begin, t->end, k.magnitude ? est : lb, cum,
-            k.magnitude, node_phil);
+            d_leaves, (int)leaves.size(), t->begin, t->end, est, dev, cum_lo, cum_hi, st_pos,
+            st_neg, st_mix);
         refresh_up_kernel<<<1, 1024, 0, s>>>(t->depth_nodes, d_doff, n_depths, t->left, t->right,
-                                             node_phil);
+                                             st_pos, st_neg, st_mix);
         MB_HIP(hipGetLastError());
         MB_HIP(hipStreamSynchronize(s));
         top = top - B + num[0];
+        visited += B - (limit < INFINITY ? num[1] : 0);
         if (limit < INFINITY) far_top += num[1];
         max_stack = std::max(max_stack, top + far_top);
         ++rounds;
@@ -1062,9 +1210,9 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
             MtCounters hc;
             MB_HIP(hipMemcpy(&hc, ctr, sizeof hc, hipMemcpyDeviceToHost));
             std::fprintf(stderr,
-                         "[mb multitree] round %lld phase %d stack %lld far %lld visited %llu det %llu "
+                         "[mb multitree] round %lld phase %d stack %lld far %lld visited %lld det %llu "
                          "mc %llu/%llu base %llu\n",
-                         (long long)rounds, phase, (long long)top, (long long)far_top, hc.visited,
+                         (long long)rounds, phase, (long long)top, (long long)far_top, (long long)visited,
                          hc.det_prunes, hc.mc_prunes, hc.mc_failed, hc.base_cases);
         }
     }
@@ -1075,7 +1223,7 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
     MB_HIP(hipMemcpyAsync(&hc, ctr, sizeof hc, hipMemcpyDeviceToHost, s));
     MB_HIP(hipStreamSynchronize(s));
     if (stats) {
-        stats->visited = (int64_t)hc.visited;
+        stats->visited = visited;
         stats->det_prunes = (int64_t)hc.det_prunes;
         stats->mc_prunes = (int64_t)hc.mc_prunes;
         stats->mc_failed = (int64_t)hc.mc_failed;

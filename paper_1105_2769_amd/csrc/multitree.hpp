@@ -20,7 +20,7 @@ struct MtParams {
     // largest box distance within the triple): 0, unit, 2 unit, 4 unit, ...;
     // 0 disables the bands (one LIFO stack)
     double spread_unit = 0.0;
-    int bound = 0;  // 0: signed running lower bound (the paper); 1: magnitude of the estimate
+    int bound = MB_BOUND_SIGNED;  // or MB_BOUND_TWO_SIDED (running lower and upper bounds)
 };
 
 struct MtStats {
@@ -28,6 +28,11 @@ struct MtStats {
             base_triples = 0, mc_samples = 0, max_stack = 0, rounds = 0;
     double traverse_ms = 0.0;
 };
+
+// Whether tree t was built from the points x (N = n, same coordinates bit for
+// bit in the tree's order).  Waits on s.
+mb_status tree_matches_points(const DeviceTree *t, const double *x, int64_t n, hipStream_t s,
+                              bool *same);
 
 // z with P(Z > z) = alpha_half for a standard normal Z (0 if out of range).
 double normal_quantile_upper(double alpha_half);
