@@ -30,6 +30,24 @@ __device__ __forceinline__ void pair_terms(double dx, double dy, double dz, bool
     ia_out = valid ? ia : 0.0;
 }
 
+// The same with a = |d|^2 formed in binary64 and rounded once to binary32,
+// and q = a^(-3/2), w = a^(-5/2) in binary32 from the hardware reciprocal
+// square root (about one ulp; the binary64 route costs three times the
+// instructions).  a keeps the binary64-then-rounded value the law-of-cosines
+// differences need; q and w are only factors of a triple's value.
+__device__ __forceinline__ void pair_terms32(double dx, double dy, double dz, bool valid, float &a,
+                                             float &q, float &w, float &ia_out) {
+    const float aa = (float)fma(dx, dx, fma(dy, dy, dz * dz));
+    const float ra = __builtin_amdgcn_rsqf(aa);  // 1 / r
+    const float ia = ra * ra;
+    const float qq = ra * ia;
+    const float ww = qq * ia;
+    a = valid ? aa : 1.0f;
+    q = valid ? qq : 0.0f;
+    w = valid ? ww : 0.0f;
+    ia_out = valid ? ia : 0.0f;
+}
+
 // phi of one triangle from its three pair terms (the identity above).
 template <typename T>
 __device__ __forceinline__ T phi_from_pairs(T a, T qa, T wa, T b, T qb, T wb, T c, T qc, T wc) {

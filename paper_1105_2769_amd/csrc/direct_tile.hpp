@@ -73,27 +73,55 @@ template <> struct DirectShape<double> {
     static constexpr int IPW = MB_IPW64;
     static constexpr int NW = MB_NW64;
     static constexpr int KR = MB_KR64;
+    static constexpr bool kPair32 = false;  // (i, k) and (j, k) terms from pair_terms (binary64)
     static constexpr int MINB = MB_MINB64;  // workgroups per CU the registers must allow
 };
 template <> struct DirectShape<float> {
     static constexpr int IPW = MB_IPW32;
     static constexpr int NW = MB_NW32;
     static constexpr int KR = MB_KR32;
+    static constexpr bool kPair32 = false;
     static constexpr int MINB = MB_MINB32;
 };
 
-template <typename T>
+// LDS of one work unit.  Shape gives i points per wave, waves and k points
+// per lane (DirectShape<T> for the exhaustive sum); JB is the J block.
+template <typename T, int JB = kB, typename Shape = DirectShape<T>>
 struct DirectLds {
-    static constexpr int TPB = DirectShape<T>::NW * 64;  // threads per workgroup
-    static constexpr int IB = DirectShape<T>::NW * DirectShape<T>::IPW;
-    static constexpr int KR = DirectShape<T>::KR;
+    static_assert(JB % kJC == 0, "the J block is a whole number of chunks");
+    static constexpr int TPB = Shape::NW * 64;  // threads per workgroup
+    static constexpr int IB = Shape::NW * Shape::IPW;
+    static constexpr int KR = Shape::KR;
     static constexpr int KT = 64 * KR;                   // points per K tile
-    static constexpr int XS = IB + kB + KT;
+    static constexpr int XS = IB + JB + KT;
     double xs[3][XS];                              // coordinates of the I, J blocks and K tile
     T cb[kJC][KT], cq[kJC][KT], co[kJC][KT];       // (j, k) terms of the chunk
     double pj[kJC][64];                            // Phi_j partials per (j, lane), all waves
-    double pjacc[kB];                              // Phi_j of the unit
+    double pjacc[JB];                              // Phi_j of the unit
     double kacc[KT];                               // Phi_k of the unit
+};
+
+// Where the points of a unit's slots come from: slot p of the unit (I block
+// [0, IB), J block [IB, IB + JB), K tile [IB + JB, XS)) holds the point of
+// index rank(p) in the coordinate array, or none if rank(p) < 0; ri, rj, rk
+// give the same by offset inside the I block, J block and K tile.  A pair
+// (u, v) of slots counts iff both hold points and rank(u) < rank(v): every
+// triple of a unit is then taken once, in the order i < j < k.
+//
+// BlockIndex: the exhaustive sum's blocks of consecutive input indices
+// (I block a, J block b, K tile t).
+template <int IB, int JB, int KT>
+struct BlockIndex {
+    int n, I0, J0, K0;
+    __device__ __forceinline__ BlockIndex(int n_, int a, int b, int t)
+        : n(n_), I0(a * IB), J0(b * JB), K0(t * KT) {}
+    __device__ __forceinline__ int rank(int p) const {
+        const int g = p < IB ? I0 + p : (p < IB + JB ? J0 + p - IB : K0 + p - IB - JB);
+        return g < n ? g : -1;
+    }
+    __device__ __forceinline__ int ri(int il) const { return I0 + il < n ? I0 + il : -1; }
+    __device__ __forceinline__ int rj(int jl) const { return J0 + jl < n ? J0 + jl : -1; }
+    __device__ __forceinline__ int rk(int kl) const { return K0 + kl < n ? K0 + kl : -1; }
 };
 
 // Units of J block b: a in [0, na_b) times t in [b / kr, nt), where a K tile
@@ -181,32 +209,33 @@ __device__ __forceinline__ T tile_psi(T a, T qa, T wa, T g, T qg, T wg, T b, T b
     return fma(ob, Y, X);
 }
 
-// One work unit (I block a, J block b, K tile t) of the triple sum; ublk is
-// the (i, j) table block of (a, b), read with scalar loads (a pointer into
-// the constant address space where the caller cannot otherwise show the
-// table is unchanged during the kernel).  Every thread of the workgroup
-// calls it.
-template <typename T, typename TabPtr = const T *>
-__device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__restrict__ x, int n,
-                                            int a, int b, int t, TabPtr ublk,
-                                            double scale, double out_scale,
-                                            double *__restrict__ phi) {
-    constexpr int IPW = DirectShape<T>::IPW;
-    constexpr int IB = DirectLds<T>::IB;
-    constexpr int TPB = DirectLds<T>::TPB;
-    constexpr int kKR = DirectLds<T>::KR;
-    constexpr int kKT = DirectLds<T>::KT;
+// One work unit of the triple sum: the I block, J block and K tile named by
+// the index policy `ix` (see BlockIndex); ublk is the unit's (i, j) table,
+// [jl][il][a, q, w] for the IB x JB pairs, read with scalar loads (a pointer
+// into the constant address space where the caller cannot otherwise show
+// the table is unchanged during the kernel).  x holds the coordinates the
+// ranks index; sums go to phi[rank] (times out_scale).  Every thread of the
+// workgroup calls it.
+template <typename T, int JB, typename Shape, typename Ix, typename TabPtr>
+__device__ __forceinline__ void tile_unit(DirectLds<T, JB, Shape> &s, const double *__restrict__ x,
+                                          const Ix &ix, TabPtr ublk, double scale,
+                                          double out_scale, double *__restrict__ phi) {
+    constexpr int IPW = Shape::IPW;
+    constexpr int IB = DirectLds<T, JB, Shape>::IB;
+    constexpr int TPB = DirectLds<T, JB, Shape>::TPB;
+    constexpr int kKR = DirectLds<T, JB, Shape>::KR;
+    constexpr int kKT = DirectLds<T, JB, Shape>::KT;
+    constexpr int XS = DirectLds<T, JB, Shape>::XS;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    constexpr int XI = 0, XJ = IB, XK = IB + kB;
-    const int I0 = a * IB, J0 = b * kB, K0 = t * kKT;
+    constexpr int XI = 0, XJ = IB, XK = IB + JB;
     const TabPtr up = ublk + wave * (IPW * 3);
 
     __syncthreads();  // the previous unit is done with the LDS
-    for (int p = tid; p < DirectLds<T>::XS; p += TPB) {
-        const int g = p < XJ ? I0 + p : (p < XK ? J0 + p - XJ : K0 + p - XK);
-        const bool ok = g < n;
+    for (int p = tid; p < XS; p += TPB) {
+        const int g = ix.rank(p);
+        const bool ok = g >= 0;
         s.xs[0][p] = ok ? x[3 * (int64_t)g + 0] * scale : 0.0;
         s.xs[1][p] = ok ? x[3 * (int64_t)g + 1] * scale : 0.0;
         s.xs[2][p] = ok ? x[3 * (int64_t)g + 2] * scale : 0.0;
@@ -221,18 +250,25 @@ __device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__res
 #pragma unroll
     for (int ii = 0; ii < IPW; ++ii) {
         const int il = wave * IPW + ii;
-        const int i = I0 + il;
+        const int i = ix.ri(il);
 #pragma unroll
         for (int kk = 0; kk < kKR; ++kk) {
             const int kl = lane + 64 * kk;
-            const int k = K0 + kl;
-            double pa, pq, pw, pia;
-            pair_terms(s.xs[0][XK + kl] - s.xs[0][XI + il], s.xs[1][XK + kl] - s.xs[1][XI + il],
-                       s.xs[2][XK + kl] - s.xs[2][XI + il], (i < k) && (k < n), pa, pq, pw,
-                       pia);
-            ag[ii][kk] = (T)pa;
-            aq[ii][kk] = (T)pq;
-            aw[ii][kk] = (T)pw;
+            const int k = ix.rk(kl);
+            const double dx = s.xs[0][XK + kl] - s.xs[0][XI + il];
+            const double dy = s.xs[1][XK + kl] - s.xs[1][XI + il];
+            const double dz = s.xs[2][XK + kl] - s.xs[2][XI + il];
+            if constexpr (Shape::kPair32) {
+                float pia;
+                pair_terms32(dx, dy, dz, (i >= 0) && (k > i), ag[ii][kk], aq[ii][kk], aw[ii][kk],
+                             pia);
+            } else {
+                double pa, pq, pw, pia;
+                pair_terms(dx, dy, dz, (i >= 0) && (k > i), pa, pq, pw, pia);
+                ag[ii][kk] = (T)pa;
+                aq[ii][kk] = (T)pq;
+                aw[ii][kk] = (T)pw;
+            }
         }
         acc_i[ii] = T(0);
         acc_i64[ii] = 0.0;
@@ -247,19 +283,28 @@ __device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__res
 #pragma unroll
     for (int kk = 0; kk < KR32; ++kk) acck32[kk] = T(0);
 
-    for (int jc = 0; jc < kB / kJC; ++jc) {
+    for (int jc = 0; jc < JB / kJC; ++jc) {
         __syncthreads();  // previous chunk's readers are done
         for (int e = tid; e < kJC * kKT; e += TPB) {
             const int jj = e / kKT, kl = e % kKT;
             const int jl = jc * kJC + jj;
-            const int j = J0 + jl, k = K0 + kl;
-            double pa, pq, pw, pia;
-            pair_terms(s.xs[0][XK + kl] - s.xs[0][XJ + jl], s.xs[1][XK + kl] - s.xs[1][XJ + jl],
-                       s.xs[2][XK + kl] - s.xs[2][XJ + jl], (j < k) && (k < n), pa, pq, pw,
-                       pia);
-            s.cb[jj][kl] = (T)pa;
-            s.cq[jj][kl] = (T)pq;
-            s.co[jj][kl] = (T)(0.375 * pia);
+            const int j = ix.rj(jl), k = ix.rk(kl);
+            const double dx = s.xs[0][XK + kl] - s.xs[0][XJ + jl];
+            const double dy = s.xs[1][XK + kl] - s.xs[1][XJ + jl];
+            const double dz = s.xs[2][XK + kl] - s.xs[2][XJ + jl];
+            if constexpr (Shape::kPair32) {
+                float pa, pq, pw, pia;
+                pair_terms32(dx, dy, dz, (j >= 0) && (k > j), pa, pq, pw, pia);
+                s.cb[jj][kl] = pa;
+                s.cq[jj][kl] = pq;
+                s.co[jj][kl] = 0.375f * pia;
+            } else {
+                double pa, pq, pw, pia;
+                pair_terms(dx, dy, dz, (j >= 0) && (k > j), pa, pq, pw, pia);
+                s.cb[jj][kl] = (T)pa;
+                s.cq[jj][kl] = (T)pq;
+                s.co[jj][kl] = (T)(0.375 * pia);
+            }
         }
         for (int e = tid; e < kJC * 64; e += TPB) s.pj[e / 64][e % 64] = 0.0;
         __syncthreads();
@@ -372,21 +417,31 @@ __device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__res
 #pragma unroll
     for (int ii = 0; ii < IPW; ++ii) {
         const double v = wave_sum(sizeof(T) == 4 ? acc_i64[ii] : (double)acc_i[ii]);
-        const int i = I0 + wave * IPW + ii;
-        if (lane == 0 && i < n) atomicAdd(&phi[i], v * out_scale);
+        const int i = ix.ri(wave * IPW + ii);
+        if (lane == 0 && i >= 0) atomicAdd(&phi[i], v * out_scale);
     }
 #pragma unroll
     for (int kk = 0; kk < kKR; ++kk) atomicAdd(&s.kacc[lane + 64 * kk], acck[kk]);
     __syncthreads();
-    for (int e = tid; e < kKT + kB; e += TPB) {
+    for (int e = tid; e < kKT + JB; e += TPB) {
         if (e < kKT) {
-            const int k = K0 + e;
-            if (k < n) atomicAdd(&phi[k], s.kacc[e] * out_scale);
+            const int k = ix.rk(e);
+            if (k >= 0) atomicAdd(&phi[k], s.kacc[e] * out_scale);
         } else {
-            const int j = J0 + e - kKT;
-            if (j < n) atomicAdd(&phi[j], s.pjacc[e - kKT] * out_scale);
+            const int j = ix.rj(e - kKT);
+            if (j >= 0) atomicAdd(&phi[j], s.pjacc[e - kKT] * out_scale);
         }
     }
+}
+
+// One unit (I block a, J block b, K tile t) of the exhaustive sum over the
+// input order; ublk is the (i, j) table block of (a, b).
+template <typename T, typename TabPtr = const T *>
+__device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__restrict__ x, int n,
+                                            int a, int b, int t, TabPtr ublk, double scale,
+                                            double out_scale, double *__restrict__ phi) {
+    const BlockIndex<DirectLds<T>::IB, kB, DirectLds<T>::KT> ix(n, a, b, t);
+    tile_unit<T, kB, DirectShape<T>>(s, x, ix, ublk, scale, out_scale, phi);
 }
 
 }  // namespace

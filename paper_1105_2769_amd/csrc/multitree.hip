@@ -46,6 +46,7 @@
 #include <vector>
 
 #include "at_device.hpp"
+#include "direct_tile.hpp"
 #include "mb_internal.hpp"
 #include "multitree.hpp"
 #include "tree.hpp"
@@ -58,7 +59,7 @@ struct Item {
 };
 
 struct MtCounters {
-    unsigned long long n_base, n_mc;
+    unsigned long long n_base, n_mc, n_units, n_short;
     unsigned long long det_prunes, mc_prunes, mc_failed, base_cases, base_triples,
         mc_samples;
 };
@@ -651,212 +652,210 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
     }
 }
 
-// 3. Exhaustive base case over a triple of leaves (MTPotentialBase): all
-// (i, j, k) in P1 x P2 x P3 with depth-first ranks i < j < k.  One
-// workgroup per leaf triple; leaves hold at most kLeafMax points.
-constexpr int kLeafMax = 32;
-constexpr int kBaseThreads = 256;
-constexpr int kBaseJU = 4;     // j values per step, read as one LDS vector (binary32)
-constexpr int kBaseJU64 = 2;   // the same for binary64 tables (one 16-byte read)
-constexpr int kBaseSlots = 8;  // LDS accumulator slots per Phi_j (one slot per 8 lanes)
-static_assert(kLeafMax % kBaseJU == 0 && kLeafMax % kBaseJU64 == 0, "j steps must tile a leaf");
+// 3. Exhaustive base cases (MTPotentialBase) through the tile code of the
+// exhaustive sum.  A leaf triple (P1, P2, P3) holds the particle triples
+// i in P1, j in P2, k in P3 with depth-first ranks i < j < k, so it is a
+// work unit of that code with an I block of P1's points, a J block of P2's
+// and a K tile of P3's; since the tile's K dimension (one k per lane) is
+// wider than a leaf, the leaf triples of a round are sorted by (P1, P2) and
+// up to 256 / (leaf width) of them with the same (P1, P2) form one unit,
+// their P3 leaves side by side in the K tile.  The unit's (i, j) terms go to
+// a table that the tile code reads with scalar loads, as in the exhaustive
+// sum.
+constexpr int kLeafMax = 32;  // points per leaf at most (leaf_size <= 32)
 
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x2 __attribute__((ext_vector_type(2)));
+// Tile shapes of the base-case units: an I block of 32 slots (IPW * NW) and a
+// J block of 32; KR k per lane: a K tile of 256 for full units and of 128 for
+// the short last unit of a run.  Binary32 units form their (i, k) and (j, k)
+// powers in binary32 (pair_terms32): with I and J blocks of one leaf those
+// pair terms are a sixth of the work, three times that in binary64.
+template <typename T, int KR_> struct LeafShape;
+template <int KR_> struct LeafShape<float, KR_> {
+    static constexpr int IPW = 8, NW = 4, KR = KR_;
+    static constexpr bool kPair32 = true;
+};
+template <int KR_> struct LeafShape<double, KR_> {
+    static constexpr int IPW = 4, NW = 8, KR = KR_;
+    static constexpr bool kPair32 = false;
+};
+template <typename T, int KR>
+using LeafLds = DirectLds<T, kLeafMax, LeafShape<T, KR>>;
+static_assert(LeafLds<float, 4>::IB == kLeafMax && LeafLds<double, 4>::IB == kLeafMax,
+              "I block = leaf");
+constexpr int kLeafKT = LeafLds<float, 4>::KT;  // K tile of a full unit
+static_assert(LeafLds<double, 4>::KT == kLeafKT && LeafLds<float, 2>::KT == kLeafKT / 2,
+              "K tiles of full and short units");
+constexpr int kLeafTab = kLeafMax * kLeafMax * 3;  // (i, j) table entries per unit
+constexpr int kUnitBatch = 131072;  // units whose tables are held at once (1.5 GiB in binary32)
 
-// N consecutive table entries in as few LDS reads as the vector width
-// allows; p is aligned to the read width (N * sizeof(T) bytes, at most 16).
-template <int N, typename T>
-__device__ __forceinline__ void lds_row(const T *p, T *o) {
-    if constexpr (N == 1) {
-        o[0] = p[0];
-    } else if constexpr (sizeof(T) == 4 && N == 2) {
-        const f32x2 v = *reinterpret_cast<const f32x2 *>(p);
-        o[0] = v.x;
-        o[1] = v.y;
-    } else if constexpr (sizeof(T) == 4) {
-#pragma unroll
-        for (int h = 0; h < N; h += 4) {
-            const f32x4 v = *reinterpret_cast<const f32x4 *>(p + h);
-            o[h] = v.x;
-            o[h + 1] = v.y;
-            o[h + 2] = v.z;
-            o[h + 3] = v.w;
+// Ranks of a unit's slots, filled into LDS before the tile code runs.
+struct LeafIndex {
+    const int *r;  // LDS, one entry per slot of the unit
+    __device__ __forceinline__ int rank(int p) const { return r[p]; }
+    __device__ __forceinline__ int ri(int il) const { return r[il]; }
+    __device__ __forceinline__ int rj(int jl) const { return r[kLeafMax + jl]; }
+    __device__ __forceinline__ int rk(int kl) const { return r[2 * kLeafMax + kl]; }
+};
+
+// Sort keys of the round's leaf triples: (P1, P2) as p1 * M + p2, P3 as the
+// value; slots past the round's count get the largest key.  Also the base
+// case statistics (and, for the coverage check, the tuples per node).
+__global__ void leaf_keys_kernel(const Item *__restrict__ base_list, int cap, NodeView nv, int M,
+                                 MtConst k, MtCounters *__restrict__ ctr,
+                                 unsigned long long *__restrict__ node_cov,
+                                 unsigned long long *__restrict__ keys, int *__restrict__ vals) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= cap) return;
+    const int n_base = (int)ctr->n_base;
+    if (e >= n_base) {
+        keys[e] = ~0ull;
+        vals[e] = -1;
+        return;
+    }
+    const Item it = base_list[e];
+    keys[e] = (unsigned long long)it.p1 * (unsigned long long)M + (unsigned long long)it.p2;
+    vals[e] = it.p3;
+    const int64_t n1 = nv.end[it.p1] - nv.begin[it.p1], n2 = nv.end[it.p2] - nv.begin[it.p2],
+                  n3 = nv.end[it.p3] - nv.begin[it.p3];
+    const char cs = canonical_case(it.p1, it.p2, it.p3);
+    unsigned long long tri;
+    if (cs == 'a') tri = (unsigned long long)(n1 * (n1 - 1) * (n1 - 2) / 6);
+    else if (cs == 'b') tri = (unsigned long long)(comb2(n1) * n3);
+    else if (cs == 'c') tri = (unsigned long long)(n1 * comb2(n2));
+    else tri = (unsigned long long)(n1 * n2 * n3);
+    atomicAdd(&ctr->base_cases, 1ull);
+    atomicAdd(&ctr->base_triples, tri);
+    if (k.want_cov) {
+        const Roles r = roles_of(it.p1, it.p2, it.p3, n1, n2, n3);
+        for (int q = 0; q < r.n_roles; ++q)
+            atomicAdd(&node_cov[r.node[q]], (unsigned long long)r.t[q]);
+    }
+}
+
+// Units from the sorted keys: each run of equal (P1, P2) is cut into full
+// units of per_unit leaf triples; a remainder of more than per_unit / 2
+// makes one more full unit, a smaller one a short unit (half the K tile).
+// The first thread of the run writes them.
+__global__ void leaf_units_kernel(const unsigned long long *__restrict__ keys, int cap,
+                                  MtCounters *__restrict__ ctr, int per_unit,
+                                  int *__restrict__ u_start, int *__restrict__ u_count,
+                                  int *__restrict__ h_start, int *__restrict__ h_count) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n_base = (int)ctr->n_base;
+    if (e >= n_base || e >= cap) return;
+    const unsigned long long key = keys[e];
+    if (e > 0 && keys[e - 1] == key) return;
+    int len = 1;
+    while (e + len < n_base && keys[e + len] == key) ++len;
+    int full = len / per_unit;
+    const int rest = len - full * per_unit;
+    const bool short_rest = rest > 0 && 2 * rest <= per_unit;
+    if (rest > 0 && !short_rest) ++full;
+    if (full > 0) {
+        const int base = (int)atomicAdd(&ctr->n_units, (unsigned long long)full);
+        for (int q = 0; q < full; ++q) {
+            u_start[base + q] = e + q * per_unit;
+            u_count[base + q] = min(per_unit, len - q * per_unit);
         }
-    } else {
-#pragma unroll
-        for (int h = 0; h < N; h += 2) {
-            const f64x2 v = *reinterpret_cast<const f64x2 *>(p + h);
-            o[h] = v.x;
-            o[h + 1] = v.y;
+    }
+    if (short_rest) {
+        const int h = (int)atomicAdd(&ctr->n_short, 1ull);
+        h_start[h] = e + len - rest;
+        h_count[h] = rest;
+    }
+}
+
+// (i, j) tables of the units [u0, u0 + batch) that exist: [jl][il][a, q, w]
+// for i in P1, j in P2, masked unless both exist and rank i < rank j (P1 = P2
+// in cases (a) and (b)); coordinates times `scale`.
+template <typename T>
+__global__ __launch_bounds__(256) void leaf_table_kernel(
+    const unsigned long long *__restrict__ keys, const int *__restrict__ u_start,
+    const unsigned long long *__restrict__ count, int u0, int batch, int M, NodeView nv,
+    const double *__restrict__ xs, double scale, T *__restrict__ tab) {
+    __shared__ double xa[3][kLeafMax], xb[3][kLeafMax];
+    const int tid = threadIdx.x;
+    const int n_units = min((int)*count - u0, batch);
+    for (int w = blockIdx.x; w < n_units; w += gridDim.x) {
+        const unsigned long long key = keys[u_start[u0 + w]];
+        const int p1 = (int)(key / (unsigned long long)M), p2 = (int)(key % (unsigned long long)M);
+        const int b1 = nv.begin[p1], b2 = nv.begin[p2];
+        const int n1 = nv.end[p1] - b1, n2 = nv.end[p2] - b2;
+        __syncthreads();  // the previous unit is done with xa, xb
+        if (tid < kLeafMax) {
+            for (int c = 0; c < 3; ++c)
+                xa[c][tid] = tid < n1 ? xs[3 * (int64_t)(b1 + tid) + c] * scale : 0.0;
+        } else if (tid < 2 * kLeafMax) {
+            const int o = tid - kLeafMax;
+            for (int c = 0; c < 3; ++c)
+                xb[c][o] = o < n2 ? xs[3 * (int64_t)(b2 + o) + c] * scale : 0.0;
+        }
+        __syncthreads();
+        T *out = tab + (int64_t)w * kLeafTab;
+        for (int e = tid; e < kLeafMax * kLeafMax; e += 256) {
+            const int jl = e / kLeafMax, il = e % kLeafMax;
+            double pa, pq, pw, pia;
+            pair_terms(xb[0][jl] - xa[0][il], xb[1][jl] - xa[1][il], xb[2][jl] - xa[2][il],
+                       il < n1 && jl < n2 && b1 + il < b2 + jl, pa, pq, pw, pia);
+            out[3 * e + 0] = (T)pa;
+            out[3 * e + 1] = (T)pq;
+            out[3 * e + 2] = (T)pw;
         }
     }
 }
 
-template <typename T>
-struct alignas(16) BaseLds {
-    double x[3][3][kLeafMax];         // coordinates of P1, P2, P3
-    double pj[kLeafMax][kBaseSlots];  // Phi_j partials
-    double pk[kLeafMax];              // Phi_k partials
-    T ua[kLeafMax][kLeafMax], uq[kLeafMax][kLeafMax], uw[kLeafMax][kLeafMax];  // (i, j)
-    T cb[kLeafMax][kLeafMax], cq[kLeafMax][kLeafMax], co[kLeafMax][kLeafMax];  // (j, k)
-};
-
-template <typename T>
-__global__ __launch_bounds__(kBaseThreads) void base_kernel(
-    const Item *__restrict__ base_list, NodeView nv, const double *__restrict__ xs,
-    double *__restrict__ est, unsigned long long *__restrict__ node_cov,
-    MtConst k, MtCounters *__restrict__ ctr) {
-    __shared__ BaseLds<T> s;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int kl = lane & 31, ih = lane >> 5;  // this lane's k and its half of the i points
-    const unsigned long long n_base = ctr->n_base;
-    unsigned long long my_cases = 0, my_tri = 0;  // statistics; thread 2 * kLeafMax counts
-    for (unsigned long long w = blockIdx.x; w < n_base; w += gridDim.x) {
-        const Item it = base_list[w];
-        const int b1 = nv.begin[it.p1], b2 = nv.begin[it.p2], b3 = nv.begin[it.p3];
-        const int n1 = nv.end[it.p1] - b1, n2 = nv.end[it.p2] - b2, n3 = nv.end[it.p3] - b3;
-        __syncthreads();
-        if (tid < 3 * kLeafMax) {
-            const int set = tid / kLeafMax, o = tid % kLeafMax;
-            const int b = set == 0 ? b1 : (set == 1 ? b2 : b3);
-            const int cnt = set == 0 ? n1 : (set == 1 ? n2 : n3);
-            for (int c = 0; c < 3; ++c) s.x[set][c][o] = o < cnt ? xs[3 * (int64_t)(b + o) + c] : 0.0;
-        }
-        if (tid < kLeafMax) s.pk[tid] = 0.0;
-        for (int e = tid; e < kLeafMax * kBaseSlots; e += kBaseThreads)
-            s.pj[e / kBaseSlots][e % kBaseSlots] = 0.0;
-        __syncthreads();
-        // pair tables: (i, j) and (j, k), masked by rank order and size
-        for (int e = tid; e < kLeafMax * kLeafMax; e += kBaseThreads) {
-            const int a = e / kLeafMax, c = e % kLeafMax;
-            double pa, pq, pw, pia;
-            // (i = a, j = c)
-            pair_terms(s.x[1][0][c] - s.x[0][0][a], s.x[1][1][c] - s.x[0][1][a],
-                       s.x[1][2][c] - s.x[0][2][a], a < n1 && c < n2 && b1 + a < b2 + c, pa, pq, pw,
-                       pia);
-            s.ua[a][c] = (T)pa;
-            s.uq[a][c] = (T)pq;
-            s.uw[a][c] = (T)pw;
-            // (j = a, k = c)
-            pair_terms(s.x[2][0][c] - s.x[1][0][a], s.x[2][1][c] - s.x[1][1][a],
-                       s.x[2][2][c] - s.x[1][2][a], a < n2 && c < n3 && b2 + a < b3 + c, pa, pq, pw,
-                       pia);
-            s.cb[a][c] = (T)pa;
-            s.cq[a][c] = (T)pq;
-            s.co[a][c] = (T)(0.375 * pia);
-        }
-        // (i, k) terms of this lane: i = 8 m + 2 wave + ih, m = 0..3
-        T ag[4], aq[4], aw[4], acc_i[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int il = 8 * m + 2 * wave + ih;
-            double pa, pq, pw, pia;
-            pair_terms(s.x[2][0][kl] - s.x[0][0][il], s.x[2][1][kl] - s.x[0][1][il],
-                       s.x[2][2][kl] - s.x[0][2][il], il < n1 && kl < n3 && b1 + il < b3 + kl, pa,
-                       pq, pw, pia);
-            ag[m] = (T)pa;
-            aq[m] = (T)pq;
-            aw[m] = (T)pw;
-            acc_i[m] = T(0);
-        }
-        __syncthreads();
-        constexpr int kJU = sizeof(T) == 4 ? kBaseJU : kBaseJU64;
-        // j in steps of kJU; entries past n2 are masked pairs, which
-        // contribute exact zeros
-        double acck = 0.0;
-        const int n2r = (n2 + kJU - 1) / kJU * kJU;
-        for (int j0 = 0; j0 < n2r; j0 += kJU) {
-            T bj[kJU], qj[kJU], oj[kJU], bb[kJU], sk[kJU];
-#pragma unroll
-            for (int u = 0; u < kJU; ++u) {
-                bj[u] = s.cb[j0 + u][kl];
-                qj[u] = s.cq[j0 + u][kl];
-                oj[u] = s.co[j0 + u][kl];
-                bb[u] = bj[u] * bj[u];
-                sk[u] = T(0);
-            }
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int il = 8 * m + 2 * wave + ih;
-                T al[kJU], qa[kJU], wa[kJU];
-                lds_row<kJU>(&s.ua[il][j0], al);
-                lds_row<kJU>(&s.uq[il][j0], qa);
-                lds_row<kJU>(&s.uw[il][j0], wa);
-#pragma unroll
-                for (int u = 0; u < kJU; ++u) {
-                    const T d = al[u] - ag[m];
-                    const T tt = (al[u] + ag[m]) - bj[u];
-                    const T mm = fma(-d, d, bb[u]);
-                    const T X = qa[u] * aq[m];
-                    const T Y = (wa[u] * aw[m]) * (tt * mm);
-                    const T psi = fma(oj[u], Y, X);
-                    sk[u] += psi;
-                    acc_i[m] = fma(qj[u], psi, acc_i[m]);
+// The units [u0, u0 + batch) that exist (of *count) through the tile code;
+// the K tile holds the P3 leaves of a unit's items, `width` slots each (the
+// largest leaf).  The tables were written by the previous launch and are
+// only read.
+template <typename T, int KR>
+__global__ __launch_bounds__((LeafLds<T, KR>::TPB)) void leaf_tile_kernel(
+    const unsigned long long *__restrict__ keys, const int *__restrict__ vals,
+    const int *__restrict__ u_start, const int *__restrict__ u_count,
+    const unsigned long long *__restrict__ count, int u0, int batch, int M, NodeView nv,
+    const double *__restrict__ xs, const T *__restrict__ tab, int width, double scale,
+    double out_scale, double *__restrict__ est) {
+    using Lds = LeafLds<T, KR>;
+    __shared__ Lds s;
+    __shared__ int rk[Lds::XS];
+    using CT = __attribute__((address_space(4))) const T;
+    constexpr int TPB = Lds::TPB;
+    const int n_units = min((int)*count - u0, batch);
+    for (int w = blockIdx.x; w < n_units; w += gridDim.x) {
+        const int u = u0 + w;
+        const int e0 = u_start[u], cnt = u_count[u];
+        const unsigned long long key = keys[e0];
+        const int p1 = (int)(key / (unsigned long long)M), p2 = (int)(key % (unsigned long long)M);
+        const int b1 = nv.begin[p1], b2 = nv.begin[p2];
+        const int n1 = nv.end[p1] - b1, n2 = nv.end[p2] - b2;
+        __syncthreads();  // the previous unit is done with rk and the LDS
+        for (int p = threadIdx.x; p < Lds::XS; p += TPB) {
+            int r = -1;
+            if (p < kLeafMax) {
+                if (p < n1) r = b1 + p;
+            } else if (p < 2 * kLeafMax) {
+                if (p - kLeafMax < n2) r = b2 + p - kLeafMax;
+            } else {
+                const int q = (p - 2 * kLeafMax) / width, o = (p - 2 * kLeafMax) % width;
+                if (q < cnt) {
+                    const int v = vals[e0 + q];
+                    if (o < nv.end[v] - nv.begin[v]) r = nv.begin[v] + o;
                 }
             }
-#pragma unroll
-            for (int u = 0; u < kJU; ++u) {
-                const double v = (double)(qj[u] * sk[u]);
-                acck += v;
-                atomicAdd(&s.pj[j0 + u][lane % kBaseSlots], v);
-            }
+            rk[p] = r;
         }
-        // Phi_i: sum over the 32 k lanes of each half-wave
-        double vi[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            double v = (double)acc_i[m];
-#pragma unroll
-            for (int sh = 16; sh >= 1; sh >>= 1) v += __shfl_xor(v, sh);
-            vi[m] = v;
-        }
-        if (kl == 0) {
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int il = 8 * m + 2 * wave + ih;
-                if (il < n1) atomicAdd(&est[b1 + il], vi[m]);
-            }
-        }
-        atomicAdd(&s.pk[kl], acck);
         __syncthreads();
-        if (tid < kLeafMax) {
-            if (tid < n3) atomicAdd(&est[b3 + tid], s.pk[tid]);
-        } else if (tid < 2 * kLeafMax) {
-            const int j = tid - kLeafMax;
-            if (j < n2) {
-                double v = 0.0;
-                for (int q = 0; q < kBaseSlots; ++q) v += s.pj[j][q];
-                atomicAdd(&est[b2 + j], v);
-            }
-        } else if (tid == 2 * kLeafMax) {
-            ++my_cases;
-            const Roles r = roles_of(it.p1, it.p2, it.p3, n1, n2, n3);
-            unsigned long long tri = 0;
-            const char cs = canonical_case(it.p1, it.p2, it.p3);
-            if (cs == 'a') tri = (unsigned long long)(n1 * (int64_t)(n1 - 1) * (n1 - 2) / 6);
-            else if (cs == 'b') tri = (unsigned long long)(comb2(n1) * n3);
-            else if (cs == 'c') tri = (unsigned long long)(n1 * comb2(n2));
-            else tri = (unsigned long long)n1 * n2 * n3;
-            my_tri += tri;
-            if (k.want_cov)
-                for (int q = 0; q < r.n_roles; ++q)
-                    atomicAdd(&node_cov[r.node[q]], (unsigned long long)r.t[q]);
-        }
-    }
-    // one update of the global counters per workgroup: the same-address
-    // atomics of every leaf triple serialized the whole kernel
-    if (tid == 2 * kLeafMax && my_cases) {
-        atomicAdd(&ctr->base_cases, my_cases);
-        atomicAdd(&ctr->base_triples, my_tri);
+        const LeafIndex ix{rk};
+        tile_unit<T, kLeafMax, LeafShape<T, KR>>(s, xs, ix, (CT *)tab + (int64_t)w * kLeafTab,
+                                                 scale, out_scale, est);
     }
 }
 
 __global__ void reset_round_kernel(MtCounters *ctr) {
     ctr->n_base = 0;
     ctr->n_mc = 0;
+    ctr->n_units = 0;
+    ctr->n_short = 0;
 }
 
 __global__ void zero_u64_kernel(unsigned long long *__restrict__ p, int64_t n) {
@@ -866,7 +865,7 @@ __global__ void zero_u64_kernel(unsigned long long *__restrict__ p, int64_t n) {
 }
 
 __global__ void zero_counters_kernel(MtCounters *ctr) {
-    ctr->n_base = ctr->n_mc = ctr->det_prunes = ctr->mc_prunes = 0;
+    ctr->n_base = ctr->n_mc = ctr->n_units = ctr->n_short = ctr->det_prunes = ctr->mc_prunes = 0;
     ctr->mc_failed = ctr->base_cases = ctr->base_triples = ctr->mc_samples = 0;
 }
 
@@ -1085,6 +1084,66 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
                                          8 * chunk, s));
     if ((st = s_tmp.alloc(tmp_bytes, s)) != MB_OK) return st;
 
+    // base cases: sort keys and values of the round's leaf triples (two
+    // copies each), units, and the (i, j) tables of up to `ubatch` units
+    const bool base64 = prm.base_prec == MB_FP64;
+    int width = 1;  // K-tile slots per leaf: the largest leaf
+    for (int32_t v : leaves) width = std::max(width, t->h.end[v] - t->h.begin[v]);
+    const int per_unit = kLeafKT / width;
+    const int ubatch = std::min(chunk, kUnitBatch);
+    Scratch s_keys, s_vals, s_ust, s_ucnt, s_hst, s_hcnt, s_tab, s_htab, s_stmp;
+    unsigned long long *keys;
+    int *vals, *u_start, *u_count, *h_start, *h_count;
+    char *tab, *htab;
+    const size_t tab_bytes = (size_t)ubatch * kLeafTab * (base64 ? 8 : 4);
+    if ((st = dalloc(s_keys, &keys, 2 * (size_t)chunk, s)) ||
+        (st = dalloc(s_vals, &vals, 2 * (size_t)chunk, s)) ||
+        (st = dalloc(s_ust, &u_start, chunk, s)) || (st = dalloc(s_ucnt, &u_count, chunk, s)) ||
+        (st = dalloc(s_hst, &h_start, chunk, s)) || (st = dalloc(s_hcnt, &h_count, chunk, s)) ||
+        (st = dalloc(s_tab, &tab, tab_bytes, s)) || (st = dalloc(s_htab, &htab, tab_bytes, s)))
+        return st;
+    const unsigned long long key_max = (unsigned long long)M * (unsigned long long)M - 1ull;
+    const int end_bit = std::max(1, 64 - __builtin_clzll(std::max(key_max, 1ull)));
+    size_t stmp_bytes = 0;
+    MB_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, stmp_bytes, keys, keys + chunk, vals,
+                                              vals + chunk, chunk, 0, end_bit, s));
+    if ((st = s_stmp.alloc(stmp_bytes, s)) != MB_OK) return st;
+    // binary32 tiles work on coordinates scaled by a power of two that puts
+    // the closest pair in [1, 2) (exact), as in the exhaustive sum
+    const double lscale = base64 || !(prm.r_min > 0.0) ? 1.0 : unit_scale(prm.r_min * prm.r_min);
+    const double lout = std::pow(lscale, 9.0);
+    const NodeView nv{t->begin, t->end, t->left, t->right, t->lo, t->hi, t->centroid};
+    // one batch of full units and one of short units, from unit u0 of each
+    auto leaf_batch = [&](int u0) -> mb_status {
+        const unsigned grid = (unsigned)std::min(ubatch, 2048);
+        const unsigned long long *nf = &ctr->n_units, *nh = &ctr->n_short;
+        if (base64) {
+            leaf_table_kernel<double><<<grid, 256, 0, s>>>(keys + chunk, u_start, nf, u0, ubatch,
+                                                          M, nv, t->xs, lscale, (double *)tab);
+            leaf_tile_kernel<double, 4><<<grid, LeafLds<double, 4>::TPB, 0, s>>>(
+                keys + chunk, vals + chunk, u_start, u_count, nf, u0, ubatch, M, nv, t->xs,
+                (const double *)tab, width, lscale, lout, est);
+            leaf_table_kernel<double><<<grid, 256, 0, s>>>(keys + chunk, h_start, nh, u0, ubatch,
+                                                          M, nv, t->xs, lscale, (double *)htab);
+            leaf_tile_kernel<double, 2><<<grid, LeafLds<double, 2>::TPB, 0, s>>>(
+                keys + chunk, vals + chunk, h_start, h_count, nh, u0, ubatch, M, nv, t->xs,
+                (const double *)htab, width, lscale, lout, est);
+        } else {
+            leaf_table_kernel<float><<<grid, 256, 0, s>>>(keys + chunk, u_start, nf, u0, ubatch,
+                                                         M, nv, t->xs, lscale, (float *)tab);
+            leaf_tile_kernel<float, 4><<<grid, LeafLds<float, 4>::TPB, 0, s>>>(
+                keys + chunk, vals + chunk, u_start, u_count, nf, u0, ubatch, M, nv, t->xs,
+                (const float *)tab, width, lscale, lout, est);
+            leaf_table_kernel<float><<<grid, 256, 0, s>>>(keys + chunk, h_start, nh, u0, ubatch,
+                                                         M, nv, t->xs, lscale, (float *)htab);
+            leaf_tile_kernel<float, 2><<<grid, LeafLds<float, 2>::TPB, 0, s>>>(
+                keys + chunk, vals + chunk, h_start, h_count, nh, u0, ubatch, M, nv, t->xs,
+                (const float *)htab, width, lscale, lout, est);
+        }
+        MB_HIP(hipGetLastError());
+        return MB_OK;
+    };
+
     const Item root{0, 0, 0, 0};
     MB_HIP(hipMemcpyAsync(stack, &root, sizeof(Item), hipMemcpyHostToDevice, s));
     int64_t top = 1, far_top = 0;
@@ -1094,7 +1153,6 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
         return ph == 0 ? 0.0 : prm.spread_unit * std::ldexp(1.0, ph - 1);
     };
 
-    NodeView nv{t->begin, t->end, t->left, t->right, t->lo, t->hi, t->centroid};
     MtConst k;
     k.n = n;
     k.eps = prm.eps;
@@ -1171,12 +1229,14 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
             mc_kernel<<<std::min(B, 4096), kMcThreads, 0, s>>>(mc_list, nv, t->xs, ns, est, dev,
                                                                node_cov, k, ctr, base_list,
                                                                child_buf, child_flag);
-        if (prm.base_prec == MB_FP64)
-            base_kernel<double><<<std::min(B, 8192), kBaseThreads, 0, s>>>(
-                base_list, nv, t->xs, est, node_cov, k, ctr);
-        else
-            base_kernel<float><<<std::min(B, 8192), kBaseThreads, 0, s>>>(
-                base_list, nv, t->xs, est, node_cov, k, ctr);
+        // base cases: sort by (P1, P2), cut into units, tables, tiles
+        leaf_keys_kernel<<<(B + 255) / 256, 256, 0, s>>>(base_list, B, nv, M, k, ctr, node_cov,
+                                                        keys, vals);
+        MB_HIP(hipcub::DeviceRadixSort::SortPairs(s_stmp.ptr, stmp_bytes, keys, keys + chunk, vals,
+                                                  vals + chunk, B, 0, end_bit, s));
+        leaf_units_kernel<<<(B + 255) / 256, 256, 0, s>>>(keys + chunk, B, ctr, per_unit, u_start,
+                                                         u_count, h_start, h_count);
+        if ((st = leaf_batch(0)) != MB_OK) return st;
         MB_HIP(hipGetLastError());
         // children of split triples, in order, onto the stack where the chunk was;
         // deferred far triples, in order, onto the far stack
@@ -1190,6 +1250,8 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
         }
         int num[2] = {0, 0};
         MB_HIP(hipMemcpyAsync(num, d_num, sizeof(num), hipMemcpyDeviceToHost, s));
+        unsigned long long n_units[2] = {0, 0};  // full and short units (adjacent counters)
+        MB_HIP(hipMemcpyAsync(n_units, &ctr->n_units, sizeof n_units, hipMemcpyDeviceToHost, s));
         // Phi^l refresh for the next round
         refresh_down_kernel<<<1, 1024, 0, s>>>(t->depth_nodes, d_doff, n_depths, t->parent,
                                                node_lo, node_hi, cum_lo, cum_hi);
@@ -1200,6 +1262,14 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
                                              st_pos, st_neg, st_mix);
         MB_HIP(hipGetLastError());
         MB_HIP(hipStreamSynchronize(s));
+        // units beyond the first batch (their credits reach the statistics
+        // one round later, which only delays prunes)
+        const unsigned long long n_units_max = std::max(n_units[0], n_units[1]);
+        if (n_units_max > (unsigned long long)ubatch) {
+            for (int u0 = ubatch; (unsigned long long)u0 < n_units_max; u0 += ubatch)
+                if ((st = leaf_batch(u0)) != MB_OK) return st;
+            MB_HIP(hipStreamSynchronize(s));
+        }
         top = top - B + num[0];
         visited += B - (limit < INFINITY ? num[1] : 0);
         if (limit < INFINITY) far_top += num[1];
