@@ -300,9 +300,10 @@ double mb_normal_quantile(double alpha_half);
  *   - admission: requests are admitted in arrival order while a slot is free
  *     and their device footprint fits the HBM budget; the footprint of a
  *     request of N points is 24 N + 16 N bytes (points, Phi, near-field
- *     magnitudes) plus its (i, j) pair-term table (about 3 N^2 binary32 or
- *     binary64 numbers), each part rounded up to 256 B; room for either
- *     table is reserved until validation shows binary64 is not needed;
+ *     magnitudes) plus a region for its (i, j) pair-term table (about
+ *     3 N^2 numbers) large enough for either the binary32 or the binary64
+ *     table, each part rounded up to 256 B; the request holds all of it
+ *     until it is released, whichever table validation selects;
  *   - continuous batching: the work units (block triples) of all admitted
  *     requests are drained together by a kernel whose resident workgroups
  *     pop (request, unit) items, in slices of a bounded number of units;

@@ -80,7 +80,7 @@ __device__ __forceinline__ double rpow(double r, double ir, int e) {
 // 64 x 64 tile (ti, tk) of all four matrices.
 template <typename H, int P>
 __global__ __launch_bounds__(256) void pairmat_kernel(const double *__restrict__ xs, int n, int np,
-                                                      double r_near, H *__restrict__ planes,
+                                                      double rn2, H *__restrict__ planes,
                                                       int *__restrict__ texp) {
     const int ti = blockIdx.y, tk = blockIdx.x, tid = threadIdx.x;
     const int nt = np / kTS;
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void pairmat_kernel(const double *__restrict__
         const double dx = xk[0][b] - xi[0][a], dy = xk[1][b] - xi[1][a], dz = xk[2][b] - xi[2][a];
         const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
         const double r = sqrt(r2);
-        const bool ok = i < n && k < n && i != k && r >= r_near;
+        const bool ok = i < n && k < n && i != k && r2 >= rn2;
         const double ir = 1.0 / r;
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
@@ -166,7 +166,7 @@ template <typename H, int P>
 __global__ __launch_bounds__(64 * kGemmWaves) void gemm_kernel(const H *__restrict__ planes,
                                                    const int *__restrict__ texp,
                                                    const double *__restrict__ xs, int n, int np,
-                                                   int ma, int mb, int we, double r_near,
+                                                   int ma, int mb, int we, double rn2,
                                                    double *__restrict__ trow,
                                                    double *__restrict__ tcol) {
     constexpr int kBufs = P <= 2 ? 2 : 1;  // LDS buffers (two with register prefetch)
@@ -405,8 +405,9 @@ __global__ __launch_bounds__(64 * kGemmWaves) void gemm_kernel(const H *__restri
                 const int i = I0 + il;
                 const double dx = xc[0][jl] - xr[0][il], dy = xc[1][jl] - xr[1][il],
                              dz = xc[2][jl] - xr[2][il];
-                const double rr = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
-                const bool ok = i < n && j < n && i != j && rr >= r_near;
+                const double rr2 = fma(dx, dx, fma(dy, dy, dz * dz));
+                const double rr = sqrt(rr2);
+                const bool ok = i < n && j < n && i != j && rr2 >= rn2;
                 const double w = ok ? rpow(rr, 1.0 / rr, we) * acc64[rb][cb][r] : 0.0;
                 colsum[cb] += w;
                 // row sum over the 32 lanes that hold this row
@@ -427,7 +428,7 @@ __global__ __launch_bounds__(64 * kGemmWaves) void gemm_kernel(const H *__restri
 }
 
 // C-3a: pairs closer than r_near (u < v), appended to a list.
-__global__ void near_pairs_kernel(const double *__restrict__ xs, int n, double r_near,
+__global__ void near_pairs_kernel(const double *__restrict__ xs, int n, double rn2,
                                   int2 *__restrict__ out, unsigned long long *__restrict__ count,
                                   unsigned long long cap) {
     const int u = blockIdx.y * blockDim.x + threadIdx.x;
@@ -438,7 +439,6 @@ __global__ void near_pairs_kernel(const double *__restrict__ xs, int n, double r
     __syncthreads();
     if (u >= n || v0 + 255 <= u) return;
     const double x0 = xs[3 * (int64_t)u], x1 = xs[3 * (int64_t)u + 1], x2 = xs[3 * (int64_t)u + 2];
-    const double rn2 = r_near * r_near;
     for (int q = 0; q < 256; ++q) {
         const int vv = v0 + q;
         if (vv <= u || vv >= n) continue;
@@ -458,7 +458,7 @@ __device__ __forceinline__ bool pair_less(int a0, int a1, int b0, int b1) {
 // FP64, counted once: by the smallest (lexicographic) of its short pairs.
 // A workgroup takes 256 third points w and a range of short pairs.
 __global__ __launch_bounds__(256) void near_triples_kernel(
-    const double *__restrict__ xs, int n, double r_near, const int2 *__restrict__ pairs,
+    const double *__restrict__ xs, int n, double rn2, const int2 *__restrict__ pairs,
     long long n_pairs, long long pairs_per_block, double *__restrict__ phi) {
     const int w = blockIdx.x * 256 + threadIdx.x;
     const long long p0 = (long long)blockIdx.y * pairs_per_block;
@@ -469,7 +469,6 @@ __global__ __launch_bounds__(256) void near_triples_kernel(
     double xw[3] = {0.0, 0.0, 0.0};
     if (wok)
         for (int c = 0; c < 3; ++c) xw[c] = xs[3 * (int64_t)w + c];
-    const double rn2 = r_near * r_near;
     double accw = 0.0;
     for (long long pbase = p0; pbase < p1; pbase += 256) {
         __syncthreads();
@@ -546,44 +545,47 @@ mb_status factorized_run(const DeviceTree *tr, int n, double r_near, double *phi
     zero_doubles(t, 6 * (int64_t)n, s);
     zero_doubles(s_near.as<double>(), n, s);
 
+    // one squared threshold for every near / far decision: a pair is near
+    // iff its squared distance (formed the same way in every kernel) is < rn2
+    const double rn2 = r_near * r_near;
     hipEvent_t e0, e1, e2, e3;
     MB_HIP(hipEventCreate(&e0));
     MB_HIP(hipEventCreate(&e1));
     MB_HIP(hipEventCreate(&e2));
     MB_HIP(hipEventCreate(&e3));
     MB_HIP(hipEventRecord(e0, s));
-    pairmat_kernel<H, P><<<dim3(nt, nt), 256, 0, s>>>(tr->xs, n, np, r_near, s_planes.as<H>(),
+    pairmat_kernel<H, P><<<dim3(nt, nt), 256, 0, s>>>(tr->xs, n, np, rn2, s_planes.as<H>(),
                                                       s_exp.as<int>());
     MB_HIP(hipEventRecord(e1, s));
     const dim3 g(np / kGT, np / kGT);
     // (A matrix, B matrix, weight exponent, row target, column target); storage order -5, +1, -3, -1
     gemm_kernel<H, P><<<g, 64 * kGemmWaves, 0, s>>>(s_planes.as<H>(), s_exp.as<int>(), tr->xs, n, np, 2, 2, -3,
-                                        r_near, t + 0 * (int64_t)n, nullptr);
+                                        rn2, t + 0 * (int64_t)n, nullptr);
     gemm_kernel<H, P><<<g, 64 * kGemmWaves, 0, s>>>(s_planes.as<H>(), s_exp.as<int>(), tr->xs, n, np, 0, 0, 1,
-                                        r_near, t + 1 * (int64_t)n, nullptr);
+                                        rn2, t + 1 * (int64_t)n, nullptr);
     gemm_kernel<H, P><<<g, 64 * kGemmWaves, 0, s>>>(s_planes.as<H>(), s_exp.as<int>(), tr->xs, n, np, 0, 1, -5,
-                                        r_near, t + 2 * (int64_t)n, nullptr);
+                                        rn2, t + 2 * (int64_t)n, nullptr);
     gemm_kernel<H, P><<<g, 64 * kGemmWaves, 0, s>>>(s_planes.as<H>(), s_exp.as<int>(), tr->xs, n, np, 0, 2, -1,
-                                        r_near, t + 4 * (int64_t)n, t + 3 * (int64_t)n);
+                                        rn2, t + 4 * (int64_t)n, t + 3 * (int64_t)n);
     gemm_kernel<H, P><<<g, 64 * kGemmWaves, 0, s>>>(s_planes.as<H>(), s_exp.as<int>(), tr->xs, n, np, 0, 3, -3,
-                                        r_near, t + 5 * (int64_t)n, nullptr);
+                                        rn2, t + 5 * (int64_t)n, nullptr);
     MB_HIP(hipGetLastError());
     MB_HIP(hipEventRecord(e2, s));
     // near field: count, then list, then triples
     unsigned long long cnt = 0;
     MB_HIP(hipMemsetAsync(s_cnt.ptr, 0, sizeof cnt, s));
     const dim3 pg((n + 255) / 256, (n + 255) / 256);
-    near_pairs_kernel<<<pg, 256, 0, s>>>(tr->xs, n, r_near, nullptr, s_cnt.as<unsigned long long>(), 0);
+    near_pairs_kernel<<<pg, 256, 0, s>>>(tr->xs, n, rn2, nullptr, s_cnt.as<unsigned long long>(), 0);
     MB_HIP(hipMemcpyAsync(&cnt, s_cnt.ptr, sizeof cnt, hipMemcpyDeviceToHost, s));
     MB_HIP(hipStreamSynchronize(s));
     if (cnt > 0) {
         if ((st = s_pairs.alloc(sizeof(int2) * cnt, s)) != MB_OK) return st;
         MB_HIP(hipMemsetAsync(s_cnt.ptr, 0, sizeof cnt, s));
-        near_pairs_kernel<<<pg, 256, 0, s>>>(tr->xs, n, r_near, s_pairs.as<int2>(),
+        near_pairs_kernel<<<pg, 256, 0, s>>>(tr->xs, n, rn2, s_pairs.as<int2>(),
                                              s_cnt.as<unsigned long long>(), cnt);
         const long long per = 4096;
         const dim3 tg((n + 255) / 256, (unsigned)((cnt + per - 1) / per));
-        near_triples_kernel<<<tg, 256, 0, s>>>(tr->xs, n, r_near, s_pairs.as<int2>(), (long long)cnt,
+        near_triples_kernel<<<tg, 256, 0, s>>>(tr->xs, n, rn2, s_pairs.as<int2>(), (long long)cnt,
                                                per, s_near.as<double>());
     }
     MB_HIP(hipGetLastError());

@@ -321,16 +321,23 @@ __global__ __launch_bounds__(256) void classify_kernel(
         return;
     }
 
-    // deterministic prune (three distinct nodes).  No two points are closer
-    // than r_min, so every d^l is raised to it; d^u is the farthest pair of
-    // box corners.
+    // bounds on phi over the triple: no two points are closer than r_min, so
+    // every d^l is raised to it (a node paired with itself has d^l = 0); d^u
+    // is the farthest pair of box corners
+    const int pa[3] = {p1, p1, p2}, pb[3] = {p2, p3, p3};
+    double dl[3], du[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const double *la = lo + 3 * pa[q], *ha = hi + 3 * pa[q], *lb = lo + 3 * pb[q],
+                     *hb = hi + 3 * pb[q];
+        dl[q] = fmax(pa[q] == pb[q] ? 0.0 : box_min_dist(la, ha, lb, hb), k.r_min);
+        du[q] = fmax(box_max_dist(la, ha, lb, hb), dl[q]);
+    }
+    double phi_lo, phi_hi;
+    at_bounds(dl[0], dl[1], dl[2], du[0], du[1], du[2], phi_lo, phi_hi);
+
+    // deterministic prune (three distinct nodes)
     if (r.n_roles == 3) {
-        const double e12 = fmax(d12, k.r_min), e13 = fmax(d13, k.r_min), e23 = fmax(d23, k.r_min);
-        const double u12 = fmax(box_max_dist(lo + 3 * p1, hi + 3 * p1, lo + 3 * p2, hi + 3 * p2), e12);
-        const double u13 = fmax(box_max_dist(lo + 3 * p1, hi + 3 * p1, lo + 3 * p3, hi + 3 * p3), e13);
-        const double u23 = fmax(box_max_dist(lo + 3 * p2, hi + 3 * p2, lo + 3 * p3, hi + 3 * p3), e23);
-        double phi_lo, phi_hi;
-        at_bounds(e12, e13, e23, u12, u13, u23, phi_lo, phi_hi);
         double allow = INFINITY;
         for (int q = 0; q < 3; ++q)
             allow = fmin(allow, certified(k, ns, r.node[q], (double)r.t[q], phi_lo, phi_hi));
@@ -348,11 +355,23 @@ __global__ __launch_bounds__(256) void classify_kernel(
             return;
         }
     }
-    // Monte Carlo candidate
+    // Monte Carlo candidate.  A point can pass the stop rule only if its
+    // allowance is >= 0 (z sigma_mu >= 0); the allowance is largest for a
+    // sample mean inside [phi_lo, phi_hi] with sigma_mu = 0, so a node whose
+    // allowance is negative even then fails for certain and the triple skips
+    // the sampling.
     if (k.use_mc) {
         int64_t tmin = r.t[0];
         for (int q = 1; q < r.n_roles; ++q) tmin = min(tmin, r.t[q]);
-        if (tmin > 0 && k.zeta * (double)k.m_limit <= (double)tmin) {
+        bool can_pass = tmin > 0 && k.zeta * (double)k.m_limit <= (double)tmin;
+        for (int q = 0; q < r.n_roles && can_pass; ++q) {
+            const int v = r.node[q];
+            const double t = (double)r.t[q];
+            double best = ns.pos[v] + t * phi_hi;
+            if (k.two_sided) best = fmax(fmax(best, ns.neg[v] - t * phi_lo), ns.mix[v]);
+            can_pass = k.eps * best + k.tau >= 0.0;
+        }
+        if (can_pass) {
             const unsigned long long pos = atomicAdd(&ctr->n_mc, 1ull);
             mc_list[pos] = it;
             return;

@@ -16,6 +16,7 @@
 #include "direct_tile.hpp"
 #include "mb_internal.hpp"
 #include "serve_sched.hpp"
+#include "serve_sizes.hpp"
 
 #include <algorithm>
 #include <chrono>
@@ -107,7 +108,6 @@ double now_s() {
         .count();
 }
 
-int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 
 // Unit enumeration of the exhaustive sum for one request and tile type.
 struct UnitMap {
@@ -133,23 +133,13 @@ struct UnitMap {
     }
 };
 
-int64_t table_bytes(int64_t n, bool f64) {
-    const int64_t ib = f64 ? DirectLds<double>::IB : DirectLds<float>::IB;
-    const int64_t na = (n + ib - 1) / ib, nb = (n + kB - 1) / kB;
-    return na * nb * ib * kB * 3 * (f64 ? 8 : 4);
-}
+// The exhaustive sum's table shapes of the two tile types.
+const serve::TableShape kTab32{DirectLds<float>::IB, kB, 4};
+const serve::TableShape kTab64{DirectLds<double>::IB, kB, 8};
 
-// Device bytes a request holds while admitted: points, Phi, the near-field
-// magnitudes of the binary32 refinement and the (i, j) table.  When binary64
-// may be needed the table region holds either tile type's table (the
-// binary32 table is the smaller one for the default shapes, but not for
-// every shape: an I block wider than twice the binary64 one outgrows it for
-// small N).
-int64_t footprint(int64_t n, bool f64) {
-    const int64_t tab = f64 ? std::max(table_bytes(n, true), table_bytes(n, false))
-                            : table_bytes(n, false);
-    return align256(24 * n) + 2 * align256(8 * n) + align256(tab);
-}
+// Device bytes a request holds while admitted: its whole chunk (points, Phi,
+// near-field magnitudes and a table region that fits either tile type).
+int64_t footprint(int64_t n) { return serve::chunk_layout(n, kTab32, kTab64).total; }
 
 struct Request {
     int64_t id = 0, n = 0;
@@ -163,6 +153,7 @@ struct Request {
     void *chunk = nullptr;
     double *dx = nullptr, *dphi = nullptr, *dmag = nullptr;
     void *dtab = nullptr;
+    int64_t tab_bytes = 0;  // size of the table region at dtab
     double scale = 1.0, out_scale = 1.0;
     UnitMap um;
 };
@@ -245,7 +236,7 @@ public:
         if (n > (int64_t)65535 * kB) return fail(MB_ERR_UNSUPPORTED, "n must be <= 65535 * 64");
         for (int64_t e = 0; e < 3 * n; ++e)
             if (!std::isfinite(hx[e])) return fail(MB_ERR_INVALID, "non-finite coordinate");
-        const int64_t need = footprint(n, true);
+        const int64_t need = footprint(n);
         if (n >= 3 && !sched_.can_ever_fit(need))
             return fail(MB_ERR_OOM, "request needs " + std::to_string(need) +
                                         " device bytes, more than the server's budget");
@@ -381,17 +372,19 @@ private:
     // the validation whose result lands in the slot's pinned record.  No wait.
     mb_status stage_begin(Request &r, int slot) {
         const int64_t n = r.n;
-        if (hipMallocAsync(&r.chunk, footprint(n, true), as_) != hipSuccess) {
+        const serve::ChunkLayout lay = serve::chunk_layout(n, kTab32, kTab64);
+        if (hipMallocAsync(&r.chunk, lay.total, as_) != hipSuccess) {
             r.chunk = nullptr;
             (void)hipGetLastError();
-            return fail(MB_ERR_OOM, "device allocation of " + std::to_string(footprint(n, true)) +
-                                        " bytes failed");
+            return fail(MB_ERR_OOM,
+                        "device allocation of " + std::to_string(lay.total) + " bytes failed");
         }
         char *base = static_cast<char *>(r.chunk);
         r.dx = reinterpret_cast<double *>(base);
-        r.dphi = reinterpret_cast<double *>(base + align256(24 * n));
-        r.dmag = reinterpret_cast<double *>(base + align256(24 * n) + align256(8 * n));
-        r.dtab = base + align256(24 * n) + 2 * align256(8 * n);
+        r.dphi = reinterpret_cast<double *>(base + lay.phi);
+        r.dmag = reinterpret_cast<double *>(base + lay.mag);
+        r.dtab = base + lay.tab;
+        r.tab_bytes = lay.tab_bytes;
         MB_HIP(hipMemcpyAsync(r.dx, r.x.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, as_));
         mb_status st = zero_doubles(r.dphi, n, as_);
         if (st != MB_OK) return st;
@@ -434,6 +427,11 @@ private:
         const double s2 = r.scale * r.scale;
         r.out_scale = s2 * s2 * s2 * s2 * r.scale;
         const bool f64 = r.prec == MB_FP64;
+        // the table kernel must stay inside the chunk's table region
+        if (serve::table_extent(n, f64 ? kTab64 : kTab32) > r.tab_bytes) {
+            why = "pair-term table larger than its region";
+            return MB_ERR_DEVICE;
+        }
         if (f64) r.um.build<double>(n); else r.um.build<float>(n);
         dim3 g((unsigned)r.um.na, (unsigned)r.um.nb);
         if (f64)
@@ -450,7 +448,7 @@ private:
             if (fx != MB_OK) return fx;
         }
         units = r.um.units();
-        keep = footprint(n, f64);
+        keep = footprint(n);  // the chunk keeps its size whichever tile type runs
         return MB_OK;
     }
 
@@ -584,7 +582,7 @@ private:
                 sched_.set_slice_units(slice_request_);
                 slice_request_ = 0;
             }
-            for (int64_t id : inbox_) sched_.enqueue(id, footprint(reqs_.at(id)->n, true));
+            for (int64_t id : inbox_) sched_.enqueue(id, footprint(reqs_.at(id)->n));
             inbox_.clear();
         }
         mb_status st;

@@ -136,6 +136,28 @@ def test_budget_admission(cuda):
         np.testing.assert_allclose(got, one_shot(x, "fp32c", cuda), rtol=1e-12)
 
 
+def test_budget_counts_whole_chunks(cuda):
+    # A budget between one and two request chunks admits one request at a
+    # time: a binary32 request keeps its whole chunk (sized for either tile
+    # type) reserved until it is released, so the live chunks never exceed
+    # the budget.
+    import paper_1105_2769_amd as mb
+
+    n = 600
+    need = 14592 + 2 * 4864 + (19 * 10 * 32 * 64 * 3 * 8)
+    budget = need + need // 2
+    pts = [workloads.jittered_lattice(n, seed=40 + r) for r in range(4)]
+    with server(hbm_budget_bytes=budget, max_slots=8) as srv:
+        ids = [srv.submit(x) for x in pts]
+        assert srv.wait(-1, 60_000)
+        st = srv.stats()
+        res = [srv.result(r) for r in ids]
+    assert st["peak_active"] == 1 and st["peak_reserved"] == need <= budget
+    assert st["fp64_fallbacks"] == 0  # binary32 requests
+    for x, got in zip(pts, res):
+        np.testing.assert_allclose(got, one_shot(x, "fp32c", cuda), rtol=1e-12)
+
+
 def test_many_small_requests_none_lost(cuda):
     g = workloads.rng(11)
     sizes = g.integers(3, 300, size=60)
