@@ -171,7 +171,14 @@ typedef struct {
     int32_t base_prec; /* arithmetic of the exhaustive base cases: MB_FP64 or MB_FP32C */
     int32_t chunk;     /* node triples processed per round of the device stack         */
     int32_t bound;     /* MB_BOUND_SIGNED or MB_BOUND_TWO_SIDED (below)                */
-    int32_t pad;
+    int32_t order;     /* expansion order p of a deterministic prune's estimate, 0..2:
+                          0 = the monopole |P_j| |P_k| phi(c1, c2, c3) of Section 4;
+                          1, 2 = the truncated three-body far-field expansion of
+                          Section 3.2 at each point of a node due to the other two
+                          (mb_farfield_eval), for node triples where every two
+                          nodes have radii summing to at most half their centroid
+                          distance (elsewhere the monopole).  The prune test is
+                          the same for every p.                                     */
 } mb_mt_params;
 
 /*
@@ -202,7 +209,7 @@ enum { MB_BOUND_SIGNED = 0, MB_BOUND_TWO_SIDED = 1 };
  * sampling pays only where it replaces far more tuples than the paper's
  * small zeta suggests; measured on the 65536-point mixture: 7.2 s at
  * zeta 4, 3.8 s at 128, 4.2 s without Monte Carlo),
- * seed 0, base_prec MB_FP32C, chunk 1048576, bound MB_BOUND_SIGNED. */
+ * seed 0, base_prec MB_FP32C, chunk 1048576, bound MB_BOUND_SIGNED, order 0. */
 void mb_mt_params_default(mb_mt_params *p);
 
 typedef struct {
@@ -285,6 +292,23 @@ typedef struct {
  */
 mb_status mb_eval_factorized(const double *x, int64_t n, int32_t fmt, int32_t planes,
                              double r_near, double *phi, mb_factor_stats *stats, void *stream);
+
+/*
+ * The three-body far-field expansion of order p (Section 3.2, its truncated
+ * form) at nx target points due to two source sets: for each target x,
+ *   sum over |a| + |b| <= p of C_ab(x) M_a(Y) M_b(Z),
+ * the degree-p Taylor polynomial of phi(x, cY + u, cZ + v) in the source
+ * displacements (u, v), summed over y in Y and z in Z, with cY, cZ the
+ * centroids and M the moments about them (p = 0: |Y| |Z| phi(x, cY, cZ);
+ * the first-order moments about a centroid vanish, so p = 1 equals p = 0).
+ *   x : device, nx x 3 (nx >= 0);  y : device, ny x 3 (ny >= 1);
+ *   z : device, nz x 3 (nz >= 1);  out : device, nx doubles.
+ *   order : 0, 1 or 2 (MB_ERR_UNSUPPORTED otherwise).
+ * The expansion converges when the sets are small against their distances
+ * to each other and to x; no check is made.  Enqueue only.
+ */
+mb_status mb_farfield_eval(const double *x, int64_t nx, const double *y, int64_t ny,
+                           const double *z, int64_t nz, int32_t order, double *out, void *stream);
 
 /*
  * z such that P(Z > z) = alpha_half for a standard normal Z: the quantile

@@ -88,6 +88,7 @@ from statistics import NormalDist
 
 import numpy as np
 
+from .farfield import farfield
 from .kdtree import KdTree, box_max_dist, box_min_dist, build_kdtree
 from .philox import philox4x32_10_np
 
@@ -322,6 +323,28 @@ def at_bounds(lo: tuple[float, float, float], up: tuple[float, float, float]) ->
     return phi_lo, phi_hi
 
 
+def node_radius(tree: KdTree, v: int) -> float:
+    """Largest distance from the centroid of node v to a corner of its box."""
+    c = tree.centroid[v]
+    d = np.maximum(tree.hi[v] - c, c - tree.lo[v])
+    return float(np.sqrt(d @ d))
+
+
+def well_separated(tree: KdTree, p: tuple[int, int, int], theta: float = 0.5) -> bool:
+    """Whether every two nodes of the triple satisfy r_a + r_b <= theta |c_a - c_b|.
+
+    The far-field expansion of Section 3.2 is a Taylor series in the
+    displacements of P2's and P3's points from their centres; it converges
+    only when the nodes are small against their distances (a multipole
+    acceptance criterion).  Triples that fail it keep the p = 0 estimate.
+    """
+    for u, v in ((p[0], p[1]), (p[0], p[2]), (p[1], p[2])):
+        d = tree.centroid[u] - tree.centroid[v]
+        if node_radius(tree, u) + node_radius(tree, v) > theta * float(np.sqrt(d @ d)):
+            return False
+    return True
+
+
 def closest_pair(x: np.ndarray) -> float:
     """Smallest distance between two points of the set (brute force over all pairs)."""
     best = math.inf
@@ -436,7 +459,7 @@ class MTResult:
 
 def multitree(x, eps: float, alpha: float, leaf_size: int, tau: float = 0.0, seed: int = 0,
               m_limit: int = 128, zeta: float = 4.0, m_min: int = 30,
-              bound: str = "signed") -> MTResult:
+              bound: str = "signed", order: int = 0) -> MTResult:
     """The traversal.  ``bound`` chooses the node statistic of the prune rules:
 
     * "signed": the paper's running lower bound Phi^l (Section 4.1);
@@ -444,10 +467,19 @@ def multitree(x, eps: float, alpha: float, leaf_size: int, tau: float = 0.0, see
       and upper bounds LB, UB per point, and the allowance is a lower bound
       on max(LB, -UB), i.e. on |Phi| when its sign is settled (see
       ``certified``); for potentials >= 0 it is the paper's rule.
+
+    ``order`` is the expansion order p of a deterministic prune's estimate:
+    0 is the monopole of Section 4 (every point of P_i gets T_i phi(c1, c2,
+    c3)); p >= 1 is the truncated three-body far-field expansion of Section
+    3.2 at each point x of P_i due to the other two nodes (``farfield``),
+    kept inside [T_i phi_lo, T_i phi_hi], for node triples where it
+    converges (``well_separated``; others keep the monopole).  The prune
+    test itself is the same for every p (the paper states no error bound for
+    p > 0).
     """
     x = np.asarray(x, dtype=np.float64)
     n = x.shape[0]
-    if eps < 0 or tau < 0 or not (0.0 <= alpha < 1.0) or leaf_size < 1:
+    if eps < 0 or tau < 0 or not (0.0 <= alpha < 1.0) or leaf_size < 1 or order < 0:
         raise ValueError("bad multitree parameters")
     if bound not in ("signed", "two_sided"):
         raise ValueError("bound must be 'signed' or 'two_sided'")
@@ -490,8 +522,15 @@ def multitree(x, eps: float, alpha: float, leaf_size: int, tau: float = 0.0, see
             allow = min(certified(bound, phi_l(node), t, phi_lo, phi_hi) for node, t, _ in roles)
             if phi_hi - phi_lo <= (eps * allow + tau) / t_root:
                 phic = float(at_phi_np(tree.centroid[p1], tree.centroid[p2], tree.centroid[p3]))
-                for node, t, _ in roles:
-                    node_acc[node] += t * phic
+                use_ff = order > 0 and well_separated(tree, p)
+                for node, t, slot in roles:
+                    if not use_ff:
+                        node_acc[node] += t * phic
+                    else:
+                        oth = [xs[pts(v)] for q_, v in enumerate(p) if q_ != slot]
+                        for r_ in range(int(tree.begin[node]), int(tree.end[node])):
+                            f = farfield(xs[r_], oth[0], oth[1], order)
+                            est[r_] += min(max(f, t * phi_lo), t * phi_hi)
                     lb[pts(node)] += t * phi_lo
                     ub[pts(node)] += t * phi_hi
                     cov[pts(node)] += t

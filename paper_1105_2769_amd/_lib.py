@@ -45,7 +45,7 @@ class MtParams(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("m_limit", ctypes.c_int32),
                 ("m_min", ctypes.c_int32), ("zeta", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("base_prec", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("bound", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32), ("bound", ctypes.c_int32), ("order", ctypes.c_int32)]
 
 
 class MtStats(ctypes.Structure):
@@ -96,6 +96,8 @@ SIGNATURES = {
     "mb_eval_multitree": (_c_i32, [_c_vp, _c_i64, _c_i32, ctypes.POINTER(MtParams), _c_vp, _c_vp,
                                    _c_vp, ctypes.POINTER(MtStats), _c_vp]),
     "mb_normal_quantile": (_c_dbl, [_c_dbl]),
+    "mb_farfield_eval": (_c_i32, [_c_vp, _c_i64, _c_vp, _c_i64, _c_vp, _c_i64, _c_i32, _c_vp,
+                                  _c_vp]),
     "mb_eval_factorized": (_c_i32, [_c_vp, _c_i64, _c_i32, _c_i32, _c_dbl, _c_vp,
                                     ctypes.POINTER(FactorStats), _c_vp]),
     "mb_server_create": (_c_i32, [_c_i64, _c_i32, _c_vp, ctypes.POINTER(_c_vp)]),
@@ -249,6 +251,18 @@ def eval_multitree(x, eps: float = 1e-2, alpha: float = 0.05, leaf_size: int = 3
     if coverage:
         return phi, st.as_dict(), cov
     return phi, st.as_dict()
+
+
+def farfield_eval(x, y, z, order: int):
+    """Far-field expansion at targets x due to source sets y, z (mb_farfield_eval)."""
+    import torch
+
+    x, y, z = _points(x), _points(y), _points(z)
+    out = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
+    check(lib().mb_farfield_eval(_c_vp(x.data_ptr()), x.shape[0], _c_vp(y.data_ptr()), y.shape[0],
+                                 _c_vp(z.data_ptr()), z.shape[0], int(order),
+                                 _c_vp(out.data_ptr()), stream_of(x)))
+    return out
 
 
 def normal_quantile(alpha_half: float) -> float:

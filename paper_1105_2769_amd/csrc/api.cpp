@@ -239,7 +239,7 @@ void mb_mt_params_default(mb_mt_params *p) {
     p->base_prec = MB_FP32C;
     p->chunk = 1 << 20;  // fewer rounds: each round ends in a host wait for the stack size
     p->bound = MB_BOUND_SIGNED;
-    p->pad = 0;
+    p->order = 0;
 }
 
 mb_status mb_eval_multitree(const double *x, int64_t n, int32_t leaf_size,
@@ -251,7 +251,8 @@ mb_status mb_eval_multitree(const double *x, int64_t n, int32_t leaf_size,
     if (n < 0 || (n > 0 && (!x || !phi))) return fail(MB_ERR_INVALID, "bad points or output");
     if (!(p.eps_rel >= 0.0) || !(p.tau_abs >= 0.0) || !(p.alpha >= 0.0 && p.alpha < 1.0) ||
         p.m_limit < 2 || p.m_min < 2 || !(p.zeta >= 0.0) || p.chunk < 1 ||
-        (p.bound != MB_BOUND_SIGNED && p.bound != MB_BOUND_TWO_SIDED) ||
+        (p.bound != MB_BOUND_SIGNED && p.bound != MB_BOUND_TWO_SIDED) || p.order < 0 ||
+        p.order > 2 ||
         (p.base_prec != MB_FP64 && p.base_prec != MB_FP32C))
         return fail(MB_ERR_INVALID, "bad traversal parameters");
     if (n >= ((int64_t)1 << 31)) return fail(MB_ERR_UNSUPPORTED, "n must be < 2^31");
@@ -285,6 +286,7 @@ mb_status mb_eval_multitree(const double *x, int64_t n, int32_t leaf_size,
     mp.base_prec = p.base_prec;
     mp.chunk = p.chunk;
     mp.bound = p.bound;
+    mp.order = p.order;
     {
         double md2;
         std::memcpy(&md2, &v.min_d2_bits, sizeof md2);
@@ -339,6 +341,15 @@ mb_status mb_eval_factorized(const double *x, int64_t n, int32_t fmt, int32_t pl
         stats->gemm_flops = fs.gemm_flops;
     }
     return st;
+}
+
+mb_status mb_farfield_eval(const double *x, int64_t nx, const double *y, int64_t ny,
+                           const double *z, int64_t nz, int32_t order, double *out, void *stream) {
+    clear_error();
+    if (nx < 0 || ny < 1 || nz < 1 || (nx > 0 && (!x || !out)) || !y || !z)
+        return fail(MB_ERR_INVALID, "bad point sets or output");
+    if (order < 0 || order > 2) return fail(MB_ERR_UNSUPPORTED, "order must be 0, 1 or 2");
+    return farfield_eval(x, nx, y, ny, z, nz, order, out, (hipStream_t)stream);
 }
 
 double mb_normal_quantile(double alpha_half) { return normal_quantile_upper(alpha_half); }

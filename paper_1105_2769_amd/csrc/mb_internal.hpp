@@ -137,6 +137,12 @@ double unit_scale(double min_d2);
 // binary32 law-of-cosines terms lose about log2(spacing / pair) bits.
 bool fp32c_suitable(const ValidateOut &v, int64_t n);
 
+// The far-field expansion of order `order` (0..2) at nx target points x due
+// to the source sets y (ny points) and z (nz), about their centroids; out
+// receives one value per target.  Enqueue only.
+mb_status farfield_eval(const double *x, int64_t nx, const double *y, int64_t ny, const double *z,
+                        int64_t nz, int order, double *out, hipStream_t s);
+
 struct FactorStats {
     double pairmat_ms = 0.0, gemm_ms = 0.0, near_ms = 0.0;
     int64_t near_pairs = 0;

@@ -47,6 +47,7 @@
 
 #include "at_device.hpp"
 #include "direct_tile.hpp"
+#include "farfield.hpp"
 #include "mb_internal.hpp"
 #include "multitree.hpp"
 #include "tree.hpp"
@@ -59,7 +60,7 @@ struct Item {
 };
 
 struct MtCounters {
-    unsigned long long n_base, n_mc, n_units, n_short;
+    unsigned long long n_base, n_mc, n_units, n_short, n_far;
     unsigned long long det_prunes, mc_prunes, mc_failed, base_cases, base_triples,
         mc_samples;
 };
@@ -74,6 +75,14 @@ struct MtConst {
     int use_mc;
     int want_cov;
     int two_sided;  // allowance from both running bounds (MB_BOUND_TWO_SIDED)
+    int order;      // expansion order of a deterministic prune's estimate (0..2)
+};
+
+// A deterministically pruned node triple whose estimate is the far-field
+// expansion at each point, with the bounds of its phi.
+struct FarItem {
+    int32_t p1, p2, p3, pad;
+    double lo, hi;
 };
 
 // Node statistics of the prune rules, refreshed once per round: over the
@@ -193,6 +202,33 @@ __device__ __forceinline__ double phi3(const double *a, const double *b, const d
     return phi_from_pairs<double>(ab, qab, wab, ac, qac, wac, bc, qbc, wbc);
 }
 
+// Largest distance from node v's centroid to a corner of its box.
+__device__ __forceinline__ double node_radius(const NodeView &nv, int v) {
+    double s2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double m = nv.centroid[3 * v + c];
+        const double d = fmax(nv.hi[3 * v + c] - m, m - nv.lo[3 * v + c]);
+        s2 = fma(d, d, s2);
+    }
+    return sqrt(s2);
+}
+
+// The far-field expansion is a Taylor series in the displacements of the
+// source points from their centres; it converges only for nodes small
+// against their distances.  Accepted when every two nodes of the triple
+// have r_a + r_b <= 1/2 |c_a - c_b|.
+__device__ __forceinline__ bool well_separated(const NodeView &nv, int p1, int p2, int p3) {
+    const int a[3] = {p1, p1, p2}, b[3] = {p2, p3, p3};
+    for (int q = 0; q < 3; ++q) {
+        const double *ca = nv.centroid + 3 * a[q], *cb = nv.centroid + 3 * b[q];
+        const double dx = ca[0] - cb[0], dy = ca[1] - cb[1], dz = ca[2] - cb[2];
+        const double d = sqrt(fma(dx, dx, fma(dy, dy, dz * dz)));
+        if (node_radius(nv, a[q]) + node_radius(nv, b[q]) > 0.5 * d) return false;
+    }
+    return true;
+}
+
 // Distinct nodes of a canonical triple, each with its T_i and its first slot.
 struct Roles {
     int n_roles;
@@ -290,7 +326,7 @@ __global__ __launch_bounds__(256) void classify_kernel(
     unsigned long long *__restrict__ node_cov, MtConst k, MtCounters *__restrict__ ctr,
     Item *__restrict__ mc_list, Item *__restrict__ base_list, Item *__restrict__ child_buf,
     uint8_t *__restrict__ child_flag, double spread_limit, Item *__restrict__ defer_buf,
-    uint8_t *__restrict__ defer_flag) {
+    uint8_t *__restrict__ defer_flag, FarItem *__restrict__ far_list) {
     const int slot = blockIdx.x * blockDim.x + threadIdx.x;
     if (slot >= n_items) return;
     Item it = items[slot];
@@ -342,11 +378,19 @@ __global__ __launch_bounds__(256) void classify_kernel(
         for (int q = 0; q < 3; ++q)
             allow = fmin(allow, certified(k, ns, r.node[q], (double)r.t[q], phi_lo, phi_hi));
         if (phi_hi - phi_lo <= (k.eps * allow + k.tau) / k.t_root) {
-            // monopole estimate at the centroids, kept inside the bound interval
-            double phic = phi3(nv.centroid + 3 * p1, nv.centroid + 3 * p2, nv.centroid + 3 * p3);
-            phic = isfinite(phic) ? fmin(fmax(phic, phi_lo), phi_hi) : 0.5 * (phi_lo + phi_hi);
+            if (k.order >= 1 && well_separated(nv, p1, p2, p3)) {
+                // the far-field expansion at each point (far_kernel)
+                const unsigned long long pos = atomicAdd(&ctr->n_far, 1ull);
+                far_list[pos] = FarItem{p1, p2, p3, 0, phi_lo, phi_hi};
+            } else {
+                // monopole estimate at the centroids, kept inside the bound interval
+                double phic =
+                    phi3(nv.centroid + 3 * p1, nv.centroid + 3 * p2, nv.centroid + 3 * p3);
+                phic = isfinite(phic) ? fmin(fmax(phic, phi_lo), phi_hi) : 0.5 * (phi_lo + phi_hi);
+                for (int q = 0; q < 3; ++q)
+                    atomicAdd(&node_acc[r.node[q]], (double)r.t[q] * phic);
+            }
             for (int q = 0; q < 3; ++q) {
-                atomicAdd(&node_acc[r.node[q]], (double)r.t[q] * phic);
                 atomicAdd(&node_lo[r.node[q]], (double)r.t[q] * phi_lo);
                 atomicAdd(&node_hi[r.node[q]], (double)r.t[q] * phi_hi);
                 if (k.want_cov) atomicAdd(&node_cov[r.node[q]], (unsigned long long)r.t[q]);
@@ -870,11 +914,103 @@ __global__ __launch_bounds__((LeafLds<T, KR>::TPB)) void leaf_tile_kernel(
     }
 }
 
+// Far-field estimates of the round's far items: one workgroup per item; each
+// point x of each node gets the expansion of order k.order due to the other
+// two nodes (farfield.hpp), kept inside [T phi_lo, T phi_hi], in fest[x].
+__global__ __launch_bounds__(256) void far_kernel(const FarItem *__restrict__ far_list,
+                                                  NodeView nv, const double *__restrict__ xs,
+                                                  const double *__restrict__ smom, MtConst k,
+                                                  const MtCounters *__restrict__ ctr,
+                                                  double *__restrict__ fest) {
+    const int n_far = (int)ctr->n_far;
+    for (int w = blockIdx.x; w < n_far; w += gridDim.x) {
+        const FarItem it = far_list[w];
+        const int pn[3] = {it.p1, it.p2, it.p3};
+        const int b0 = nv.begin[pn[0]], b1 = nv.begin[pn[1]], b2 = nv.begin[pn[2]];
+        const int c0 = nv.end[pn[0]] - b0, c1 = nv.end[pn[1]] - b1, c2 = nv.end[pn[2]] - b2;
+        const int total = c0 + c1 + c2;
+        for (int e = threadIdx.x; e < total; e += blockDim.x) {
+            const int q = e < c0 ? 0 : (e < c0 + c1 ? 1 : 2);
+            const int r = q == 0 ? b0 + e : (q == 1 ? b1 + e - c0 : b2 + e - c0 - c1);
+            const int va = pn[q == 0 ? 1 : 0], vb = pn[q == 2 ? 1 : 2];
+            const double na = (double)(nv.end[va] - nv.begin[va]);
+            const double nb = (double)(nv.end[vb] - nv.begin[vb]);
+            const double x[3] = {xs[3 * (int64_t)r], xs[3 * (int64_t)r + 1], xs[3 * (int64_t)r + 2]};
+            double f = farfield_value(x, nv.centroid + 3 * va, nv.centroid + 3 * vb, na, nb,
+                                      smom + 6 * va, smom + 6 * vb, k.order);
+            const double t = na * nb;
+            f = isfinite(f) ? fmin(fmax(f, t * it.lo), t * it.hi) : 0.5 * t * (it.lo + it.hi);
+            atomicAdd(&fest[r], f);
+        }
+    }
+}
+
+// Second-moment matrices sum (y - c)(y - c)^T of every node about its
+// centroid: leaves from their points, then parents by the parallel-axis
+// rule, depth by depth in one workgroup.
+__global__ void leaf_moments_kernel(const int32_t *__restrict__ leaves, int n_leaves,
+                                    const int32_t *__restrict__ begin,
+                                    const int32_t *__restrict__ end,
+                                    const double *__restrict__ xs,
+                                    const double *__restrict__ centroid,
+                                    double *__restrict__ smom) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_leaves) return;
+    const int v = leaves[e];
+    const double *c = centroid + 3 * v;
+    double m[6] = {0, 0, 0, 0, 0, 0};
+    for (int r = begin[v]; r < end[v]; ++r) {
+        const double d0 = xs[3 * (int64_t)r] - c[0], d1 = xs[3 * (int64_t)r + 1] - c[1],
+                     d2 = xs[3 * (int64_t)r + 2] - c[2];
+        m[0] += d0 * d0;
+        m[1] += d0 * d1;
+        m[2] += d0 * d2;
+        m[3] += d1 * d1;
+        m[4] += d1 * d2;
+        m[5] += d2 * d2;
+    }
+    for (int i = 0; i < 6; ++i) smom[6 * v + i] = m[i];
+}
+
+__global__ __launch_bounds__(1024) void up_moments_kernel(const int32_t *__restrict__ depth_nodes,
+                                                          const int *__restrict__ depth_off,
+                                                          int n_depths,
+                                                          const int32_t *__restrict__ left,
+                                                          const int32_t *__restrict__ right,
+                                                          const int32_t *__restrict__ begin,
+                                                          const int32_t *__restrict__ end,
+                                                          const double *__restrict__ centroid,
+                                                          double *__restrict__ smom) {
+    for (int d = n_depths - 1; d >= 0; --d) {
+        for (int e = depth_off[d] + threadIdx.x; e < depth_off[d + 1]; e += blockDim.x) {
+            const int v = depth_nodes[e];
+            if (left[v] < 0) continue;
+            double m[6] = {0, 0, 0, 0, 0, 0};
+            for (const int ch : {left[v], right[v]}) {
+                const double w = (double)(end[ch] - begin[ch]);
+                const double d0 = centroid[3 * ch] - centroid[3 * v];
+                const double d1 = centroid[3 * ch + 1] - centroid[3 * v + 1];
+                const double d2 = centroid[3 * ch + 2] - centroid[3 * v + 2];
+                const double *s = smom + 6 * ch;
+                m[0] += s[0] + w * d0 * d0;
+                m[1] += s[1] + w * d0 * d1;
+                m[2] += s[2] + w * d0 * d2;
+                m[3] += s[3] + w * d1 * d1;
+                m[4] += s[4] + w * d1 * d2;
+                m[5] += s[5] + w * d2 * d2;
+            }
+            for (int i = 0; i < 6; ++i) smom[6 * v + i] = m[i];
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void reset_round_kernel(MtCounters *ctr) {
     ctr->n_base = 0;
     ctr->n_mc = 0;
     ctr->n_units = 0;
     ctr->n_short = 0;
+    ctr->n_far = 0;
 }
 
 __global__ void zero_u64_kernel(unsigned long long *__restrict__ p, int64_t n) {
@@ -884,7 +1020,8 @@ __global__ void zero_u64_kernel(unsigned long long *__restrict__ p, int64_t n) {
 }
 
 __global__ void zero_counters_kernel(MtCounters *ctr) {
-    ctr->n_base = ctr->n_mc = ctr->n_units = ctr->n_short = ctr->det_prunes = ctr->mc_prunes = 0;
+    ctr->n_base = ctr->n_mc = ctr->n_units = ctr->n_short = ctr->n_far = 0;
+    ctr->det_prunes = ctr->mc_prunes = 0;
     ctr->mc_failed = ctr->base_cases = ctr->base_triples = ctr->mc_samples = 0;
 }
 
@@ -962,12 +1099,13 @@ __global__ __launch_bounds__(1024) void refresh_up_kernel(const int32_t *__restr
 // 6. Top-down (Section 3): node accumulators to points, back to input order.
 __global__ void topdown_kernel(int n, const int32_t *__restrict__ leaf_of,
                                const int32_t *__restrict__ parent, const int32_t *__restrict__ perm,
-                               const double *__restrict__ est, const double *__restrict__ node_acc,
+                               const double *__restrict__ est, const double *__restrict__ fest,
+                               const double *__restrict__ node_acc,
                                const unsigned long long *__restrict__ node_cov,
                                double *__restrict__ phi, int64_t *__restrict__ coverage) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    double acc = est[r];
+    double acc = est[r] + fest[r];
     unsigned long long cv = 0;
     for (int v = leaf_of[r]; v >= 0; v = parent[v]) {
         acc += node_acc[v];
@@ -1063,22 +1201,30 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
     MtCounters *ctr;
     int32_t *d_leaves;
     int *d_doff;
-    if ((st = dalloc(s_pt, &pt, 2 * (size_t)n, s)) || (st = dalloc(s_nd, &nd, 8 * (size_t)M, s)) ||
+    if ((st = dalloc(s_pt, &pt, 3 * (size_t)n, s)) || (st = dalloc(s_nd, &nd, 14 * (size_t)M, s)) ||
         (st = dalloc(s_cov, &node_cov, M, s)) || (st = dalloc(s_ctr, &ctr, 1, s)) ||
         (st = dalloc(s_leaves, &d_leaves, leaves.size(), s)) ||
         (st = dalloc(s_doff, &d_doff, t->depth_off.size(), s)))
         return st;
-    double *est = pt, *dev = pt + n;
+    double *est = pt, *dev = pt + n, *fest = pt + 2 * (size_t)n;  // fest: far-field estimates
     double *node_acc = nd, *node_lo = nd + M, *node_hi = nd + 2 * (size_t)M;
     double *st_pos = nd + 3 * (size_t)M, *st_neg = nd + 4 * (size_t)M, *st_mix = nd + 5 * (size_t)M;
     double *cum_lo = nd + 6 * (size_t)M, *cum_hi = nd + 7 * (size_t)M;
+    double *smom = nd + 8 * (size_t)M;  // second moments, 6 per node
     const NodeStats ns{st_pos, st_neg, st_mix};
     MB_HIP(hipMemcpyAsync(d_leaves, leaves.data(), sizeof(int32_t) * leaves.size(),
                           hipMemcpyHostToDevice, s));
     MB_HIP(hipMemcpyAsync(d_doff, t->depth_off.data(), sizeof(int) * t->depth_off.size(),
                           hipMemcpyHostToDevice, s));
-    if ((st = zero_doubles(pt, 2 * (int64_t)n, s)) != MB_OK) return st;
-    if ((st = zero_doubles(nd, 8 * (int64_t)M, s)) != MB_OK) return st;
+    if ((st = zero_doubles(pt, 3 * (int64_t)n, s)) != MB_OK) return st;
+    if ((st = zero_doubles(nd, 14 * (int64_t)M, s)) != MB_OK) return st;
+    if (prm.order >= 2) {
+        leaf_moments_kernel<<<((int)leaves.size() + 255) / 256, 256, 0, s>>>(
+            d_leaves, (int)leaves.size(), t->begin, t->end, t->xs, t->centroid, smom);
+        up_moments_kernel<<<1, 1024, 0, s>>>(t->depth_nodes, d_doff, n_depths, t->left, t->right,
+                                             t->begin, t->end, t->centroid, smom);
+        MB_HIP(hipGetLastError());
+    }
     zero_u64_kernel<<<(M + 255) / 256, 256, 0, s>>>(node_cov, M);
     zero_counters_kernel<<<1, 1, 0, s>>>(ctr);
 
@@ -1087,8 +1233,9 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
     // boxes are pairwise apart are deferred to the far stack meanwhile
     int64_t cap = std::max<int64_t>(16 * (int64_t)chunk, 1 << 16);
     int64_t fcap = cap;
-    Scratch s_stack, s_far, s_mc, s_base, s_child, s_flag, s_dbuf, s_dflag, s_num, s_tmp;
+    Scratch s_stack, s_far, s_mc, s_base, s_child, s_flag, s_dbuf, s_dflag, s_num, s_tmp, s_flist;
     Item *stack, *far, *mc_list, *base_list, *child_buf, *defer_buf;
+    FarItem *far_list;
     uint8_t *child_flag, *defer_flag;
     int *d_num;
     if ((st = dalloc(s_stack, &stack, cap, s)) || (st = dalloc(s_far, &far, fcap, s)) ||
@@ -1096,7 +1243,8 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
         (st = dalloc(s_child, &child_buf, 8 * (size_t)chunk, s)) ||
         (st = dalloc(s_flag, &child_flag, 8 * (size_t)chunk, s)) ||
         (st = dalloc(s_dbuf, &defer_buf, chunk, s)) || (st = dalloc(s_dflag, &defer_flag, chunk, s)) ||
-        (st = dalloc(s_num, &d_num, 2, s)))
+        (st = dalloc(s_num, &d_num, 2, s)) ||
+        (st = dalloc(s_flist, &far_list, prm.order >= 1 ? chunk : 1, s)))
         return st;
     size_t tmp_bytes = 0;
     MB_HIP(hipcub::DeviceSelect::Flagged(nullptr, tmp_bytes, child_buf, child_flag, stack, d_num,
@@ -1186,6 +1334,7 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
     k.use_mc = prm.alpha > 0.0 ? 1 : 0;
     k.want_cov = coverage ? 1 : 0;
     k.two_sided = prm.bound == MB_BOUND_TWO_SIDED ? 1 : 0;
+    k.order = prm.order;
 
     auto grow = [&](Scratch &sc, Item *&buf, int64_t &c, int64_t keep, int64_t need) -> mb_status {
         if (need <= c) return MB_OK;
@@ -1243,7 +1392,9 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
         classify_kernel<<<(B + 255) / 256, 256, 0, s>>>(items, B, nv, ns, node_acc, node_lo,
                                                        node_hi, node_cov, k, ctr, mc_list,
                                                        base_list, child_buf, child_flag, limit,
-                                                       defer_buf, defer_flag);
+                                                       defer_buf, defer_flag, far_list);
+        if (k.order >= 1)
+            far_kernel<<<std::min(B, 2048), 256, 0, s>>>(far_list, nv, t->xs, smom, k, ctr, fest);
         if (k.use_mc)
             mc_kernel<<<std::min(B, 4096), kMcThreads, 0, s>>>(mc_list, nv, t->xs, ns, est, dev,
                                                                node_cov, k, ctr, base_list,
@@ -1305,8 +1456,8 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
                          hc.det_prunes, hc.mc_prunes, hc.mc_failed, hc.base_cases);
         }
     }
-    topdown_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, t->leaf_of, t->parent, t->perm, est, node_acc,
-                                                   node_cov, phi, coverage);
+    topdown_kernel<<<(n + 255) / 256, 256, 0, s>>>(n, t->leaf_of, t->parent, t->perm, est, fest,
+                                                   node_acc, node_cov, phi, coverage);
     MB_HIP(hipGetLastError());
     MtCounters hc;
     MB_HIP(hipMemcpyAsync(&hc, ctr, sizeof hc, hipMemcpyDeviceToHost, s));

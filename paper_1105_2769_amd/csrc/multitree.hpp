@@ -21,6 +21,7 @@ struct MtParams {
     // 0 disables the bands (one LIFO stack)
     double spread_unit = 0.0;
     int bound = MB_BOUND_SIGNED;  // or MB_BOUND_TWO_SIDED (running lower and upper bounds)
+    int order = 0;  // 0: monopole estimate of a prune; 1, 2: far-field expansion at each point
 };
 
 struct MtStats {
