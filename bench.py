@@ -30,8 +30,12 @@ Extra fields:
                  against the binary64 GPU sum on sampled requests.
   multitree    - the triple-tree traversal on the N = 262144 Gaussian-mixture
                  set (eps 1e-2, alpha 0.05, leaf 32, FP32C base cases,
-                 magnitude bound), effective triples/s = C(N, 3) / time and
-                 the fraction of the 64 stored oracle samples within eps.
+                 two-sided statistic), effective triples/s = C(N, 3) / time,
+                 the fraction of the stored oracle samples within eps with
+                 its 95 % Wilson interval, the device time of each phase and
+                 the base cases' fraction of the binary32 vector peak; the
+                 far-field orders 1 and 2; the paper's signed statistic
+                 beside the two-sided one on a 65536-point mixture.
   factorized   - the matrix-product form (FP16, two planes, r_near = 1.5)
                  on the N = 16384 lattice (seed 4) against the binary64 GPU
                  sum on all points.
@@ -158,6 +162,18 @@ def main() -> int:
                "sample": f"full sums of {m} seeded-sampled particles of the N={n} workload "
                          f"({evals:.3e} phi evaluations, {dt:.1f} s); triples/s = evaluations/3/s "
                          f"since all-particle Phi takes 3 C(N,3) evaluations by this loop"}
+        # one core, and the whole all-particle sum extrapolated from the rates
+        m1 = 2
+        print(f"cpu oracle: {m1} particles on 1 thread", flush=True)
+        t0 = time.perf_counter()
+        oracle_direct.phi(x_np, sample_idx[:m1], threads=1)
+        dt1 = time.perf_counter() - t0
+        evals1 = m1 * (n - 1) * (n - 2) // 2
+        cpu["one_core"] = {"value": evals1 / 3.0 / dt1, "unit": "triples/s", "cores": 1,
+                           "sample": f"full sums of {m1} particles ({dt1:.1f} s)"}
+        cpu["full_n_seconds_extrapolated"] = {
+            "all_cores": 3.0 * triples / (evals / dt),
+            "one_core": 3.0 * triples / (evals1 / dt1)}
 
     results = {}
     precs = ["fp64", "fp32c"] if args.prec == "both" else [args.prec]
@@ -324,10 +340,43 @@ def serve_leg(n_req: int, dev) -> dict:
     return out
 
 
-def multitree_leg(n: int, dev) -> dict:
-    """The triple-tree traversal on the Gaussian-mixture set (eps 1e-2, alpha 0.05)."""
+def wilson(k: int, m: int, z: float = 1.959963984540054) -> tuple:
+    """95 % Wilson score interval of a binomial proportion k / m."""
+    p = k / m
+    c = (p + z * z / (2 * m)) / (1 + z * z / m)
+    h = z * math.sqrt(p * (1 - p) / m + z * z / (4 * m * m)) / (1 + z * z / m)
+    return c - h, c + h
+
+
+def c3_golden():
+    """Oracle values at the seeded-sampled points of the 262144-point mixture."""
     import json as _json
 
+    import numpy as np
+
+    here = os.path.join(ROOT, "tests", "golden")
+    g = _json.load(open(os.path.join(here, "c3_direct_samples.json")))
+    idx, ref = list(g["indices"]), [float(v) for v in g["phi"]]
+    extra = os.path.join(here, "c3_direct_samples_extra.json")
+    if os.path.exists(extra):
+        e = _json.load(open(extra))
+        idx += e["indices"]
+        ref += [float(v) for v in e["phi"]]
+    return np.array(idx), np.array(ref)
+
+
+def multitree_leg(n: int, dev) -> dict:
+    """The triple-tree traversal on the Gaussian-mixture set (eps 1e-2, alpha 0.05).
+
+    The run the leg is quoted on: two-sided statistic, monopole prunes
+    (order 0), FP32C base cases, against the stored oracle values with the
+    95 % Wilson interval of the fraction within eps; then the far-field
+    orders 1 and 2 on the same set, and the paper's signed statistic next to
+    the two-sided one on the first 65536-point mixture (the signed one at
+    the full size runs most of the exhaustive sum, ~20 minutes).  Base-case
+    roofline: 19 flops per base triple over the device time of the base-case
+    phase, against the binary32 vector peak.
+    """
     import numpy as np
     import torch
 
@@ -337,38 +386,80 @@ def multitree_leg(n: int, dev) -> dict:
     print(f"multitree: generating the N={n} Gaussian mixture", flush=True)
     x_np = workloads.saturated_gaussian_mixture(n, seed=3)
     x = torch.from_numpy(x_np).to(dev)
-    golden = os.path.join(ROOT, "tests", "golden", "c3_direct_samples.json")
-    if n == 262144 and os.path.exists(golden):
-        g = _json.load(open(golden))
-        idx = np.array(g["indices"])
-        ref = np.array([float(v) for v in g["phi"]])
-        ref_kind = "CPU oracle at 64 seeded-sampled points"
+    if n == 262144:
+        idx, ref = c3_golden()
+        ref_kind = f"CPU oracle at {idx.size} seeded-sampled points (tests/golden)"
     else:
         idx = np.arange(n)
         ref = mb.eval_direct(x, prec="fp64").cpu().numpy()
         ref_kind = "binary64 GPU sum at every point"
-    out = {"workload": f"N={n} saturated 32-component Gaussian mixture (means U[0,100]^3, "
-                       f"sigma 2, min separation 0.3, seed 3), leaf 32, eps 1e-2, alpha 0.05, "
-                       f"FP32C base cases, magnitude bound", "reference": ref_kind}
-    for bound in ("magnitude",):
-        print(f"multitree: bound {bound}", flush=True)
+
+    def run(xt, bound, order, ids, refs):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        phi, st = mb.eval_multitree(x, eps=1e-2, alpha=0.05, leaf_size=32, bound=bound)
+        phi, st = mb.eval_multitree(xt, eps=1e-2, alpha=0.05, leaf_size=32, bound=bound,
+                                    order=order)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        rel = np.abs(phi.cpu().numpy()[idx] - ref) / np.abs(ref)
-        out.update({
-            "seconds": dt,
-            "triples_per_s": comb3(n) / dt,
-            "within_eps_fraction": float(np.mean(rel <= 1e-2)),
-            "max_rel_err": float(rel.max()),
-            "median_rel_err": float(np.median(rel)),
-            "exhaustive_fraction": st["base_triples"] / comb3(n),
-            "stats": st,
-        })
-        print(f"multitree: {dt:.1f} s, {comb3(n) / dt:.3e} effective triples/s, within eps "
-              f"{out['within_eps_fraction']:.3f}", flush=True)
+        nn = xt.shape[0]
+        rel = np.abs(phi.cpu().numpy()[ids] - refs) / np.abs(refs)
+        k = int(np.sum(rel <= 1e-2))
+        lo, hi = wilson(k, rel.size)
+        base_tflops = FLOPS_PER_TRIPLE * st["base_triples"] / (st["base_ms"] * 1e-3) / 1e12 \
+            if st["base_ms"] > 0 else None
+        return {"seconds": dt, "triples_per_s": comb3(nn) / dt,
+                "within_eps": f"{k}/{rel.size}", "within_eps_fraction": k / rel.size,
+                "wilson95": [lo, hi], "max_rel_err": float(rel.max()),
+                "median_rel_err": float(np.median(rel)),
+                "exhaustive_fraction": st["base_triples"] / comb3(nn),
+                "phase_ms": {"classify": st["classify_ms"], "monte_carlo": st["mc_ms"],
+                             "base_cases": st["base_ms"]},
+                "base_roofline": {"bound": "alu", "achieved": base_tflops, "peak": 157.3,
+                                  "unit": "TFLOP/s",
+                                  "frac": base_tflops / 157.3 if base_tflops else None,
+                                  "base_triples_per_s": st["base_triples"] / (st["base_ms"] * 1e-3)
+                                  if st["base_ms"] > 0 else None},
+                "mc_samples_per_s": st["mc_samples"] / (st["mc_ms"] * 1e-3) if st["mc_ms"] > 0
+                else None,
+                "stats": st}
+
+    out = {"workload": f"N={n} saturated 32-component Gaussian mixture (means U[0,100]^3, "
+                       f"sigma 2, min separation 0.3, seed 3), leaf 32, eps 1e-2, alpha 0.05, "
+                       f"FP32C base cases, two-sided statistic", "reference": ref_kind}
+    print("multitree: two-sided statistic, order 0", flush=True)
+    r = run(x, "two_sided", 0, idx, ref)
+    out.update(r)
+    print(f"multitree: {r['seconds']:.1f} s, {r['triples_per_s']:.3e} effective triples/s, within "
+          f"eps {r['within_eps']} (Wilson [{r['wilson95'][0]:.4f}, {r['wilson95'][1]:.4f}]), "
+          f"base cases {r['base_roofline']['base_triples_per_s']:.3e} triples/s", flush=True)
+    out["far_field_orders"] = {}
+    for order in (1, 2):
+        print(f"multitree: two-sided statistic, order {order}", flush=True)
+        ro = run(x, "two_sided", order, idx, ref)
+        out["far_field_orders"][str(order)] = {k_: ro[k_] for k_ in (
+            "seconds", "within_eps", "max_rel_err", "median_rel_err", "exhaustive_fraction")}
+        out["far_field_orders"][str(order)]["det_prunes"] = ro["stats"]["det_prunes"]
+        print(f"multitree: order {order}: {ro['seconds']:.1f} s, max rel err "
+              f"{ro['max_rel_err']:.2e}", flush=True)
+    out["far_field_orders"]["0"] = {"seconds": r["seconds"], "within_eps": r["within_eps"],
+                                    "max_rel_err": r["max_rel_err"],
+                                    "median_rel_err": r["median_rel_err"],
+                                    "exhaustive_fraction": r["exhaustive_fraction"],
+                                    "det_prunes": r["stats"]["det_prunes"]}
+    # the two statistics side by side on a 65536-point mixture
+    m = min(n, 65536)
+    xs_np = workloads.saturated_gaussian_mixture(m, seed=3)
+    xs = torch.from_numpy(xs_np).to(dev)
+    ref_s = mb.eval_direct(xs, prec="fp64").cpu().numpy()
+    ids = np.arange(m)
+    out["statistics_n65536"] = {}
+    for bound in ("two_sided", "signed"):
+        print(f"multitree: N={m}, {bound} statistic", flush=True)
+        rb = run(xs, bound, 0, ids, ref_s)
+        out["statistics_n65536"][bound] = {k_: rb[k_] for k_ in (
+            "seconds", "within_eps", "max_rel_err", "exhaustive_fraction")}
+        print(f"multitree: N={m} {bound}: {rb['seconds']:.2f} s, exhaustive fraction "
+              f"{rb['exhaustive_fraction']:.3f}", flush=True)
     return out
 
 
@@ -382,7 +473,7 @@ def paper_leg(dev) -> dict:
     and at N = 10000 the end-to-end time (tree build included) against the
     binary64 exhaustive GPU sum for eps = 0.1 with alpha = 0 and 0.1 (the
     settings of the paper's speedup statements).  Both bounds (the paper's
-    signed one and the magnitude one), binary64 base cases, leaf 32.
+    signed one and the two-sided one), binary64 base cases, leaf 32.
     """
     import numpy as np
     import torch
@@ -392,7 +483,7 @@ def paper_leg(dev) -> dict:
 
     gens = (("uniform", workloads.uniform_cube), ("ball", workloads.unit_ball),
             ("annulus", workloads.annulus))
-    bounds = ("signed", "magnitude")
+    bounds = ("signed", "two_sided")
 
     def timed(fn):
         torch.cuda.synchronize()

@@ -224,6 +224,10 @@ typedef struct {
     int64_t rounds;       /* rounds of the device stack                              */
     double build_ms;      /* tree build (0 if a tree was passed in)                  */
     double traverse_ms;   /* traversal incl. top-down pass                           */
+    double classify_ms;   /* device time classifying node triples (and far-field
+                             estimates of prunes)                                    */
+    double mc_ms;         /* device time of Monte Carlo tests                        */
+    double base_ms;       /* device time of base cases (sort, units, tiles)         */
 } mb_mt_stats;
 
 /*

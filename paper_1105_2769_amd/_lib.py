@@ -52,7 +52,9 @@ class MtStats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in
                 ("visited", "det_prunes", "mc_prunes", "mc_failed", "base_cases", "base_triples",
                  "mc_samples", "max_stack", "rounds")] + \
-               [("build_ms", ctypes.c_double), ("traverse_ms", ctypes.c_double)]
+               [("build_ms", ctypes.c_double), ("traverse_ms", ctypes.c_double),
+                ("classify_ms", ctypes.c_double), ("mc_ms", ctypes.c_double),
+                ("base_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

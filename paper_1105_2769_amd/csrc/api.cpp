@@ -308,6 +308,9 @@ mb_status mb_eval_multitree(const double *x, int64_t n, int32_t leaf_size,
         stats->rounds = ms.rounds;
         stats->build_ms = own ? own->build_ms : 0.0;
         stats->traverse_ms = ms.traverse_ms;
+        stats->classify_ms = ms.classify_ms;
+        stats->mc_ms = ms.mc_ms;
+        stats->base_ms = ms.base_ms;
     }
     if (own) tree_free(own);
     return st;

@@ -749,7 +749,8 @@ constexpr int kLeafKT = LeafLds<float, 4>::KT;  // K tile of a full unit
 static_assert(LeafLds<double, 4>::KT == kLeafKT && LeafLds<float, 2>::KT == kLeafKT / 2,
               "K tiles of full and short units");
 constexpr int kLeafTab = kLeafMax * kLeafMax * 3;  // (i, j) table entries per unit
-constexpr int kUnitBatch = 131072;  // units whose tables are held at once (1.5 GiB in binary32)
+constexpr int kUnitBatch = 131072;  // units whose tables are held at most (1.5 GiB in binary32)
+constexpr int kUnitStart = 8192;    // table capacity a traversal starts with
 
 // Ranks of a unit's slots, filled into LDS before the tile code runs.
 struct LeafIndex {
@@ -1257,12 +1258,15 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
     int width = 1;  // K-tile slots per leaf: the largest leaf
     for (int32_t v : leaves) width = std::max(width, t->h.end[v] - t->h.begin[v]);
     const int per_unit = kLeafKT / width;
-    const int ubatch = std::min(chunk, kUnitBatch);
+    // table capacity in units: starts small and grows to the largest round
+    // seen (up to kUnitBatch); units beyond it run in further batches
+    int ubatch = std::min(chunk, kUnitStart);
     Scratch s_keys, s_vals, s_ust, s_ucnt, s_hst, s_hcnt, s_tab, s_htab, s_stmp;
     unsigned long long *keys;
     int *vals, *u_start, *u_count, *h_start, *h_count;
     char *tab, *htab;
-    const size_t tab_bytes = (size_t)ubatch * kLeafTab * (base64 ? 8 : 4);
+    const size_t unit_tab_bytes = (size_t)kLeafTab * (base64 ? 8 : 4);
+    const size_t tab_bytes = (size_t)ubatch * unit_tab_bytes;
     if ((st = dalloc(s_keys, &keys, 2 * (size_t)chunk, s)) ||
         (st = dalloc(s_vals, &vals, 2 * (size_t)chunk, s)) ||
         (st = dalloc(s_ust, &u_start, chunk, s)) || (st = dalloc(s_ucnt, &u_count, chunk, s)) ||
@@ -1354,6 +1358,18 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
     };
 
     int64_t max_stack = 1, rounds = 0, visited = 0;
+    // device time of the phases of each round: classification (with the
+    // far-field estimates), Monte Carlo, base cases (sort, units, tiles)
+    struct Events {
+        hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+        ~Events() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } evs;
+    hipEvent_t *ev = evs.e;
+    for (int q = 0; q < 4; ++q) MB_HIP(hipEventCreate(&ev[q]));
+    double phase_ms[3] = {0.0, 0.0, 0.0};
     const bool trace = std::getenv("MB_TRACE") != nullptr;
     auto last_print = std::chrono::steady_clock::now();
     for (;;) {
@@ -1388,6 +1404,7 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
         const double limit = (prm.spread_unit > 0.0 && phase < 64) ? spread_limit(phase) : INFINITY;
         const int B = (int)std::min<int64_t>(top, chunk);
         Item *items = stack + (top - B);
+        MB_HIP(hipEventRecord(ev[0], s));
         reset_round_kernel<<<1, 1, 0, s>>>(ctr);
         classify_kernel<<<(B + 255) / 256, 256, 0, s>>>(items, B, nv, ns, node_acc, node_lo,
                                                        node_hi, node_cov, k, ctr, mc_list,
@@ -1395,10 +1412,12 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
                                                        defer_buf, defer_flag, far_list);
         if (k.order >= 1)
             far_kernel<<<std::min(B, 2048), 256, 0, s>>>(far_list, nv, t->xs, smom, k, ctr, fest);
+        MB_HIP(hipEventRecord(ev[1], s));
         if (k.use_mc)
             mc_kernel<<<std::min(B, 4096), kMcThreads, 0, s>>>(mc_list, nv, t->xs, ns, est, dev,
                                                                node_cov, k, ctr, base_list,
                                                                child_buf, child_flag);
+        MB_HIP(hipEventRecord(ev[2], s));
         // base cases: sort by (P1, P2), cut into units, tables, tiles
         leaf_keys_kernel<<<(B + 255) / 256, 256, 0, s>>>(base_list, B, nv, M, k, ctr, node_cov,
                                                         keys, vals);
@@ -1408,6 +1427,7 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
                                                          u_count, h_start, h_count);
         if ((st = leaf_batch(0)) != MB_OK) return st;
         MB_HIP(hipGetLastError());
+        MB_HIP(hipEventRecord(ev[3], s));
         // children of split triples, in order, onto the stack where the chunk was;
         // deferred far triples, in order, onto the far stack
         if ((st = grow(s_stack, stack, cap, top - B, top - B + 8 * (int64_t)B)) != MB_OK) return st;
@@ -1432,13 +1452,38 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
                                              st_pos, st_neg, st_mix);
         MB_HIP(hipGetLastError());
         MB_HIP(hipStreamSynchronize(s));
+        float ms[3];
+        for (int q = 0; q < 3; ++q) MB_HIP(hipEventElapsedTime(&ms[q], ev[q], ev[q + 1]));
+        phase_ms[0] += ms[0];
+        phase_ms[1] += ms[1];
+        phase_ms[2] += ms[2];
         // units beyond the first batch (their credits reach the statistics
         // one round later, which only delays prunes)
         const unsigned long long n_units_max = std::max(n_units[0], n_units[1]);
         if (n_units_max > (unsigned long long)ubatch) {
+            MB_HIP(hipEventRecord(ev[0], s));
             for (int u0 = ubatch; (unsigned long long)u0 < n_units_max; u0 += ubatch)
                 if ((st = leaf_batch(u0)) != MB_OK) return st;
+            MB_HIP(hipEventRecord(ev[1], s));
             MB_HIP(hipStreamSynchronize(s));
+            MB_HIP(hipEventElapsedTime(&ms[0], ev[0], ev[1]));
+            phase_ms[2] += ms[0];
+            // larger tables for the next rounds
+            if (ubatch < std::min(chunk, kUnitBatch)) {
+                int cap = ubatch;
+                while ((unsigned long long)cap < n_units_max && cap < kUnitBatch) cap *= 2;
+                cap = std::min({cap, chunk, kUnitBatch});
+                Scratch n1, n2;
+                char *t1, *t2;
+                if ((st = dalloc(n1, &t1, (size_t)cap * unit_tab_bytes, s)) ||
+                    (st = dalloc(n2, &t2, (size_t)cap * unit_tab_bytes, s)))
+                    return st;
+                std::swap(s_tab.ptr, n1.ptr);
+                std::swap(s_htab.ptr, n2.ptr);
+                tab = t1;
+                htab = t2;
+                ubatch = cap;
+            }
         }
         top = top - B + num[0];
         visited += B - (limit < INFINITY ? num[1] : 0);
@@ -1472,6 +1517,9 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
         stats->mc_samples = (int64_t)hc.mc_samples;
         stats->max_stack = max_stack;
         stats->rounds = rounds;
+        stats->classify_ms = phase_ms[0];
+        stats->mc_ms = phase_ms[1];
+        stats->base_ms = phase_ms[2];
         stats->traverse_ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }

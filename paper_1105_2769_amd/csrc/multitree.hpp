@@ -28,6 +28,7 @@ struct MtStats {
     int64_t visited = 0, det_prunes = 0, mc_prunes = 0, mc_failed = 0, base_cases = 0,
             base_triples = 0, mc_samples = 0, max_stack = 0, rounds = 0;
     double traverse_ms = 0.0;
+    double classify_ms = 0.0, mc_ms = 0.0, base_ms = 0.0;
 };
 
 // Whether tree t was built from the points x (N = n, same coordinates bit for
