@@ -102,6 +102,21 @@ mb_status mb_eval_direct_unchecked(const double *x, int64_t n, int32_t prec, dou
                                    void *stream);
 
 /*
+ * mb_eval_direct_unchecked for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same arguments, preconditions and result; it calls no
+ * hipMalloc, hipFree or allocating routine.  Its scratch - the unit offsets
+ * and the (i, j) pair-term table - lives in one library-owned device array
+ * of 24 MiB + 256 bytes per GPU, allocated when the library is loaded and
+ * held until the process ends, so N is limited to 1024
+ * (MB_ERR_UNSUPPORTED above).  Every call on a GPU uses that GPU's array:
+ * calls that overlap on one GPU (several streams or threads) race and give
+ * wrong results.  Only enqueues work on `stream`.
+ */
+mb_status mb_eval_direct_noalloc(const double *x, int64_t n, int32_t prec, double *phi,
+                                 void *stream);
+
+/*
  * The minimum squared pair distance of the point set and whether every
  * coordinate is finite (the validation step of every evaluation, exposed
  * for callers that pick a precision themselves).

@@ -89,6 +89,7 @@ SIGNATURES = {
                              ctypes.POINTER(_c_dbl), _c_vp]),
     "mb_eval_direct": (_c_i32, [_c_vp, _c_i64, _c_i32, _c_vp, _c_vp]),
     "mb_eval_direct_unchecked": (_c_i32, [_c_vp, _c_i64, _c_i32, _c_vp, _c_vp]),
+    "mb_eval_direct_noalloc": (_c_i32, [_c_vp, _c_i64, _c_i32, _c_vp, _c_vp]),
     "mb_build_kdtree": (_c_i32, [_c_vp, _c_i64, _c_i32, _c_vp, ctypes.POINTER(_c_vp)]),
     "mb_free_kdtree": (_c_i32, [_c_vp]),
     "mb_kdtree_info": (_c_i32, [_c_vp, ctypes.POINTER(_c_i64), ctypes.POINTER(_c_i32),

@@ -158,6 +158,17 @@ mb_status mb_eval_direct_unchecked(const double *x, int64_t n, int32_t prec, dou
     return direct_launch(x, n, prec, 1.0, phi, (hipStream_t)stream);
 }
 
+mb_status mb_eval_direct_noalloc(const double *x, int64_t n, int32_t prec, double *phi,
+                                 void *stream) {
+    clear_error();
+    if (n < 0) return fail(MB_ERR_INVALID, "n < 0");
+    if (n > 0 && (!x || !phi)) return fail(MB_ERR_INVALID, "null pointer");
+    if (prec != MB_FP64 && prec != MB_FP32C) return fail(MB_ERR_INVALID, "unknown precision");
+    if (n > kNoAllocMaxN) return fail(MB_ERR_UNSUPPORTED, "n above 1024 for mb_eval_direct_noalloc");
+    if (n == 0) return MB_OK;
+    return direct_launch_noalloc(x, n, prec, phi, (hipStream_t)stream);
+}
+
 mb_status mb_build_kdtree(const double *x, int64_t n, int32_t leaf_size, void *stream,
                           mb_tree *out) {
     clear_error();

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 namespace mb {
@@ -400,6 +401,46 @@ double key_to_double(unsigned long long k) {
     return d;
 }
 
+// Units of the exhaustive sum of N points with tile type T, and the bytes
+// of its (i, j) table over J blocks [0, nb).
+template <typename T>
+int64_t direct_units(int64_t n) {
+    constexpr int IB = DirectLds<T>::IB, KR = DirectLds<T>::KR, KT = DirectLds<T>::KT;
+    const int na = (int)((n + IB - 1) / IB), nb = (int)((n + kB - 1) / kB);
+    const int nt = (int)((n + KT - 1) / KT);
+    int64_t u = 0;
+    for (int b = 0; b < nb; ++b) u += (int64_t)units_a(b, IB, na) * (nt - b / KR);
+    return u;
+}
+
+template <typename T>
+constexpr size_t direct_table_bytes(int64_t n) {
+    return (size_t)((n + DirectLds<T>::IB - 1) / DirectLds<T>::IB) *
+           (size_t)((n + kB - 1) / kB) * DirectLds<T>::IB * kB * 3 * sizeof(T);
+}
+
+// The exhaustive sum with its unit offsets and (i, j) table in caller-given
+// device memory (`offsets`: nb + 1 int64, `table`: the whole table), one
+// stripe; phi must already be zero.
+template <typename T>
+mb_status direct_launch_into(const double *x, int64_t n, double scale, double *phi,
+                             int64_t *offsets, T *table, hipStream_t s) {
+    constexpr int IB = DirectLds<T>::IB, KR = DirectLds<T>::KR, KT = DirectLds<T>::KT;
+    const int na = (int)((n + IB - 1) / IB), nb = (int)((n + kB - 1) / kB);
+    const int nt = (int)((n + KT - 1) / KT);
+    unit_offsets_kernel<<<1, 1, 0, s>>>(nb, nt, KR, IB, na, offsets);
+    pair_table_kernel<T><<<dim3((unsigned)na, (unsigned)nb), 256, 0, s>>>(x, (int)n, na, 0, scale,
+                                                                          table);
+    const double s2 = scale * scale;
+    const double out_scale = s2 * s2 * s2 * s2 * scale;
+    const int64_t units = direct_units<T>(n);
+    direct_kernel<T><<<(unsigned)std::min<int64_t>(units, (int64_t)1 << 30), DirectLds<T>::TPB, 0,
+                       s>>>(x, (int)n, na, nb, nt, offsets, 0, units, 0, table, scale, out_scale,
+                            phi);
+    MB_HIP(hipGetLastError());
+    return MB_OK;
+}
+
 template <typename T>
 mb_status direct_launch_t(const double *x, int64_t n, double scale, double *phi, hipStream_t s) {
     constexpr int IB = DirectLds<T>::IB;
@@ -413,8 +454,6 @@ mb_status direct_launch_t(const double *x, int64_t n, double scale, double *phi,
     mb_status st;
     Scratch unit_tab;
     if ((st = unit_tab.alloc(sizeof(int64_t) * (nb + 1), s)) != MB_OK) return st;
-    unit_offsets_kernel<<<1, 1, 0, s>>>(nb, nt, KR, IB, na, unit_tab.as<int64_t>());
-    MB_HIP(hipGetLastError());
 
     // the (i, j) table is built for a stripe of J blocks at a time
     const size_t per_b = (size_t)na * IB * kB * 3 * sizeof(T);
@@ -422,7 +461,11 @@ mb_status direct_launch_t(const double *x, int64_t n, double scale, double *phi,
     stripe = std::min(stripe, nb);
     Scratch pair_tab;
     if ((st = pair_tab.alloc(per_b * stripe, s)) != MB_OK) return st;
+    if (stripe == nb)
+        return direct_launch_into<T>(x, n, scale, phi, unit_tab.as<int64_t>(), pair_tab.as<T>(), s);
 
+    unit_offsets_kernel<<<1, 1, 0, s>>>(nb, nt, KR, IB, na, unit_tab.as<int64_t>());
+    MB_HIP(hipGetLastError());
     const double s2 = scale * scale;
     const double out_scale = s2 * s2 * s2 * s2 * scale;  // scale^9, exact for a power of two
     for (int b0 = 0; b0 < nb; b0 += stripe) {
@@ -436,6 +479,36 @@ mb_status direct_launch_t(const double *x, int64_t n, double scale, double *phi,
                                                    out_scale, phi);
         MB_HIP(hipGetLastError());
     }
+    return MB_OK;
+}
+
+// Device memory of mb_eval_direct_noalloc: the unit offsets (first 256
+// bytes) and the (i, j) table of either tile type for N <= kNoAllocMaxN.
+// In host code `scratch` only names the array; its device address on the
+// current GPU comes from hipGetSymbolAddress (noalloc_scratch below).
+constexpr size_t kNoAllocOffsets = 256;
+constexpr size_t kNoAllocBytes =
+    kNoAllocOffsets + (direct_table_bytes<double>(kNoAllocMaxN) > direct_table_bytes<float>(kNoAllocMaxN)
+                           ? direct_table_bytes<double>(kNoAllocMaxN)
+                           : direct_table_bytes<float>(kNoAllocMaxN));
+static_assert(((kNoAllocMaxN + kB - 1) / kB + 1) * 8 <= kNoAllocOffsets, "offsets fit");
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// Address of `scratch` on the current device, looked up once per device.
+mb_status noalloc_scratch(unsigned char **out) {
+    static std::mutex mu;
+    static unsigned char *ptr[64] = {};
+    int dev = 0;
+    MB_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(MB_ERR_UNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> g(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        ptr[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = ptr[dev];
     return MB_OK;
 }
 
@@ -537,6 +610,21 @@ mb_status point_fp64_redo_all(const double *x, int64_t n, double *phi, hipStream
     mb_status st = zero_doubles(phi, n, s);
     if (st != MB_OK) return st;
     return direct_launch_t<double>(x, n, 1.0, phi, s);
+}
+
+mb_status direct_launch_noalloc(const double *x, int64_t n, int prec, double *phi, hipStream_t s) {
+    if (n > kNoAllocMaxN) return fail(MB_ERR_UNSUPPORTED, "n above the no-allocation maximum");
+    unsigned char *base = nullptr;
+    mb_status st = noalloc_scratch(&base);
+    if (st != MB_OK) return st;
+    if ((st = zero_doubles(phi, n, s)) != MB_OK) return st;
+    if (n < 3) return MB_OK;
+    int64_t *off = reinterpret_cast<int64_t *>(base);
+    if (prec == MB_FP64)
+        return direct_launch_into<double>(x, n, 1.0, phi, off,
+                                          reinterpret_cast<double *>(base + kNoAllocOffsets), s);
+    return direct_launch_into<float>(x, n, 1.0, phi, off,
+                                     reinterpret_cast<float *>(base + kNoAllocOffsets), s);
 }
 
 mb_status direct_launch(const double *x, int64_t n, int prec, double scale, double *phi,

@@ -93,6 +93,11 @@ size_t table_budget_bytes();
 mb_status direct_launch(const double *x, int64_t n, int prec, double scale, double *phi,
                         hipStream_t s, double r_fix = 0.0, int64_t *recomputed = nullptr);
 
+// The exhaustive sum as mb_eval_direct_unchecked, with its scratch in the
+// library's static device array (no allocation); n <= kNoAllocMaxN.
+constexpr int64_t kNoAllocMaxN = 1024;
+mb_status direct_launch_noalloc(const double *x, int64_t n, int prec, double *phi, hipStream_t s);
+
 // Near-field refinement of a binary32 tile sum already in (or going to)
 // phi: every triple with all sides < r_fix (input units), at most 64
 // forward neighbours per point, is moved from its binary32 tile value to
