@@ -110,6 +110,9 @@ def main() -> int:
                     help="points of the Gaussian-mixture traversal leg (0: skip); 262144 is "
                          "checked against stored oracle values, other sizes against the "
                          "binary64 GPU sum")
+    ap.add_argument("--no-multitree-extra", action="store_true",
+                    help="run only the quoted traversal (two-sided, order 0), not the far-field "
+                         "orders 1, 2 or the two statistics at N=65536")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (the "
                          "reference kernel for scaling HBM byte counters), then exit")
@@ -217,7 +220,8 @@ def main() -> int:
             results[prec]["frac_above_1e6"] = float(np.mean(r_all > 1e-6))
 
     latency = serve_leg(args.serve_requests, dev) if args.serve_requests else None
-    multitree = multitree_leg(args.multitree_n, dev) if args.multitree_n else None
+    multitree = multitree_leg(args.multitree_n, dev, not args.no_multitree_extra) \
+        if args.multitree_n else None
     factorized = None if args.no_factorized else factorized_leg(dev)
     paper = None if args.no_paper else paper_leg(dev)
 
@@ -365,7 +369,7 @@ def c3_golden():
     return np.array(idx), np.array(ref)
 
 
-def multitree_leg(n: int, dev) -> dict:
+def multitree_leg(n: int, dev, extra: bool = True) -> dict:
     """The triple-tree traversal on the Gaussian-mixture set (eps 1e-2, alpha 0.05).
 
     The run the leg is quoted on: two-sided statistic, monopole prunes
@@ -432,6 +436,8 @@ def multitree_leg(n: int, dev) -> dict:
     print(f"multitree: {r['seconds']:.1f} s, {r['triples_per_s']:.3e} effective triples/s, within "
           f"eps {r['within_eps']} (Wilson [{r['wilson95'][0]:.4f}, {r['wilson95'][1]:.4f}]), "
           f"base cases {r['base_roofline']['base_triples_per_s']:.3e} triples/s", flush=True)
+    if not extra:
+        return out
     out["far_field_orders"] = {}
     for order in (1, 2):
         print(f"multitree: two-sided statistic, order {order}", flush=True)

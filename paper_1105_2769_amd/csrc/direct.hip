@@ -23,7 +23,7 @@ __global__ __launch_bounds__(DirectLds<T>::TPB, DirectShape<T>::MINB) void direc
     for (int64_t u = u_begin + blockIdx.x; u < u_end; u += gridDim.x) {
         int a, b, t;
         decode_unit(u, unit_off, nb, nt, DirectLds<T>::KR, a, b, t);
-        direct_unit<T>(s, x, n, a, b, t, utab + ((int64_t)(b - b0) * na + a) * (IB * kB * 3),
+        direct_unit<T>(s, x, n, a, b, t, utab + ((int64_t)(b - b0) * na + a) * (IB * kB * kPairVals),
                        scale, out_scale, phi);
     }
 }
@@ -118,9 +118,9 @@ __global__ __launch_bounds__(256) void near_fix_kernel(const double *__restrict_
         pair_terms(xw[0] - xv[0], xw[1] - xv[1], xw[2] - xv[2], true, a3, q3, w3, i3);
         const double f64 = phi_from_pairs<double>(a1, q1, w1, a2, q2, w2, a3, q3, w3);
         const float cb = (float)a3;
-        const float psi = tile_psi<float>((float)a1, (float)q1, (float)w1, (float)a2, (float)q2,
-                                          (float)w2, cb, cb * cb, (float)(0.375 * i3));
-        const double f32 = (double)(float)q3 * (double)psi;
+        const float psi = tile_psi<float>((float)a1, (float)a2, (float)w2, cb, cb * cb,
+                                          (float)(0.375 * i3));
+        const double f32 = (double)(float)q3 * (double)(float)w1 * (double)psi;
         const double dlt = (f64 - f32) * out_scale;
         const double m = fabs(f64) * out_scale;
         acc_u += dlt;
@@ -416,7 +416,7 @@ int64_t direct_units(int64_t n) {
 template <typename T>
 constexpr size_t direct_table_bytes(int64_t n) {
     return (size_t)((n + DirectLds<T>::IB - 1) / DirectLds<T>::IB) *
-           (size_t)((n + kB - 1) / kB) * DirectLds<T>::IB * kB * 3 * sizeof(T);
+           (size_t)((n + kB - 1) / kB) * DirectLds<T>::IB * kB * kPairVals * sizeof(T);
 }
 
 // The exhaustive sum with its unit offsets and (i, j) table in caller-given
@@ -456,7 +456,7 @@ mb_status direct_launch_t(const double *x, int64_t n, double scale, double *phi,
     if ((st = unit_tab.alloc(sizeof(int64_t) * (nb + 1), s)) != MB_OK) return st;
 
     // the (i, j) table is built for a stripe of J blocks at a time
-    const size_t per_b = (size_t)na * IB * kB * 3 * sizeof(T);
+    const size_t per_b = (size_t)na * IB * kB * kPairVals * sizeof(T);
     int stripe = (int)std::max<size_t>(1, table_budget_bytes() / per_b);
     stripe = std::min(stripe, nb);
     Scratch pair_tab;

@@ -17,18 +17,20 @@
 //   * the (j, k) terms (one per lane) are staged in LDS per chunk of 16 j
 //     and also read one j ahead into registers.
 //
-// Inner step for one triple, with (a, qa, wa) the (i, j) terms, (g, qg, wg)
-// the (i, k) terms and (b, qb, ob = 3/8 / b) the (j, k) terms:
+// Inner step for one triple, with (a, wa) the (i, j) terms, (g, wg) the
+// (i, k) terms and (b, qb, ob = 3/8 / b) the (j, k) terms.  Since
+// q_x = x w_x, phi = qa qb qg + 3/8 wa wb wg P factors as
 //
-//   phi = qb * psi,   psi = qa qg + ob (wa wg) (a + g - b)(b^2 - (a - g)^2)
+//   phi = qb wa psi,   psi = wg (a g + ob (a + g - b)(b^2 - (a - g)^2))
 //
-// which is 11 VALU operations per triple including the sums
-// Phi_k += qb * sum_i psi (register), Phi_i += qb * psi (register array) and
-// Phi_j += sum over lanes, waves of sum_k qb * sum_i psi (one LDS atomic per
-// lane and j into a per-(j, lane) slot, reduced once per chunk).  The
-// register partials of Phi_i and Phi_k live in the tile type for one chunk
-// of 16 j and are folded into binary64 after it; unit sums go to Phi with
-// FP64 atomics.
+// (8 VALU operations), and the sums take the two remaining factors at once:
+// Phi_k += qb * sum_i wa psi (register), Phi_i += wa * sum_k qb psi
+// (register array, the wa product once per (i, j)) and Phi_j += sum over
+// lanes, waves of sum_k qb * sum_i wa psi (one LDS atomic per lane and j
+// into a per-(j, lane) slot, reduced once per chunk): about 10.3 operations
+// per triple.  The register partials of Phi_i and Phi_k live in the tile
+// type for one chunk of 16 j and are folded into binary64 after it; unit
+// sums go to Phi with FP64 atomics.
 #pragma once
 
 #include "at_device.hpp"
@@ -37,22 +39,23 @@ namespace mb {
 namespace {
 
 constexpr int kB = 64;              // points per J block
-constexpr int kJC = 16;             // j points per LDS chunk
+constexpr int kPairVals = 2;        // numbers per pair of the (i, j) table: a, w
 #ifndef MB_FOLD_J
 #define MB_FOLD_J 16                // j steps per binary32 partial of Phi_i
 #endif
 
 // Tile shape per arithmetic type: i points per wave, waves per workgroup,
-// k points per lane.
+// k points per lane, j points per LDS chunk; kLdsBB: b^2 of the (j, k)
+// terms is staged in LDS with them (else squared at every j step).
 template <typename T> struct DirectShape;
 #ifndef MB_IPW64
-#define MB_IPW64 4
+#define MB_IPW64 8
 #endif
 #ifndef MB_NW64
 #define MB_NW64 8
 #endif
 #ifndef MB_KR64
-#define MB_KR64 4
+#define MB_KR64 2
 #endif
 #ifndef MB_IPW32
 #define MB_IPW32 8
@@ -62,6 +65,18 @@ template <typename T> struct DirectShape;
 #endif
 #ifndef MB_KR32
 #define MB_KR32 4
+#endif
+#ifndef MB_JC64
+#define MB_JC64 16
+#endif
+#ifndef MB_JC32
+#define MB_JC32 16
+#endif
+#ifndef MB_BB64
+#define MB_BB64 1
+#endif
+#ifndef MB_BB32
+#define MB_BB32 1
 #endif
 #ifndef MB_MINB64
 #define MB_MINB64 1
@@ -73,14 +88,18 @@ template <> struct DirectShape<double> {
     static constexpr int IPW = MB_IPW64;
     static constexpr int NW = MB_NW64;
     static constexpr int KR = MB_KR64;
+    static constexpr int JC = MB_JC64;
     static constexpr bool kPair32 = false;  // (i, k) and (j, k) terms from pair_terms (binary64)
+    static constexpr bool kLdsBB = MB_BB64;
     static constexpr int MINB = MB_MINB64;  // workgroups per CU the registers must allow
 };
 template <> struct DirectShape<float> {
     static constexpr int IPW = MB_IPW32;
     static constexpr int NW = MB_NW32;
     static constexpr int KR = MB_KR32;
+    static constexpr int JC = MB_JC32;
     static constexpr bool kPair32 = false;
+    static constexpr bool kLdsBB = MB_BB32;
     static constexpr int MINB = MB_MINB32;
 };
 
@@ -88,7 +107,8 @@ template <> struct DirectShape<float> {
 // per lane (DirectShape<T> for the exhaustive sum); JB is the J block.
 template <typename T, int JB = kB, typename Shape = DirectShape<T>>
 struct DirectLds {
-    static_assert(JB % kJC == 0, "the J block is a whole number of chunks");
+    static constexpr int kJC = Shape::JC;
+    static_assert(JB % kJC == 0 && kJC % 2 == 0, "the J block is a whole number of chunks");
     static constexpr int TPB = Shape::NW * 64;  // threads per workgroup
     static constexpr int IB = Shape::NW * Shape::IPW;
     static constexpr int KR = Shape::KR;
@@ -96,6 +116,7 @@ struct DirectLds {
     static constexpr int XS = IB + JB + KT;
     double xs[3][XS];                              // coordinates of the I, J blocks and K tile
     T cb[kJC][KT], cq[kJC][KT], co[kJC][KT];       // (j, k) terms of the chunk
+    T cbb[Shape::kLdsBB ? kJC : 1][KT];            // their b^2 (kLdsBB)
     double pj[kJC][64];                            // Phi_j partials per (j, lane), all waves
     double pjacc[JB];                              // Phi_j of the unit
     double kacc[KT];                               // Phi_k of the unit
@@ -160,8 +181,19 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// One entry of an (i, j) table: a = |d|^2 and w = a^(-5/2) in binary64,
+// rounded to T; a masked pair gets a = 1, w = 0, so the triples through it
+// vanish.
+template <typename T>
+__device__ __forceinline__ void table_entry(double dx, double dy, double dz, bool valid, T *out) {
+    double pa, pq, pw, pia;
+    pair_terms(dx, dy, dz, valid, pa, pq, pw, pia);
+    out[0] = (T)pa;
+    out[1] = (T)pw;
+}
+
 // (i, j) pair-term table for J blocks b0 <= b < b0 + gridDim.y: block (a, b)
-// holds (a_ij, q_ij, w_ij) at [jl][il][3] for i = IB a + il, j = 64 b + jl,
+// holds (a_ij, w_ij) at [jl][il][kPairVals] for i = IB a + il, j = 64 b + jl,
 // masked unless i < j < n.
 template <typename T>
 __global__ __launch_bounds__(256) void pair_table_kernel(const double *__restrict__ x, int n,
@@ -180,38 +212,31 @@ __global__ __launch_bounds__(256) void pair_table_kernel(const double *__restric
         for (int c = 0; c < 3; ++c) xb[c][tid - IB] = j < n ? x[3 * (int64_t)j + c] * scale : 0.0;
     }
     __syncthreads();
-    T *out = tab + ((int64_t)blockIdx.y * na + a) * (IB * kB * 3);
+    T *out = tab + ((int64_t)blockIdx.y * na + a) * (IB * kB * kPairVals);
     for (int e = tid; e < IB * kB; e += 256) {
         const int jl = e / IB, il = e % IB;
         const int i = a * IB + il, j = b * kB + jl;
-        double pa, pq, pw, pia;
-        pair_terms(xb[0][jl] - xa[0][il], xb[1][jl] - xa[1][il], xb[2][jl] - xa[2][il],
-                   (i < j) && (j < n), pa, pq, pw, pia);
-        out[3 * e + 0] = (T)pa;
-        out[3 * e + 1] = (T)pq;
-        out[3 * e + 2] = (T)pw;
+        table_entry(xb[0][jl] - xa[0][il], xb[1][jl] - xa[1][il], xb[2][jl] - xa[2][il],
+                    (i < j) && (j < n), out + kPairVals * e);
     }
 }
 
-// psi of one triple as the tiles evaluate it (phi = q_jk psi), from the
-// (i, j) terms (a, qa, wa), the (i, k) terms (g, qg, wg) and the (j, k)
-// terms (b, bb = b * b, ob = 3/8 / b).  Written once so that the binary32
-// near-field refinement reproduces the tile value bit for bit.
+// psi of one triple as the tiles evaluate it (phi = q_jk w_ij psi), from
+// a = |x_j - x_i|^2, the (i, k) terms (g, wg) and the (j, k) terms
+// (b, bb = b * b, ob = 3/8 / b).  Written once so that the binary32
+// near-field refinement reproduces the tile's psi bit for bit.
 template <typename T>
-__device__ __forceinline__ T tile_psi(T a, T qa, T wa, T g, T qg, T wg, T b, T bb, T ob) {
+__device__ __forceinline__ T tile_psi(T a, T g, T wg, T b, T bb, T ob) {
     const T d = a - g;
     const T tt = (a + g) - b;
     const T m = fma(-d, d, bb);
-    const T X = qa * qg;
-    const T W = wa * wg;
     const T P = tt * m;
-    const T Y = W * P;
-    return fma(ob, Y, X);
+    return wg * fma(ob, P, a * g);
 }
 
 // One work unit of the triple sum: the I block, J block and K tile named by
 // the index policy `ix` (see BlockIndex); ublk is the unit's (i, j) table,
-// [jl][il][a, q, w] for the IB x JB pairs, read with scalar loads (a pointer
+// [jl][il][a, w] for the IB x JB pairs, read with scalar loads (a pointer
 // into the constant address space where the caller cannot otherwise show
 // the table is unchanged during the kernel).  x holds the coordinates the
 // ranks index; sums go to phi[rank] (times out_scale).  Every thread of the
@@ -226,11 +251,12 @@ __device__ __forceinline__ void tile_unit(DirectLds<T, JB, Shape> &s, const doub
     constexpr int kKR = DirectLds<T, JB, Shape>::KR;
     constexpr int kKT = DirectLds<T, JB, Shape>::KT;
     constexpr int XS = DirectLds<T, JB, Shape>::XS;
+    constexpr int kJC = Shape::JC;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     constexpr int XI = 0, XJ = IB, XK = IB + JB;
-    const TabPtr up = ublk + wave * (IPW * 3);
+    const TabPtr up = ublk + wave * (IPW * kPairVals);
 
     __syncthreads();  // the previous unit is done with the LDS
     for (int p = tid; p < XS; p += TPB) {
@@ -244,7 +270,7 @@ __device__ __forceinline__ void tile_unit(DirectLds<T, JB, Shape> &s, const doub
     __syncthreads();
 
     // (i, k) pair terms of this wave, in registers for the whole unit
-    T ag[IPW][kKR], aq[IPW][kKR], aw[IPW][kKR];
+    T ag[IPW][kKR], aw[IPW][kKR];
     T acc_i[IPW];
     double acc_i64[IPW];
 #pragma unroll
@@ -259,14 +285,12 @@ __device__ __forceinline__ void tile_unit(DirectLds<T, JB, Shape> &s, const doub
             const double dy = s.xs[1][XK + kl] - s.xs[1][XI + il];
             const double dz = s.xs[2][XK + kl] - s.xs[2][XI + il];
             if constexpr (Shape::kPair32) {
-                float pia;
-                pair_terms32(dx, dy, dz, (i >= 0) && (k > i), ag[ii][kk], aq[ii][kk], aw[ii][kk],
-                             pia);
+                float pq, pia;
+                pair_terms32(dx, dy, dz, (i >= 0) && (k > i), ag[ii][kk], pq, aw[ii][kk], pia);
             } else {
                 double pa, pq, pw, pia;
                 pair_terms(dx, dy, dz, (i >= 0) && (k > i), pa, pq, pw, pia);
                 ag[ii][kk] = (T)pa;
-                aq[ii][kk] = (T)pq;
                 aw[ii][kk] = (T)pw;
             }
         }
@@ -298,50 +322,62 @@ __device__ __forceinline__ void tile_unit(DirectLds<T, JB, Shape> &s, const doub
                 s.cb[jj][kl] = pa;
                 s.cq[jj][kl] = pq;
                 s.co[jj][kl] = 0.375f * pia;
+                if constexpr (Shape::kLdsBB) s.cbb[jj][kl] = pa * pa;
             } else {
                 double pa, pq, pw, pia;
                 pair_terms(dx, dy, dz, (j >= 0) && (k > j), pa, pq, pw, pia);
-                s.cb[jj][kl] = (T)pa;
+                const T b = (T)pa;
+                s.cb[jj][kl] = b;
                 s.cq[jj][kl] = (T)pq;
                 s.co[jj][kl] = (T)(0.375 * pia);
+                if constexpr (Shape::kLdsBB) s.cbb[jj][kl] = b * b;
             }
         }
         for (int e = tid; e < kJC * 64; e += TPB) s.pj[e / 64][e % 64] = 0.0;
         __syncthreads();
 
-        const TabPtr uc = up + (jc * kJC) * (IB * 3);
+        const TabPtr uc = up + (jc * kJC) * (IB * kPairVals);
         // Operands of one j step: the (i, j) terms of the wave's IPW points
-        // (uniform, SGPRs) and the (j, k) terms of the lane's four k.
+        // (uniform, SGPRs) and the (j, k) terms of the lane's KR k.
+        constexpr int KBB = Shape::kLdsBB ? kKR : 1;
         struct Ops {
-            T u[IPW * 3];
-            T cb[kKR], cq[kKR], co[kKR];
+            T u[IPW * kPairVals];
+            T cb[kKR], cq[kKR], co[kKR], bb[KBB];
         };
         auto load = [&](int jj, Ops &o) {
-            const TabPtr p = uc + jj * (IB * 3);
+            const TabPtr p = uc + jj * (IB * kPairVals);
 #pragma unroll
-            for (int e = 0; e < IPW * 3; ++e) o.u[e] = p[e];
+            for (int e = 0; e < IPW * kPairVals; ++e) o.u[e] = p[e];
 #pragma unroll
             for (int kk = 0; kk < kKR; ++kk) {
                 o.cb[kk] = s.cb[jj][lane + 64 * kk];
                 o.cq[kk] = s.cq[jj][lane + 64 * kk];
                 o.co[kk] = s.co[jj][lane + 64 * kk];
+                if constexpr (Shape::kLdsBB) o.bb[kk] = s.cbb[jj][lane + 64 * kk];
             }
         };
-        // One j step: 4 * IPW triples per lane.
+        // One j step: KR * IPW triples per lane.
         auto step = [&](int jj, const Ops &o) {
             T bb[kKR], sk[kKR];
 #pragma unroll
-            for (int kk = 0; kk < kKR; ++kk) bb[kk] = o.cb[kk] * o.cb[kk];
+            for (int kk = 0; kk < kKR; ++kk) {
+                if constexpr (Shape::kLdsBB)
+                    bb[kk] = o.bb[kk];
+                else
+                    bb[kk] = o.cb[kk] * o.cb[kk];
+            }
 #pragma unroll
             for (int ii = 0; ii < IPW; ++ii) {
-                const T al = o.u[3 * ii], qa = o.u[3 * ii + 1], wa = o.u[3 * ii + 2];
+                const T al = o.u[kPairVals * ii], wa = o.u[kPairVals * ii + 1];
+                T ti = T(0);
 #pragma unroll
                 for (int kk = 0; kk < kKR; ++kk) {
-                    const T psi = tile_psi(al, qa, wa, ag[ii][kk], aq[ii][kk], aw[ii][kk], o.cb[kk],
-                                           bb[kk], o.co[kk]);
-                    sk[kk] = ii ? sk[kk] + psi : psi;
-                    acc_i[ii] = fma(o.cq[kk], psi, acc_i[ii]);
+                    const T psi =
+                        tile_psi(al, ag[ii][kk], aw[ii][kk], o.cb[kk], bb[kk], o.co[kk]);
+                    sk[kk] = ii ? fma(wa, psi, sk[kk]) : wa * psi;
+                    ti = kk ? fma(o.cq[kk], psi, ti) : o.cq[kk] * psi;
                 }
+                acc_i[ii] = fma(wa, ti, acc_i[ii]);
             }
             T pj32 = T(0);
 #pragma unroll

@@ -734,12 +734,14 @@ constexpr int kLeafMax = 32;  // points per leaf at most (leaf_size <= 32)
 // pair terms are a sixth of the work, three times that in binary64.
 template <typename T, int KR_> struct LeafShape;
 template <int KR_> struct LeafShape<float, KR_> {
-    static constexpr int IPW = 8, NW = 4, KR = KR_;
+    static constexpr int IPW = 8, NW = 4, KR = KR_, JC = 16;
     static constexpr bool kPair32 = true;
+    static constexpr bool kLdsBB = false;  // two workgroups per CU fit the LDS without it
 };
 template <int KR_> struct LeafShape<double, KR_> {
-    static constexpr int IPW = 4, NW = 8, KR = KR_;
+    static constexpr int IPW = 4, NW = 8, KR = KR_, JC = 16;
     static constexpr bool kPair32 = false;
+    static constexpr bool kLdsBB = true;
 };
 template <typename T, int KR>
 using LeafLds = DirectLds<T, kLeafMax, LeafShape<T, KR>>;
@@ -748,8 +750,8 @@ static_assert(LeafLds<float, 4>::IB == kLeafMax && LeafLds<double, 4>::IB == kLe
 constexpr int kLeafKT = LeafLds<float, 4>::KT;  // K tile of a full unit
 static_assert(LeafLds<double, 4>::KT == kLeafKT && LeafLds<float, 2>::KT == kLeafKT / 2,
               "K tiles of full and short units");
-constexpr int kLeafTab = kLeafMax * kLeafMax * 3;  // (i, j) table entries per unit
-constexpr int kUnitBatch = 131072;  // units whose tables are held at most (1.5 GiB in binary32)
+constexpr int kLeafTab = kLeafMax * kLeafMax * kPairVals;  // (i, j) table numbers per unit
+constexpr int kUnitBatch = 131072;  // units whose tables are held at most (1 GiB in binary32)
 constexpr int kUnitStart = 8192;    // table capacity a traversal starts with
 
 // Ranks of a unit's slots, filled into LDS before the tile code runs.
@@ -829,7 +831,7 @@ __global__ void leaf_units_kernel(const unsigned long long *__restrict__ keys, i
     }
 }
 
-// (i, j) tables of the units [u0, u0 + batch) that exist: [jl][il][a, q, w]
+// (i, j) tables of the units [u0, u0 + batch) that exist: [jl][il][a, w]
 // for i in P1, j in P2, masked unless both exist and rank i < rank j (P1 = P2
 // in cases (a) and (b)); coordinates times `scale`.
 template <typename T>
@@ -858,12 +860,8 @@ __global__ __launch_bounds__(256) void leaf_table_kernel(
         T *out = tab + (int64_t)w * kLeafTab;
         for (int e = tid; e < kLeafMax * kLeafMax; e += 256) {
             const int jl = e / kLeafMax, il = e % kLeafMax;
-            double pa, pq, pw, pia;
-            pair_terms(xb[0][jl] - xa[0][il], xb[1][jl] - xa[1][il], xb[2][jl] - xa[2][il],
-                       il < n1 && jl < n2 && b1 + il < b2 + jl, pa, pq, pw, pia);
-            out[3 * e + 0] = (T)pa;
-            out[3 * e + 1] = (T)pq;
-            out[3 * e + 2] = (T)pw;
+            table_entry(xb[0][jl] - xa[0][il], xb[1][jl] - xa[1][il], xb[2][jl] - xa[2][il],
+                        il < n1 && jl < n2 && b1 + il < b2 + jl, out + kPairVals * e);
         }
     }
 }

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(DirectLds<T>::TPB, 1) void serve_kernel(const Serve
         const ServeDesc d = uniform_load(desc + it.slot);
         // the tables are written before the launch and only read by it
         using CT = __attribute__((address_space(4))) const T;
-        CT *blk = (CT *)static_cast<const T *>(d.tab) + ((int64_t)it.b * d.na + it.a) * (IB * kB * 3);
+        CT *blk = (CT *)static_cast<const T *>(d.tab) + ((int64_t)it.b * d.na + it.a) * (IB * kB * kPairVals);
         direct_unit<T, CT *>(s, d.x, d.n, it.a, it.b, it.t, blk, d.scale, d.out_scale, d.phi);
         if (wave == 0) atomicAdd(&counts[it.slot], lane == 0 ? 1u : 0u);
     }
@@ -134,8 +134,8 @@ struct UnitMap {
 };
 
 // The exhaustive sum's table shapes of the two tile types.
-const serve::TableShape kTab32{DirectLds<float>::IB, kB, 4};
-const serve::TableShape kTab64{DirectLds<double>::IB, kB, 8};
+const serve::TableShape kTab32{DirectLds<float>::IB, kB, 4, kPairVals};
+const serve::TableShape kTab64{DirectLds<double>::IB, kB, 8, kPairVals};
 
 // Device bytes a request holds while admitted: its whole chunk (points, Phi,
 // near-field magnitudes and a table region that fits either tile type).

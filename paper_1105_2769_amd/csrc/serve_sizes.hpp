@@ -17,9 +17,9 @@ namespace serve {
 inline int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 
 // Shape of the exhaustive sum's (i, j) table: I blocks of `ib` points, J
-// blocks of `jb`, `elem` bytes per number, three numbers per pair.
+// blocks of `jb`, `elem` bytes per number, `vals` numbers per pair.
 struct TableShape {
-    int64_t ib, jb, elem;
+    int64_t ib, jb, elem, vals;
 };
 
 // I blocks that J block b needs: those holding an i < 64 b + 63, the last j
@@ -30,10 +30,10 @@ inline int64_t table_blocks_a(int64_t b, int64_t ib, int64_t jb, int64_t na) {
 
 // Bytes the table kernel writes for N points, from its launch: block (a, b)
 // with a < table_blocks_a(b) fills [(b na + a) S, (b na + a + 1) S) with
-// S = ib jb 3 elem bytes.  The largest end over all blocks it writes.
+// S = ib jb vals elem bytes.  The largest end over all blocks it writes.
 inline int64_t table_extent(int64_t n, const TableShape &t) {
     const int64_t na = (n + t.ib - 1) / t.ib, nb = (n + t.jb - 1) / t.jb;
-    const int64_t blk = t.ib * t.jb * 3 * t.elem;
+    const int64_t blk = t.ib * t.jb * t.vals * t.elem;
     int64_t end = 0;
     for (int64_t b = 0; b < nb; ++b) {
         const int64_t ka = table_blocks_a(b, t.ib, t.jb, na);
@@ -45,7 +45,7 @@ inline int64_t table_extent(int64_t n, const TableShape &t) {
 // Bytes reserved for the table: the whole na x nb block grid.
 inline int64_t table_region(int64_t n, const TableShape &t) {
     const int64_t na = (n + t.ib - 1) / t.ib, nb = (n + t.jb - 1) / t.jb;
-    return na * nb * t.ib * t.jb * 3 * t.elem;
+    return na * nb * t.ib * t.jb * t.vals * t.elem;
 }
 
 // Offsets of the parts of a chunk and its total size; the table region

@@ -17,9 +17,10 @@ int main() {
     const int64_t ib32[] = {16, 32, 48, 64, 96, 128, 192};
     const int64_t ib64[] = {16, 32, 48, 64, 96};
     long checked = 0;
+    for (int64_t v : {2, 3})  // numbers per pair: (a, w), or (a, q, w)
     for (int64_t a : ib32)
         for (int64_t b : ib64) {
-            const TableShape t32{a, 64, 4}, t64{b, 64, 8};
+            const TableShape t32{a, 64, 4, v}, t64{b, 64, 8, v};
             for (int64_t n = 3; n <= 4096; ++n) {
                 const ChunkLayout c = chunk_layout(n, t32, t64);
                 // the launch's own grid (what the kernel indexes)

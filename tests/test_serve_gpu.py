@@ -21,6 +21,16 @@ def server(**kw):
     return mb.Server(**kw)
 
 
+def chunk_bytes(n):
+    """Device bytes of one request's chunk: 24 N (points) + 8 N (Phi) + 8 N
+    (near-field magnitudes) + the larger (i, j) table of the two tile types,
+    each part rounded up to 256.  The binary64 table is the larger one: I and
+    J blocks of 64 points, (a, w) per pair in 8 bytes each."""
+    up = lambda b: (b + 255) // 256 * 256
+    blocks = -(-n // 64)
+    return up(24 * n) + 2 * up(8 * n) + up(blocks * blocks * 64 * 64 * 2 * 8)
+
+
 def one_shot(x, prec, cuda):
     import torch
 
@@ -118,9 +128,7 @@ def test_budget_admission(cuda):
     import paper_1105_2769_amd as mb
 
     n = 600
-    # 24 N (points) + 8 N (Phi) + 8 N (near-field magnitudes) + a binary64
-    # table of ceil(N/32) ceil(N/64) 32*64*3*8 bytes, each part rounded up to 256
-    need = 14592 + 2 * 4864 + (19 * 10 * 32 * 64 * 3 * 8)
+    need = chunk_bytes(n)
     with server(hbm_budget_bytes=need - 1) as srv:
         with pytest.raises(mb.MBError) as e:
             srv.submit(workloads.jittered_lattice(n, seed=1))
@@ -144,7 +152,7 @@ def test_budget_counts_whole_chunks(cuda):
     import paper_1105_2769_amd as mb
 
     n = 600
-    need = 14592 + 2 * 4864 + (19 * 10 * 32 * 64 * 3 * 8)
+    need = chunk_bytes(n)
     budget = need + need // 2
     pts = [workloads.jittered_lattice(n, seed=40 + r) for r in range(4)]
     with server(hbm_budget_bytes=budget, max_slots=8) as srv:
