@@ -181,18 +181,27 @@ def canonical_children(tree: KdTree, p: tuple[int, int, int]) -> list[tuple[int,
 
 
 def mc_draw(seed: int, p: tuple[int, int, int], x_rank: int, s: np.ndarray) -> np.ndarray:
-    """64-bit uniform integers for samples s of point x in node triple p."""
+    """64-bit uniform integers for samples s of point x in node triple p.
+
+    One Philox block (four 32-bit words) serves two consecutive samples:
+    sample s uses counter (x, s // 2, p1, p2), key (p3, seed), and words
+    (0, 1) for even s, (2, 3) for odd s.
+    """
+    s = s.astype(np.uint64)
     m = s.shape[0]
     ctr = np.zeros((m, 4), dtype=np.uint64)
     ctr[:, 0] = x_rank
-    ctr[:, 1] = s
+    ctr[:, 1] = s >> np.uint64(1)
     ctr[:, 2] = p[0]
     ctr[:, 3] = p[1]
     key = np.zeros((m, 2), dtype=np.uint64)
     key[:, 0] = p[2]
     key[:, 1] = (seed ^ (seed >> 32)) & 0xFFFFFFFF
     w = philox4x32_10_np(ctr, key).astype(np.uint64)
-    return (w[:, 1] << np.uint64(32)) | w[:, 0]
+    odd = (s & np.uint64(1)).astype(bool)
+    lo = np.where(odd, w[:, 2], w[:, 0])
+    hi = np.where(odd, w[:, 3], w[:, 1])
+    return (hi << np.uint64(32)) | lo
 
 
 def uniform_index(r: np.ndarray, m: int) -> np.ndarray:

@@ -186,11 +186,22 @@ __device__ __forceinline__ void at_bounds(double l12, double l13, double l23, do
 // the largest of min LB + t lo, min(-UB) - t hi and
 // min max(LB, -UB) + min(t lo, -t hi), each a lower bound on the new
 // max(LB, -UB) of every point; with all LB > 0 the first is the paper's.
+// One node's statistics, read once.
+struct NodeAllow {
+    double pos, neg, mix;
+};
+__device__ __forceinline__ NodeAllow node_allow(const NodeStats &ns, int v) {
+    return NodeAllow{ns.pos[v], ns.neg[v], ns.mix[v]};
+}
+__device__ __forceinline__ double certified(const MtConst &k, const NodeAllow &na, double t,
+                                            double lo, double hi) {
+    const double sg = na.pos + t * lo;
+    if (!k.two_sided) return sg;
+    return fmax(fmax(sg, na.neg - t * hi), na.mix + fmin(t * lo, -t * hi));
+}
 __device__ __forceinline__ double certified(const MtConst &k, const NodeStats &ns, int v, double t,
                                             double lo, double hi) {
-    const double sg = ns.pos[v] + t * lo;
-    if (!k.two_sided) return sg;
-    return fmax(fmax(sg, ns.neg[v] - t * hi), ns.mix[v] + fmin(t * lo, -t * hi));
+    return certified(k, node_allow(ns, v), t, lo, hi);
 }
 
 // phi of three points from binary64 coordinates (law-of-cosines form).
@@ -459,54 +470,82 @@ __device__ __forceinline__ void pair_from_index(uint64_t t, int64_t &u, int64_t 
     u = (int64_t)t - vv * (vv - 1) / 2;
 }
 
-// The two partners of point x (offset xl inside the node at slot `slot`) for
-// one uniform 64-bit integer r: offsets inside their nodes and their slots.
-__device__ __forceinline__ void sample_partners(char cs, int slot, int64_t xl, int64_t n1,
-                                                int64_t n2, int64_t n3, uint64_t r, int64_t &u,
-                                                int64_t &v, int &su, int &sv) {
-    if (cs == 'a') {
-        pair_from_index(__umul64hi(r, (uint64_t)comb2(n1 - 1)), u, v);
-        u += u >= xl;
-        v += v >= xl;
-        su = sv = 0;
-    } else if (cs == 'b') {
-        if (slot == 0) {
-            const uint64_t t = __umul64hi(r, (uint64_t)((n1 - 1) * n3));
-            u = (int64_t)(t / (uint64_t)n3);
-            v = (int64_t)(t % (uint64_t)n3);
-            u += u >= xl;
-            su = 0;
-            sv = 2;
-        } else {
-            pair_from_index(__umul64hi(r, (uint64_t)comb2(n1)), u, v);
-            su = sv = 0;
-        }
-    } else if (cs == 'c') {
-        if (slot == 0) {
-            pair_from_index(__umul64hi(r, (uint64_t)comb2(n2)), u, v);
-            su = sv = 1;
-        } else {
-            const uint64_t t = __umul64hi(r, (uint64_t)(n1 * (n2 - 1)));
-            u = (int64_t)(t / (uint64_t)(n2 - 1));
-            v = (int64_t)(t % (uint64_t)(n2 - 1));
-            v += v >= xl;
-            su = 0;
-            sv = 1;
-        }
-    } else {
-        const int o0 = slot == 0 ? 1 : 0;
-        const int o1 = slot == 2 ? 1 : 2;
-        const int64_t na = o0 == 0 ? n1 : n2;
-        const int64_t nb = o1 == 1 ? n2 : n3;
-        const uint64_t t = __umul64hi(r, (uint64_t)(na * nb));
-        u = (int64_t)(t / (uint64_t)nb);
-        v = (int64_t)(t % (uint64_t)nb);
-        su = o0;
-        sv = o1;
+// How one uniform 64-bit integer r picks the two partners of a point x
+// (offset xl inside its node, at slot `slot` of the node triple): the
+// T_i partner tuples are numbered 0..range-1, t = floor(r range / 2^64), and
+// t is decoded either as an unordered pair of one node (pair_from_index) or
+// as (t / div, t mod div) over two nodes, skipping x itself where a partner
+// comes from x's own node.  Set up once per point.
+struct PartnerMap {
+    uint64_t range;
+    double inv;       // 1 / div
+    int32_t div;      // product decode: second partner's range
+    int32_t skip_u, skip_v;  // a partner offset >= skip is moved up by one
+    int32_t pair;     // 1: unordered pair of one node
+    int32_t su, sv;   // slots of the partners' nodes
+};
+
+__device__ __forceinline__ PartnerMap partner_map(char cs, int slot, int64_t xl, int64_t n1,
+                                                  int64_t n2, int64_t n3) {
+    constexpr int32_t kNone = INT32_MAX;
+    PartnerMap m;
+    m.div = 1;
+    m.skip_u = m.skip_v = kNone;
+    if (cs == 'a') {  // a pair of A minus x
+        m.pair = 1; m.range = (uint64_t)comb2(n1 - 1); m.su = m.sv = 0;
+        m.skip_u = m.skip_v = (int32_t)xl;
+    } else if (cs == 'b' && slot == 0) {  // x in A: one partner in A minus x, one in B
+        m.pair = 0; m.range = (uint64_t)((n1 - 1) * n3); m.div = (int32_t)n3; m.su = 0; m.sv = 2;
+        m.skip_u = (int32_t)xl;
+    } else if (cs == 'b') {  // x in B: a pair of A
+        m.pair = 1; m.range = (uint64_t)comb2(n1); m.su = m.sv = 0;
+    } else if (cs == 'c' && slot == 0) {  // x in A: a pair of B
+        m.pair = 1; m.range = (uint64_t)comb2(n2); m.su = m.sv = 1;
+    } else if (cs == 'c') {  // x in B: one partner in A, one in B minus x
+        m.pair = 0; m.range = (uint64_t)(n1 * (n2 - 1)); m.div = (int32_t)(n2 - 1); m.su = 0;
+        m.sv = 1;
+        m.skip_v = (int32_t)xl;
+    } else {  // three distinct nodes: one partner in each of the other two
+        m.su = slot == 0 ? 1 : 0;
+        m.sv = slot == 2 ? 1 : 2;
+        const int64_t na = m.su == 0 ? n1 : n2, nb = m.sv == 1 ? n2 : n3;
+        m.pair = 0; m.range = (uint64_t)(na * nb); m.div = (int32_t)nb;
     }
+    m.inv = 1.0 / (double)m.div;
+    return m;
+}
+
+// Partner offsets (u, v) inside their nodes for one uniform integer r.  The
+// quotient t / div comes from binary64 (t < 2^53, so the estimate is off by
+// at most one) and is corrected exactly.
+__device__ __forceinline__ void partners(const PartnerMap &m, uint64_t r, int64_t &u, int64_t &v) {
+    const uint64_t t = __umul64hi(r, m.range);
+    if (m.pair) {
+        pair_from_index(t, u, v);
+    } else {
+        int64_t q = (int64_t)((double)t * m.inv);
+        int64_t rem = (int64_t)t - q * m.div;
+        if (rem < 0) {
+            --q;
+            rem += m.div;
+        } else if (rem >= m.div) {
+            ++q;
+            rem -= m.div;
+        }
+        u = q;
+        v = rem;
+    }
+    u += u >= m.skip_u;
+    v += v >= m.skip_v;
 }
 
 constexpr int kMcThreads = 256;
+#ifndef MB_MC_ABORT
+#define MB_MC_ABORT 0
+#endif
+#ifndef MB_MC_WAVES
+#define MB_MC_WAVES 4  // waves per SIMD the sampler's registers must allow
+#endif
 constexpr int kMcCache = 2048;  // points whose (mu, lower bound) stay in LDS between passes
 
 struct McPoint {
@@ -515,88 +554,217 @@ struct McPoint {
     int drawn;
 };
 
-// Inclusive prefix sum over each aligned group of W lanes (gl: lane in group).
-template <int W>
-__device__ __forceinline__ double group_incl_scan(double v, int gl) {
-#pragma unroll
-    for (int d = 1; d < W; d <<= 1) {
-        const double u = __shfl_up(v, d, W);
-        if (gl >= d) v += u;
-    }
+// v from lane l - D of the same row of 16 lanes (DPP row_shr:D); the first
+// D lanes of a row receive 0.
+template <int D>
+__device__ __forceinline__ double row_shr(double v) {
+    static_assert(D >= 1 && D <= 15, "row shift");
+    const unsigned long long b = __double_as_longlong(v);
+    // bound_ctrl: a lane whose source lies before its row reads 0
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, 0x110 + D, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), 0x110 + D, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                            (unsigned)lo));
+}
+
+// Inclusive prefix sum over each row of 16 lanes.
+__device__ __forceinline__ double row16_incl_scan(double v) {
+    v += row_shr<1>(v);
+    v += row_shr<2>(v);
+    v += row_shr<4>(v);
+    v += row_shr<8>(v);
     return v;
 }
 
-// Algorithm 4 for one point, by a group of kMcGroup lanes of a wave (two
-// points per wave): samples are drawn kMcGroup at a time (sample s by lane
-// s mod kMcGroup of the group); prefix sums give the running mean and
-// unbiased variance after every sample, and the first sample count m at
-// which the sequential loop would stop - the termination rule holding with
-// m >= m_min, or m = m_limit - is found with a ballot.  The decision depends
-// only on the sample sequence, not on the group width; the width sets how
-// many samples past the stop are drawn (a point that stops at m_min = 30
-// draws 32).  Every lane of the group returns the same result.  `failed`
-// (nullable) aborts between batches.  gl: lane in the group, g0: the
-// group's first lane in the wave.
-constexpr int kMcGroup = 32;
-__device__ McPoint mc_point_group(const Item &it, char cs, int slot, int64_t off, int64_t xr,
-                                  int64_t n1, int64_t n2, int64_t n3, const int *pn,
-                                  const NodeView &nv, const double *__restrict__ xs, double t,
+// phi of the triangle (x, a, b) from binary64 coordinates, evaluated in
+// binary32 after an exact power-of-two rescaling: the squared sides are
+// formed in binary64 and divided by 4^e so that the longest lies in [1, 4)
+// (the triangle inequality keeps a second side >= 1/4 of it), and since phi
+// is homogeneous of degree -9/2 in the squared sides the binary32 value is
+// multiplied back by 2^(-9 e).  Monte Carlo samples only: their relative
+// error (about 1e-6 away from collinear triangles) is far below the
+// statistical error they are averaged into.
+__device__ __forceinline__ double phi_sample(double x0, double x1, double x2, const double *a,
+                                             const double *b) {
+    const double dx = a[0] - x0, dy = a[1] - x1, dz = a[2] - x2;
+    const double ex = b[0] - x0, ey = b[1] - x1, ez = b[2] - x2;
+    const double fx = b[0] - a[0], fy = b[1] - a[1], fz = b[2] - a[2];
+    const double s_ab = fma(dx, dx, fma(dy, dy, dz * dz));
+    const double s_ac = fma(ex, ex, fma(ey, ey, ez * ez));
+    const double s_bc = fma(fx, fx, fma(fy, fy, fz * fz));
+    const double mx = fmax(s_ab, fmax(s_ac, s_bc));
+    const int e = (__builtin_amdgcn_frexp_exp(mx) - 1) >> 1;  // 4^e <= mx < 4^(e+1)
+    const float A = (float)__builtin_amdgcn_ldexp(s_ab, -2 * e);
+    const float B = (float)__builtin_amdgcn_ldexp(s_ac, -2 * e);
+    const float C = (float)__builtin_amdgcn_ldexp(s_bc, -2 * e);
+    auto terms = [](float v, float &q, float &w) {
+        const float r = __builtin_amdgcn_rsqf(v);
+        const float iv = r * r;
+        q = r * iv;
+        w = q * iv;
+    };
+    float qa, wa, qb, wb, qc, wc;
+    terms(A, qa, wa);
+    terms(B, qb, wb);
+    terms(C, qc, wc);
+    const float f = phi_from_pairs<float>(A, qa, wa, B, qb, wb, C, qc, wc);
+    return __builtin_amdgcn_ldexp((double)f, -9 * e);
+}
+
+// Algorithm 4 for one point, by a group of kMcGroup lanes of a wave (four
+// points per wave): samples are drawn kMcBatch at a time, lane l of the group
+// taking samples 2l and 2l + 1 of the batch from the two halves of one
+// Philox block (sample s uses counter s / 2, half s mod 2); prefix sums give
+// the running mean and unbiased variance after every sample, and the first
+// sample count m at which the sequential loop would stop - the termination
+// rule holding with m >= m_min, or m = m_limit - is found with a ballot.
+// The decision depends only on the sample sequence, not on the group width;
+// the width sets how many samples past the stop are drawn (a point that
+// stops at m_min = 30 draws 32).  Every lane of the group returns the same
+// result.  `failed` (nullable) aborts between batches.  gl: lane in the
+// group, g0: the group's first lane in the wave.
+constexpr int kMcGroup = 16;  // one DPP row
+constexpr int kMcBatch = 2 * kMcGroup;
+
+// Running statistics after sample count m (m >= 1) from the shifted sums
+// t1 = sum (f - f0), t2 = sum (f - f0)^2.
+struct McStat {
+    bool ok, stop;
+    double mean, sig;
+    double need;  // samples the rule would need at this sigma: m (z sigma_mu / allowance)^2
+};
+__device__ __forceinline__ McStat mc_stat(double f0, double t1, double t2, int m, double t,
+                                          const NodeAllow &na, const MtConst &k) {
+    const double dm = (double)m;
+    double im = __builtin_amdgcn_rcp(dm);  // 1/m: hardware estimate, one Newton step
+    im = fma(fma(-dm, im, 1.0), im, im);
+    double im1 = __builtin_amdgcn_rcp(dm - 1.0);
+    im1 = fma(fma(-(dm - 1.0), im1, 1.0), im1, im1);
+    McStat r;
+    r.mean = fma(t1, im, f0);
+    const double var = m >= 2 ? fmax(fma(-t1 * t1, im, t2), 0.0) * im1 : 0.0;
+    r.sig = sqrt(var * im);
+    const double credit = certified(k, na, t, r.mean - k.z * r.sig, r.mean + k.z * r.sig);
+    const double lim = (k.eps * credit + k.tau) / k.t_root;
+    const bool cond = m >= 2 && k.z * r.sig <= lim;
+    const double ratio = k.z * r.sig / lim;
+    r.need = lim > 0.0 ? dm * ratio * ratio : INFINITY;
+    r.ok = cond && m >= k.m_min;
+    r.stop = r.ok || m == k.m_limit;
+    return r;
+}
+
+// Algorithm 4 for one point in progress, held by a group: the point, its
+// partner map and node statistics, and the sums over the batches so far.
+struct McRun {
+    PartnerMap pm;
+    NodeAllow na;
+    int32_t xr, bu, bv;
+    double x0, x1, x2, t;
+    double f0, s1, s2;
+    int base;
+};
+
+__device__ __forceinline__ void mc_begin(McRun &r, const PartnerMap &pm, int64_t xr,
+                                         const int64_t nb[3], const double *__restrict__ xs,
+                                         double t, const NodeStats &ns, int node) {
+    r.pm = pm;
+    r.na = node_allow(ns, node);
+    r.xr = (int32_t)xr;
+    r.bu = pm.su == 0 ? nb[0] : (pm.su == 1 ? nb[1] : nb[2]);
+    r.bv = pm.sv == 0 ? nb[0] : (pm.sv == 1 ? nb[1] : nb[2]);
+    r.x0 = xs[3 * xr];
+    r.x1 = xs[3 * xr + 1];
+    r.x2 = xs[3 * xr + 2];
+    r.t = t;
+    r.f0 = r.s1 = r.s2 = 0.0;
+    r.base = 0;
+}
+
+// One batch of kMcBatch samples of the point in r.  Returns true when the
+// test of the point has ended, with its result in res.
+__device__ __forceinline__ bool mc_batch(McRun &r, const Item &it, const double *__restrict__ xs,
+                                         const MtConst &k, int gl, int g0, McPoint &res) {
+    constexpr int W = kMcGroup;
+    const int base = r.base;
+    const int sa = base + 2 * gl;  // this lane's samples sa, sa + 1
+    const bool va = sa < k.m_limit, vb = sa + 1 < k.m_limit;
+    double fa = 0.0, fb = 0.0;
+    if (va) {
+        uint32_t c[4] = {(uint32_t)r.xr, (uint32_t)(sa >> 1), (uint32_t)it.p1, (uint32_t)it.p2};
+        philox4x32_10(c, (uint32_t)it.p3, k.seed32);
+        // both samples' partners first, so that their four point loads are
+        // in flight together (the second tuple is a valid one even when
+        // sample sa + 1 lies past m_limit; its value is then unused)
+        int64_t ua, wa, ub, wb;
+        partners(r.pm, ((uint64_t)c[1] << 32) | c[0], ua, wa);
+        partners(r.pm, ((uint64_t)c[3] << 32) | c[2], ub, wb);
+        const double *pa = xs + 3 * (r.bu + ua), *qa = xs + 3 * (r.bv + wa);
+        const double *pb = xs + 3 * (r.bu + ub), *qb = xs + 3 * (r.bv + wb);
+        const double a0[3] = {pa[0], pa[1], pa[2]}, a1[3] = {qa[0], qa[1], qa[2]};
+        const double b0[3] = {pb[0], pb[1], pb[2]}, b1[3] = {qb[0], qb[1], qb[2]};
+        fa = phi_sample(r.x0, r.x1, r.x2, a0, a1);
+        const double fb_ = phi_sample(r.x0, r.x1, r.x2, b0, b1);
+        fb = vb ? fb_ : 0.0;
+    }
+    if (base == 0) r.f0 = __shfl(fa, g0);  // shift for numerically stable sums
+    const double ga = va ? fa - r.f0 : 0.0, gb = vb ? fb - r.f0 : 0.0;
+    const double p1 = row16_incl_scan(ga + gb);
+    const double p2 = row16_incl_scan(fma(ga, ga, gb * gb));
+    const McStat A = mc_stat(r.f0, r.s1 + (p1 - gb), r.s2 + fma(-gb, gb, p2), sa + 1, r.t, r.na, k);
+    const McStat B = mc_stat(r.f0, r.s1 + p1, r.s2 + p2, sa + 2, r.t, r.na, k);
+    const bool stop_a = va && A.stop, stop_b = vb && B.stop;
+    // this group's bits of the wave's ballot
+    const unsigned long long bal = (__ballot(stop_a || stop_b) >> g0) & ((1ull << W) - 1ull);
+    const int drawn = min(base + kMcBatch, k.m_limit);
+    if (bal) {
+        const int L = g0 + __ffsll((long long)bal) - 1;
+        const McStat &S = stop_a ? A : B;
+        res.pass = __shfl((int)S.ok, L) != 0;
+        res.mean = __shfl(S.mean, L);
+        res.sig = __shfl(S.sig, L);
+        res.drawn = drawn;
+        return true;
+    }
+    bool give_up = drawn >= k.m_limit;
+#if MB_MC_ABORT > 0
+    // A point whose sample variance, after at least m_min samples, asks for
+    // more than MB_MC_ABORT * m_limit samples is taken to fail now rather
+    // than at m_limit: failing only sends the triple on to its children, so
+    // the estimate's guarantee is unchanged.
+    give_up = give_up || (drawn >= k.m_min &&
+                          __shfl(B.need, g0 + W - 1) > (double)MB_MC_ABORT * (double)k.m_limit);
+#endif
+    if (give_up) {
+        res.pass = false;
+        res.mean = res.sig = 0.0;
+        res.drawn = drawn;
+        return true;
+    }
+    r.s1 += __shfl(p1, g0 + W - 1);
+    r.s2 += __shfl(p2, g0 + W - 1);
+    r.base = base + kMcBatch;
+    return false;
+}
+
+// Algorithm 4 for one point from start to end; `failed` (nullable) is
+// checked between batches and ends the test as a failure once set.
+__device__ McPoint mc_point_group(const Item &it, const PartnerMap &pm, int64_t xr,
+                                  const int64_t nb[3], const double *__restrict__ xs, double t,
                                   const NodeStats &ns, int node, const MtConst &k,
                                   const volatile int *failed, int gl, int g0) {
-    constexpr int W = kMcGroup;
-    const double *xp = xs + 3 * xr;
-    double f0 = 0.0, s1 = 0.0, s2 = 0.0;
-    int drawn = 0;
-    // first points of the three nodes, in registers for the whole point
-    const int64_t nb0 = nv.begin[pn[0]], nb1 = nv.begin[pn[1]], nb2 = nv.begin[pn[2]];
-    for (int base = 0; base < k.m_limit; base += W) {
-        if (failed && *failed) break;
-        const int sidx = base + gl;
-        const bool valid = sidx < k.m_limit;
-        double f = 0.0;
-        if (valid) {
-            uint32_t c[4] = {(uint32_t)xr, (uint32_t)sidx, (uint32_t)it.p1, (uint32_t)it.p2};
-            philox4x32_10(c, (uint32_t)it.p3, k.seed32);
-            const uint64_t rr = ((uint64_t)c[1] << 32) | c[0];
-            int64_t u, v;
-            int su, sv;
-            sample_partners(cs, slot, off, n1, n2, n3, rr, u, v, su, sv);
-            const int64_t bu = su == 0 ? nb0 : (su == 1 ? nb1 : nb2);
-            const int64_t bv = sv == 0 ? nb0 : (sv == 1 ? nb1 : nb2);
-            f = phi3(xp, xs + 3 * (bu + u), xs + 3 * (bv + v));
+    McRun run;
+    mc_begin(run, pm, xr, nb, xs, t, ns, node);
+    McPoint res;
+    while (!mc_batch(run, it, xs, k, gl, g0, res)) {
+        if (failed && *failed) {
+            res.pass = false;
+            res.mean = res.sig = 0.0;
+            res.drawn = run.base;
+            break;
         }
-        if (base == 0) f0 = __shfl(f, g0);  // shift for numerically stable sums
-        const double g = valid ? f - f0 : 0.0;
-        const double p1 = group_incl_scan<W>(g, gl), p2 = group_incl_scan<W>(g * g, gl);
-        const double t1 = s1 + p1, t2 = s2 + p2;
-        const double m = (double)(sidx + 1);
-        const double mean = f0 + t1 / m;
-        const double var = sidx >= 1 ? fmax(t2 - t1 * t1 / m, 0.0) / (m - 1.0) : 0.0;
-        const double sig = sqrt(var / m);
-        const double credit = certified(k, ns, node, t, mean - k.z * sig, mean + k.z * sig);
-        const bool cond = valid && sidx >= 1 && k.z * sig <= (k.eps * credit + k.tau) / k.t_root;
-        const bool ok = cond && sidx + 1 >= k.m_min;
-        const bool stop = valid && (ok || sidx + 1 == k.m_limit);
-        // this group's bits of the wave's ballot
-        const unsigned long long bal = (__ballot(stop) >> g0) & ((1ull << W) - 1ull);
-        drawn = min(base + W, k.m_limit);
-        if (bal) {
-            const int L = g0 + __ffsll((long long)bal) - 1;
-            McPoint r;
-            r.pass = __shfl((int)ok, L) != 0;
-            r.mean = __shfl(mean, L);
-            r.sig = __shfl(sig, L);
-            r.drawn = drawn;
-            return r;
-        }
-        s1 += __shfl(p1, g0 + W - 1);
-        s2 += __shfl(p2, g0 + W - 1);
     }
-    McPoint r;
-    r.pass = false;
-    r.mean = r.sig = 0.0;
-    r.drawn = drawn;
-    return r;
+    return res;
 }
 
 // 2. Monte Carlo test and commit (Algorithms 3-5), one workgroup per triple.
@@ -604,7 +772,7 @@ __device__ McPoint mc_point_group(const Item &it, char cs, int slot, int64_t off
 // the triple is summarized only if every point passes (any failure ends the
 // test), in which case the points are credited T_i mu and
 // T_i (mu - z sigma_mu).
-__global__ __launch_bounds__(kMcThreads) void mc_kernel(
+__global__ __launch_bounds__(kMcThreads, MB_MC_WAVES) void mc_kernel(
     const Item *__restrict__ mc_list, NodeView nv, const double *__restrict__ xs, NodeStats ns,
     double *__restrict__ est, double *__restrict__ dev,
     unsigned long long *__restrict__ node_cov, MtConst k, MtCounters *__restrict__ ctr,
@@ -621,7 +789,7 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
     unsigned long long drawn = 0, my_failed = 0, my_prunes = 0;
     for (unsigned long long w = blockIdx.x; w < n_mc; w += gridDim.x) {
         const Item it = mc_list[w];
-        const int pn[3] = {it.p1, it.p2, it.p3};
+        const int64_t nb[3] = {nv.begin[it.p1], nv.begin[it.p2], nv.begin[it.p3]};
         const int64_t n1 = nv.end[it.p1] - nv.begin[it.p1], n2 = nv.end[it.p2] - nv.begin[it.p2],
                       n3 = nv.end[it.p3] - nv.begin[it.p3];
         const Roles r = roles_of(it.p1, it.p2, it.p3, n1, n2, n3);
@@ -648,14 +816,14 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
         if (threadIdx.x == 0) failed = 0;
         __syncthreads();
         for (int64_t e = grp; e < total; e += kGroups) {
-            if (failed) break;
+            if (*(volatile int *)&failed) break;
             int qq = 0;
             int64_t off = e;
             while (off >= szo[qq]) off -= szo[qq++];
             const int q = qo[qq];
-            const int64_t xr = nv.begin[r.node[q]] + off;
-            const McPoint res = mc_point_group(it, cs, r.slot[q], off, xr, n1, n2, n3, pn, nv, xs,
-                                               (double)r.t[q], ns, r.node[q], k, &failed, gl, g0);
+            const McPoint res = mc_point_group(it, partner_map(cs, r.slot[q], off, n1, n2, n3),
+                                               nv.begin[r.node[q]] + off, nb, xs, (double)r.t[q],
+                                               ns, r.node[q], k, &failed, gl, g0);
             drawn += res.drawn;
             if (!res.pass) {
                 if (gl == 0) failed = 1;
@@ -689,8 +857,9 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
                 mean = c_mean[e];
                 half = c_dev[e];
             } else {
-                const McPoint res = mc_point_group(it, cs, r.slot[q], off, xr, n1, n2, n3, pn, nv,
-                                                   xs, t, ns, r.node[q], k, nullptr, gl, g0);
+                const PartnerMap pm = partner_map(cs, r.slot[q], off, n1, n2, n3);
+                const McPoint res =
+                    mc_point_group(it, pm, xr, nb, xs, t, ns, r.node[q], k, nullptr, gl, g0);
                 mean = res.mean;
                 half = k.z * res.sig;
             }
@@ -714,6 +883,24 @@ __global__ __launch_bounds__(kMcThreads) void mc_kernel(
         if (my_prunes) atomicAdd(&ctr->mc_prunes, my_prunes);
     }
 }
+
+#ifdef MB_MC_DEBUG
+__global__ void mc_debug_kernel(const Item *__restrict__ mc_list, NodeView nv,
+                                const MtCounters *__restrict__ ctr, unsigned long long *out) {
+    const unsigned long long n = ctr->n_mc;
+    for (unsigned long long w = blockIdx.x * 256ull + threadIdx.x; w < n; w += gridDim.x * 256ull) {
+        const Item it = mc_list[w];
+        const int64_t n1 = nv.end[it.p1] - nv.begin[it.p1], n2 = nv.end[it.p2] - nv.begin[it.p2],
+                      n3 = nv.end[it.p3] - nv.begin[it.p3];
+        const Roles r = roles_of(it.p1, it.p2, it.p3, n1, n2, n3);
+        unsigned long long tot = 0;
+        for (int q = 0; q < r.n_roles; ++q) tot += nv.end[r.node[q]] - nv.begin[r.node[q]];
+        atomicAdd(&out[0], tot);
+        atomicMax(&out[1], tot);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[2] = n;
+}
+#endif
 
 // 3. Exhaustive base cases (MTPotentialBase) through the tile code of the
 // exhaustive sum.  A leaf triple (P1, P2, P3) holds the particle triples
@@ -1455,6 +1642,19 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
         phase_ms[0] += ms[0];
         phase_ms[1] += ms[1];
         phase_ms[2] += ms[2];
+#ifdef MB_MC_DEBUG
+        {
+            static unsigned long long *dbg = nullptr;
+            if (!dbg) (void)hipMalloc(&dbg, 64);
+            (void)hipMemsetAsync(dbg, 0, 64, s);
+            mc_debug_kernel<<<1024, 256, 0, s>>>(mc_list, nv, ctr, dbg);
+            unsigned long long h[3];
+            (void)hipMemcpy(h, dbg, sizeof h, hipMemcpyDeviceToHost);
+            if (ms[1] > 0.5)
+                fprintf(stderr, "mcdbg B=%d n_mc=%llu P=%llu maxP=%llu mc_ms=%.3f\n", B, h[2], h[0],
+                        h[1], ms[1]);
+        }
+#endif
         // units beyond the first batch (their credits reach the statistics
         // one round later, which only delays prunes)
         const unsigned long long n_units_max = std::max(n_units[0], n_units[1]);
