@@ -333,6 +333,7 @@ def serve_leg(n_req: int, dev) -> dict:
         "host_finalize_ms": st["finalize_ms"] - st0["finalize_ms"],
         "points_fp64": st["points_fp64"] - st0["points_fp64"],
         "slices": st["slices"] - st0["slices"],
+        "drain_launches": st["drain_launches"] - st0["drain_launches"],
         "mixed_slices": st["mixed_slices"] - st0["mixed_slices"],
         "peak_active": st["peak_active"],
         "fp64_fallbacks": st["fp64_fallbacks"],

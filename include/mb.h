@@ -343,14 +343,19 @@ double mb_normal_quantile(double alpha_half);
  *   - admission: requests are admitted in arrival order while a slot is free
  *     and their device footprint fits the HBM budget; the footprint of a
  *     request of N points is 24 N + 16 N bytes (points, Phi, near-field
- *     magnitudes) plus a region for its (i, j) pair-term table (about
- *     3 N^2 numbers) large enough for either the binary32 or the binary64
- *     table, each part rounded up to 256 B; the request holds all of it
+ *     magnitudes) plus a region for its (i, j) pair-term table (about N^2
+ *     numbers: a and w of each pair) large enough for either the binary32
+ *     or the binary64 table, each part rounded up to 256 B; the request holds all of it
  *     until it is released, whichever table validation selects;
  *   - continuous batching: the work units (block triples) of all admitted
- *     requests are drained together by a kernel whose resident workgroups
- *     pop (request, unit) items, in slices of a bounded number of units;
- *     requests with the fewest units left go first;
+ *     requests are drained together by one persistent kernel whose
+ *     workgroups take (request, unit) items from a ring in pinned host
+ *     memory; the server thread publishes them in slices of a bounded
+ *     number of units, requests with the fewest units left first.  The
+ *     kernel stays resident while work arrives and exits after all its
+ *     workgroups have been idle for 20 ms at once (it is launched again
+ *     when work arrives); it leaves 32 CUs free for the staging and
+ *     finishing kernels of requests;
  *   - completion: when a request's last unit has run, its Phi is copied back
  *     and the request counts as done (latency = done - submit, host clock).
  * Results are those of mb_eval_direct with the same precision, up to the
@@ -359,13 +364,14 @@ double mb_normal_quantile(double alpha_half);
 typedef struct {
     int64_t submitted, completed, failed; /* failed: finished with an error     */
     int64_t fp64_fallbacks;                /* binary32 requests run in binary64  */
-    int64_t slices, units;                 /* drain launches, work units run     */
+    int64_t slices, units;                 /* slices published, work units run   */
     int64_t mixed_slices;                  /* slices holding units of >= 2 requests */
     int64_t points_fp64;                   /* points recomputed in binary64 after binary32 */
     int64_t peak_reserved;                 /* bytes of the budget held at most   */
-    int32_t peak_active, pad;              /* admitted requests at most          */
+    int32_t peak_active;                   /* admitted requests at most          */
+    int32_t drain_launches;                /* launches of the persistent drain kernel */
     double triples;                        /* sum of C(N, 3) of completed ones   */
-    double busy_ms;                        /* compute-stream time of the slices  */
+    double busy_ms;                        /* wall time with units outstanding on the device */
     double stage_ms, finalize_ms;          /* host time staging / finishing requests */
 } mb_server_stats;
 
@@ -413,8 +419,9 @@ mb_status mb_server_latency(void *srv, int64_t req_id, double *seconds);
 /* Counters of the server so far (host struct). */
 mb_status mb_server_stats_get(void *srv, mb_server_stats *out);
 
-/* Units per slice (>= 1, at most 65536); the default is 8 per resident
- * workgroup of the drain kernel.  Takes effect at the next slice. */
+/* Units per slice (>= 1, at most 65536); the default is 8 per workgroup of
+ * the drain kernel.  At most two slices' worth of units are outstanding on
+ * the device at a time.  Takes effect at the next slice. */
 mb_status mb_server_set_slice_units(void *srv, int64_t units);
 
 /* Finish every request already submitted, then free the server. */

@@ -73,7 +73,7 @@ class ServerStats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in
                 ("submitted", "completed", "failed", "fp64_fallbacks", "slices", "units",
                  "mixed_slices", "points_fp64", "peak_reserved")] + \
-               [("peak_active", ctypes.c_int32), ("pad", ctypes.c_int32),
+               [("peak_active", ctypes.c_int32), ("drain_launches", ctypes.c_int32),
                 ("triples", ctypes.c_double), ("busy_ms", ctypes.c_double),
                 ("stage_ms", ctypes.c_double), ("finalize_ms", ctypes.c_double)]
 

@@ -2,19 +2,24 @@
 // different N arrive on the host; a scheduler thread admits them under an
 // HBM budget and a slot limit, stages and validates their points on the
 // device while earlier requests compute, and drains the work units of all
-// admitted requests together: each slice is one launch of a drain kernel
-// whose resident workgroups pop (request, block triple) items from a list
-// and run the exhaustive-sum tile code on them.  A request finishes when
-// every one of its units has run; its Phi is then copied back to the host.
+// admitted requests together through one persistent drain kernel: its
+// workgroups take (request, block triple) items from a ring in device
+// memory that the scheduler thread keeps filled by copies from pinned host
+// memory, run the exhaustive-sum tile code on them and flag each item done
+// in pinned host memory (serve_ring.hpp gives the protocol).  A request finishes when every one of its units has run; its
+// Phi is then copied back to the host.
 //
-// Up to two slices are queued on the compute stream.  Staging (copy in,
+// The drain kernel stays resident while there is work and for a bounded
+// idle time after it; it exits when all its workgroups have been idle that
+// long at once (or at shutdown), and the scheduler launches it again when
+// work arrives.  It leaves a few CUs free, so that staging (copy in,
 // validation, tables) and finishing (binary64 repairs, copy out) of
-// requests run on a second stream and never block the scheduler thread: it
-// enqueues them and polls per-slot events between slices, so the compute
-// stream sees back-to-back slices.  Every slice ends with a count check:
-// each slot's items run == items issued.
+// requests, which run on a second stream, are never held behind it.  The
+// scheduler thread enqueues those and polls per-slot events, so it never
+// blocks on the device.
 #include "direct_tile.hpp"
 #include "mb_internal.hpp"
+#include "serve_ring.hpp"
 #include "serve_sched.hpp"
 #include "serve_sizes.hpp"
 
@@ -40,6 +45,7 @@ struct ServeDesc {
     const void *tab;
     int32_t n, na;
     double scale, out_scale;
+    int32_t f64, pad;  // tile type: binary64 if nonzero
 };
 
 struct ServeItem {
@@ -62,44 +68,184 @@ __device__ __forceinline__ S uniform_load(const S *p) {
     return out;
 }
 
-constexpr int kHeaderWords = 16;  // next-item counters (two used), padded to 64 B
+// Control word of the drain ring in fine-grained pinned host memory: the
+// host writes it, the kernel reads it at system scope while it waits.
+struct DrainCtl {
+    unsigned int stop;  // set at shutdown
+    unsigned int pad[15];
+};
 
-// Resident workgroups pop items until the list is exhausted.  Every
-// workgroup reaches the exit: the counter only grows.
-//
-// The item fetch and the count update are done by all 64 lanes of wave 0
-// under a wave-uniform branch (lane 0 adds 1, the others 0), never under a
-// per-lane condition: a lane-divergent region at the loop boundary can be
-// merged across the back edge by the compiler so that the other lanes of
-// the wave re-enter the barrier without the fetching lane, and the item
-// index is then never refreshed.
+// The drain ring's device side.  The host writes tail (and the ring entries
+// and descriptors before it) by copies on its own stream; the kernel reads
+// them with system-scope loads, which do not hit stale cache lines.
+struct DrainDev {
+    unsigned long long tail;  // items [0, tail) are published
+    unsigned long long head;  // next ticket; continues across launches
+    unsigned int idle;        // workgroups waiting past the idle limit
+    unsigned int closing;     // they all were at once: every workgroup exits
+};
+
+struct DrainArgs {
+    const DrainCtl *ctl;
+    const ServeItem *ring;  // device memory, cap entries
+    const ServeDesc *desc;  // device memory, one per slot
+    unsigned int *done;     // host memory, cap flags
+    DrainDev *dev;
+    unsigned int cap, grid;
+    int n_slots, pad;
+    unsigned long long idle_ticks, hard_ticks;  // wall-clock ticks
+};
+
+#ifndef MB_DRAIN_POLL_ACQUIRE
+#define MB_DRAIN_POLL_ACQUIRE 1
+#endif
+#ifndef MB_DRAIN_DONE_RELEASE
+#define MB_DRAIN_DONE_RELEASE 1
+#endif
+constexpr int kPollOrder = MB_DRAIN_POLL_ACQUIRE ? __ATOMIC_ACQUIRE : __ATOMIC_RELAXED;
+constexpr int kDoneOrder = MB_DRAIN_DONE_RELEASE ? __ATOMIC_RELEASE : __ATOMIC_RELAXED;
+
+// Done flag values: the unit ran, or the item was refused as out of range.
+constexpr unsigned kDoneRan = 1, kDoneRefused = 2;
+
+// Whether an item names a unit of its request (bounds of the tile code).
 template <typename T>
-__global__ __launch_bounds__(DirectLds<T>::TPB, 1) void serve_kernel(const ServeDesc *__restrict__ desc,
-                                                            const ServeItem *__restrict__ items,
-                                                            int n_items, unsigned *__restrict__ next,
-                                                            unsigned *__restrict__ counts) {
+__device__ __forceinline__ bool item_in_range(const ServeItem &it, const ServeDesc &d) {
+    return d.x != nullptr && d.n >= 3 && it.a >= 0 && it.a < d.na && it.b >= 0 &&
+           (int64_t)it.b * kB < d.n && it.t >= 0 && (int64_t)it.t * DirectLds<T>::KT < d.n &&
+           (int64_t)d.na * DirectLds<T>::IB >= d.n;
+}
+
+__device__ __forceinline__ unsigned long long uniform64(unsigned long long v) {
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// A word-sized struct from host memory at system scope, made wave-uniform.
+// All its words are requested before the first is used, so the struct
+// costs one round trip over the host link, not one per word.
+template <typename S>
+__device__ __forceinline__ S system_load(const S *p) {
+    static_assert(sizeof(S) % 4 == 0, "word-sized struct");
+    constexpr int W = sizeof(S) / 4;
+    const unsigned *w = reinterpret_cast<const unsigned *>(p);
+    unsigned v[W];
+#pragma unroll
+    for (int e = 0; e < W; ++e) v[e] = __hip_atomic_load(w + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+#pragma unroll
+    for (int e = 0; e < W; ++e) v[e] = __builtin_amdgcn_readfirstlane(v[e]);
+    S out;
+    __builtin_memcpy(&out, v, sizeof(S));
+    return out;
+}
+
+// vmcnt(0), the other counters left alone: this wave's stores and atomics
+// have been performed.
+__device__ __forceinline__ void wait_vm_all() {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <typename T, typename L>
+__device__ __forceinline__ void drain_unit(L &s, const ServeItem &it, const ServeDesc &d) {
     constexpr int IB = DirectLds<T>::IB;
-    __shared__ DirectLds<T> s;
-    __shared__ int cur;
+    // the tables are written before their items are published and only read
+    using CT = __attribute__((address_space(4))) const T;
+    CT *blk = (CT *)static_cast<const T *>(d.tab) +
+              ((int64_t)it.b * d.na + it.a) * (IB * kB * kPairVals);
+    direct_unit<T, CT *>(s, d.x, d.n, it.a, it.b, it.t, blk, d.scale, d.out_scale, d.phi);
+}
+
+// The persistent drain.  Wave 0 of a workgroup takes a ticket and waits for
+// it to be published, for the stop flag, or until every workgroup has
+// waited longer than idle_ticks at once (then all exit); hard_ticks bounds
+// any single wait.  Every condition it branches on is wave-uniform, and all
+// 64 lanes of wave 0 take part in the ticket and flag updates (lane 0 adds
+// 1, the others 0), so no lane-divergent region meets the loop's back edge.
+// After a unit each wave waits for its own atomics, the workgroup meets at a
+// barrier, and wave 0 sets the item's done flag with a system-scope release
+// store, which writes the L2 back first: the host sees the flag only after
+// the unit's sums have reached memory.
+__global__ __launch_bounds__(512, 1) void drain_kernel(DrainArgs a) {
+    static_assert(DirectLds<float>::TPB == 512 && DirectLds<double>::TPB == 512,
+                  "one block size for both tile types");
+    __shared__ union {
+        DirectLds<float> f;
+        DirectLds<double> d;
+    } s;
+    __shared__ ServeItem s_it;
+    __shared__ ServeDesc s_d;
+    __shared__ unsigned long long s_tk;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    constexpr unsigned long long kExit = ~0ull;
     for (;;) {
         if (wave == 0) {
-            const unsigned got = atomicAdd(next, lane == 0 ? 1u : 0u);
-            cur = (int)__builtin_amdgcn_readfirstlane(got);  // lane 0's old value
+            const unsigned long long tk =
+                uniform64(atomicAdd(&a.dev->head, lane == 0 ? 1ull : 0ull));  // lane 0's
+            unsigned long long res = tk;
+            const unsigned long long t0 = wall_clock64();
+            bool counted = false;
+            for (;;) {
+                const unsigned long long tail = uniform64(
+                    __hip_atomic_load(&a.dev->tail, kPollOrder, __HIP_MEMORY_SCOPE_SYSTEM));
+                if (tk < tail) {
+                    if (counted) atomicSub(&a.dev->idle, lane == 0 ? 1u : 0u);
+                    break;
+                }
+                const unsigned closing = __builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                    &a.dev->closing, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                const unsigned stop = __builtin_amdgcn_readfirstlane(
+                    __hip_atomic_load(&a.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM));
+                if (stop || closing) {
+                    res = kExit;
+                    break;
+                }
+                const unsigned long long dt = (unsigned long long)wall_clock64() - t0;
+                if (!counted && dt > a.idle_ticks) {
+                    counted = true;
+                    const unsigned prev = __builtin_amdgcn_readfirstlane(
+                        atomicAdd(&a.dev->idle, lane == 0 ? 1u : 0u));
+                    if (prev + 1 == a.grid)
+                        __hip_atomic_store(&a.dev->closing, 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
+                if (dt > a.hard_ticks) {
+                    res = kExit;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(63);
+            }
+            if (res != kExit) {
+                ServeItem it = system_load(a.ring + res % a.cap);
+                ServeDesc d{};
+                if (it.slot >= 0 && it.slot < a.n_slots) d = system_load(a.desc + it.slot);
+                s_it = it;  // every lane of the wave writes the same value
+                s_d = d;
+            }
+            s_tk = res;
         }
         __syncthreads();
-        // read before the unit's first barrier, so wave 0 cannot overwrite it
-        // first; uniform, so the item and its descriptor sit in SGPRs
-        const int idx = __builtin_amdgcn_readfirstlane(cur);
-        if (idx >= n_items) break;
-        const ServeItem it = uniform_load(items + idx);
-        const ServeDesc d = uniform_load(desc + it.slot);
-        // the tables are written before the launch and only read by it
-        using CT = __attribute__((address_space(4))) const T;
-        CT *blk = (CT *)static_cast<const T *>(d.tab) + ((int64_t)it.b * d.na + it.a) * (IB * kB * kPairVals);
-        direct_unit<T, CT *>(s, d.x, d.n, it.a, it.b, it.t, blk, d.scale, d.out_scale, d.phi);
-        if (wave == 0) atomicAdd(&counts[it.slot], lane == 0 ? 1u : 0u);
+        const unsigned long long tk = uniform64(s_tk);
+        if (tk == kExit) break;
+        const ServeItem it = uniform_load(&s_it);
+        const ServeDesc d = uniform_load(&s_d);
+        // an item outside its request's units is refused, not run
+        const bool ok = it.slot >= 0 && it.slot < a.n_slots &&
+                        (d.f64 ? item_in_range<double>(it, d) : item_in_range<float>(it, d));
+        if (ok) {
+            if (d.f64)
+                drain_unit<double>(s.d, it, d);
+            else
+                drain_unit<float>(s.f, it, d);
+        }
+        wait_vm_all();
+        __syncthreads();
+        if (wave == 0)
+            __hip_atomic_store(a.done + tk % a.cap, ok ? kDoneRan : kDoneRefused,
+                               kDoneOrder, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -141,6 +287,57 @@ const serve::TableShape kTab64{DirectLds<double>::IB, kB, 8, kPairVals};
 // near-field magnitudes and a table region that fits either tile type).
 int64_t footprint(int64_t n) { return serve::chunk_layout(n, kTab32, kTab64).total; }
 
+// Pinned host memory for requests' points and results.  Allocating pinned
+// memory waits for the whole device, which here means for the resident
+// drain kernel, so it is carved from blocks that are kept: one free list
+// per power-of-two size, refilled a block of at least 1 MiB at a time.
+class PinnedPool {
+public:
+    PinnedPool() = default;
+    PinnedPool(const PinnedPool &) = delete;
+    PinnedPool &operator=(const PinnedPool &) = delete;
+    ~PinnedPool() {
+        for (void *b : blocks_) (void)hipHostFree(b);
+    }
+    // A buffer of at least `bytes` bytes (null on failure).
+    void *get(size_t bytes) {
+        const int c = size_class(bytes);
+        std::vector<void *> &fl = free_[c];
+        if (fl.empty()) {
+            const size_t sz = (size_t)1 << c;
+            const size_t per = std::max<size_t>(1, ((size_t)1 << 20) / sz);
+            void *b = nullptr;
+            if (hipHostMalloc(&b, sz * per, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+            blocks_.push_back(b);
+            for (size_t e = per; e-- > 0;) fl.push_back(static_cast<char *>(b) + e * sz);
+        }
+        void *p = fl.back();
+        fl.pop_back();
+        size_of_[p] = c;
+        return p;
+    }
+    void put(void *p) {
+        if (!p) return;
+        auto it = size_of_.find(p);
+        if (it == size_of_.end()) return;
+        free_[it->second].push_back(p);
+        size_of_.erase(it);
+    }
+
+private:
+    static int size_class(size_t bytes) {
+        int c = 12;  // 4 KiB at least
+        while (((size_t)1 << c) < bytes) ++c;
+        return c;
+    }
+    std::map<int, std::vector<void *>> free_;
+    std::map<void *, int> size_of_;
+    std::vector<void *> blocks_;
+};
+
 struct Request {
     int64_t id = 0, n = 0;
     int prec_req = MB_FP32C, prec = MB_FP32C;
@@ -156,6 +353,8 @@ struct Request {
     int64_t tab_bytes = 0;  // size of the table region at dtab
     double scale = 1.0, out_scale = 1.0;
     UnitMap um;
+    int64_t units = 0, keep = 0;  // from staging, applied once the tables are built
+    double *pin_x = nullptr, *pin_phi = nullptr;  // pinned copies of the points and Phi
 };
 
 class Server {
@@ -168,12 +367,17 @@ public:
         device_pool_setup();
         int cus = 0;
         MB_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_));
-        int occ_f = 0, occ_d = 0;
-        MB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_f, serve_kernel<float>, DirectLds<float>::TPB, 0));
-        MB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ_d, serve_kernel<double>, DirectLds<double>::TPB, 0));
-        grid_f_ = std::max(1, occ_f) * cus;
-        grid_d_ = std::max(1, occ_d) * cus;
-        sched_.set_slice_units(std::min<int64_t>(8 * (int64_t)grid_f_, kMaxSliceUnits));
+        int occ = 0;
+        MB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, drain_kernel, 512, 0));
+        // every workgroup must be resident at once (the idle rule counts all
+        // of them); kReserveCus CUs stay free for staging and finishing
+        grid_ = std::max(1, std::max(1, occ) * (cus - std::min(cus / 2, kReserveCus)));
+        sched_.set_slice_units(std::min<int64_t>(8 * (int64_t)grid_, kMaxSliceUnits));
+        int rate_khz = 0;
+        MB_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev_));
+        if (rate_khz <= 0) return fail(MB_ERR_DEVICE, "no device wall clock rate");
+        idle_ticks_ = (unsigned long long)rate_khz * kIdleMs;
+        hard_ticks_ = (unsigned long long)rate_khz * kHardMs;
         if (user_stream_) {
             cs_ = user_stream_;
         } else {
@@ -181,19 +385,30 @@ public:
             cs_ = own_cs_;
         }
         MB_HIP(hipStreamCreateWithFlags(&as_, hipStreamNonBlocking));
-        MB_HIP(hipEventCreateWithFlags(&ev_adm_, hipEventDisableTiming));
-        desc_table_.assign(max_slots_, ServeDesc{});
-        ring_bytes_ = sizeof(unsigned) * (kHeaderWords + align_slots()) +
-                      sizeof(ServeItem) * (size_t)kMaxSliceUnits;
-        for (SliceBuf &b : buf_) {
-            MB_HIP(hipEventCreateWithFlags(&b.ev_end, hipEventDefault));
-            MB_HIP(hipEventCreateWithFlags(&b.ev_start, hipEventDefault));
-            MB_HIP(hipMalloc(&b.d_desc, sizeof(ServeDesc) * max_slots_));
-            MB_HIP(hipHostMalloc(&b.h_desc, sizeof(ServeDesc) * max_slots_, hipHostMallocDefault));
-            MB_HIP(hipMalloc(&b.d_ring, ring_bytes_));
-            MB_HIP(hipHostMalloc(&b.h_ring, ring_bytes_, hipHostMallocDefault));
-            MB_HIP(hipHostMalloc(&b.h_counts, sizeof(unsigned) * max_slots_, hipHostMallocDefault));
-        }
+        MB_HIP(hipEventCreateWithFlags(&ev_k0_, hipEventDefault));
+        MB_HIP(hipEventCreateWithFlags(&ev_k1_, hipEventDefault));
+        MB_HIP(hipStreamCreateWithFlags(&ps_, hipStreamNonBlocking));
+        // stop flag and done flags: fine-grained pinned host memory, written
+        // and read while the kernel runs; the ring's entries, descriptors and
+        // tail values: pinned sources of the copies to the device side
+        MB_HIP(hipHostMalloc((void **)&ctl_, sizeof(DrainCtl), hipHostMallocCoherent));
+        MB_HIP(hipHostMalloc((void **)&done_, sizeof(unsigned) * kRingCap, hipHostMallocCoherent));
+        MB_HIP(hipHostMalloc((void **)&ring_, sizeof(ServeItem) * kRingCap, hipHostMallocDefault));
+        MB_HIP(hipHostMalloc((void **)&hdesc_, sizeof(ServeDesc) * max_slots_, hipHostMallocDefault));
+        MB_HIP(hipHostMalloc((void **)&tail_src_, sizeof(unsigned long long) * kTailSlots,
+                             hipHostMallocDefault));
+        std::memset((void *)ctl_, 0, sizeof(DrainCtl));
+        std::memset((void *)done_, 0, sizeof(unsigned) * kRingCap);
+        std::memset((void *)hdesc_, 0, sizeof(ServeDesc) * max_slots_);
+        MB_HIP(hipMalloc((void **)&ddev_, sizeof(DrainDev)));
+        MB_HIP(hipMemset(ddev_, 0, sizeof(DrainDev)));
+        MB_HIP(hipMalloc((void **)&d_ring_, sizeof(ServeItem) * kRingCap));
+        MB_HIP(hipMalloc((void **)&d_desc_, sizeof(ServeDesc) * max_slots_));
+        MB_HIP(hipMemset(d_desc_, 0, sizeof(ServeDesc) * max_slots_));
+        tail_ev_.assign(kTailSlots, nullptr);
+        for (hipEvent_t &e : tail_ev_) MB_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        MB_HIP(hipDeviceSynchronize());
+        desc_host_.assign(max_slots_, ServeDesc{});
         MB_HIP(hipHostMalloc(&slot_host_, sizeof(SlotHost) * max_slots_, hipHostMallocDefault));
         std::memset(slot_host_, 0, sizeof(SlotHost) * max_slots_);
         slot_ev_.assign(max_slots_, nullptr);
@@ -209,23 +424,27 @@ public:
         }
         cv_work_.notify_all();
         if (thread_.joinable()) thread_.join();
-        for (SliceBuf &b : buf_) {
-            if (b.d_desc) (void)hipFree(b.d_desc);
-            if (b.d_ring) (void)hipFree(b.d_ring);
-            if (b.h_desc) (void)hipHostFree(b.h_desc);
-            if (b.h_ring) (void)hipHostFree(b.h_ring);
-            if (b.h_counts) (void)hipHostFree(b.h_counts);
-            if (b.ev_end) (void)hipEventDestroy(b.ev_end);
-            if (b.ev_start) (void)hipEventDestroy(b.ev_start);
+        if (ctl_) {  // the kernel, if resident, exits at its next wait
+            __atomic_store_n(&ctl_->stop, 1u, __ATOMIC_RELEASE);
+            if (running_) (void)hipEventSynchronize(ev_k1_);
         }
-        if (ev_adm_) (void)hipEventDestroy(ev_adm_);
+        if (ev_k0_) (void)hipEventDestroy(ev_k0_);
+        if (ev_k1_) (void)hipEventDestroy(ev_k1_);
+        if (ps_) (void)hipStreamSynchronize(ps_);
+        for (hipEvent_t e : tail_ev_)
+            if (e) (void)hipEventDestroy(e);
+        if (ddev_) (void)hipFree(ddev_);
+        if (d_ring_) (void)hipFree(d_ring_);
+        if (d_desc_) (void)hipFree(d_desc_);
+        if (ctl_) (void)hipHostFree((void *)ctl_);
+        if (ring_) (void)hipHostFree((void *)ring_);
+        if (done_) (void)hipHostFree((void *)done_);
+        if (hdesc_) (void)hipHostFree((void *)hdesc_);
+        if (tail_src_) (void)hipHostFree((void *)tail_src_);
+        if (ps_) (void)hipStreamDestroy(ps_);
         for (hipEvent_t e : slot_ev_)
             if (e) (void)hipEventDestroy(e);
-        if (slot_host_) {
-            for (int q = 0; q < max_slots_; ++q)
-                if (slot_host_[q].phi) (void)hipHostFree(slot_host_[q].phi);
-            (void)hipHostFree(slot_host_);
-        }
+        if (slot_host_) (void)hipHostFree(slot_host_);
         if (as_) (void)hipStreamDestroy(as_);
         if (own_cs_) (void)hipStreamDestroy(own_cs_);
     }
@@ -324,26 +543,26 @@ public:
 
 private:
     static constexpr int64_t kMaxSliceUnits = 1 << 16;
+    static constexpr int64_t kRingCap = 1 << 18;  // ring entries (4 MiB of items)
+#ifndef MB_RESERVE_CUS
+#define MB_RESERVE_CUS 32
+#endif
+    static constexpr int kReserveCus = MB_RESERVE_CUS;  // CUs the drain kernel leaves free
+    static constexpr unsigned long long kIdleMs = 20;   // idle time before the kernel exits
+    static constexpr unsigned long long kHardMs = 500;  // longest single wait
+    static constexpr int kTailSlots = 64;              // tail values in flight to the device
+    static constexpr int kMaxStalled = 50;             // launches in a row that ran nothing
 
-    // Buffers of one slice in flight; two alternate, so that the host can
-    // queue slice s + 1 while slice s runs.
-    struct SliceBuf {
-        ServeDesc *d_desc = nullptr, *h_desc = nullptr;
-        void *d_ring = nullptr, *h_ring = nullptr;
-        unsigned *h_counts = nullptr;
-        hipEvent_t ev_start = nullptr, ev_end = nullptr;
+    // A slice published to the ring: its ranges and how many of its units
+    // have not finished.
+    struct Live {
+        serve::Slice sl;
+        int64_t left;
     };
-
-    size_t align_slots() const { return (size_t)((max_slots_ + 15) / 16) * 16; }
-    static unsigned *d_header(const SliceBuf &b) { return static_cast<unsigned *>(b.d_ring); }
-    static unsigned *d_counts(const SliceBuf &b) { return d_header(b) + kHeaderWords; }
-    ServeItem *d_items(const SliceBuf &b) const {
-        return reinterpret_cast<ServeItem *>(d_counts(b) + align_slots());
-    }
-    ServeItem *h_items(const SliceBuf &b) const {
-        return reinterpret_cast<ServeItem *>(static_cast<unsigned *>(b.h_ring) + kHeaderWords +
-                                             align_slots());
-    }
+    struct Entry {
+        int64_t seq;  // slice
+        ServeItem item;
+    };
 
     Request &req(int64_t id) {
         std::lock_guard<std::mutex> g(mu_);
@@ -385,7 +604,10 @@ private:
         r.dmag = reinterpret_cast<double *>(base + lay.mag);
         r.dtab = base + lay.tab;
         r.tab_bytes = lay.tab_bytes;
-        MB_HIP(hipMemcpyAsync(r.dx, r.x.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, as_));
+        r.pin_x = static_cast<double *>(pinned_.get(sizeof(double) * 3 * n));
+        if (!r.pin_x) return fail(MB_ERR_OOM, "pinned host allocation failed");
+        std::memcpy(r.pin_x, r.x.data(), sizeof(double) * 3 * n);
+        MB_HIP(hipMemcpyAsync(r.dx, r.pin_x, sizeof(double) * 3 * n, hipMemcpyHostToDevice, as_));
         mb_status st = zero_doubles(r.dphi, n, as_);
         if (st != MB_OK) return st;
         // the magnitude region (>= 256 bytes) holds the device record until the
@@ -449,76 +671,151 @@ private:
         }
         units = r.um.units();
         keep = footprint(n);  // the chunk keeps its size whichever tile type runs
+        ServeDesc &d = desc_host_[slot];
+        d.x = r.dx;
+        d.phi = r.dphi;
+        d.tab = r.dtab;
+        d.n = (int32_t)n;
+        d.na = r.um.na;
+        d.scale = r.scale;
+        d.out_scale = r.out_scale;
+        d.f64 = f64 ? 1 : 0;
+        d.pad = 0;
         return MB_OK;
     }
 
-    mb_status launch(const serve::Slice &sl, SliceBuf &b) {
-        // items of binary32 requests first, then binary64
-        std::vector<ServeItem> fi, di;
-        for (const auto &rg : sl.ranges) {
-            Request &r = req(rg.id);
-            auto &dst = r.prec == MB_FP64 ? di : fi;
-            for (int64_t u = rg.u0; u < rg.u1; ++u) {
-                ServeItem it;
-                it.slot = rg.slot;
-                r.um.decode(u, it.a, it.b, it.t);
-                dst.push_back(it);
+    // Publish slices while fewer than two slices' worth of units are
+    // outstanding and the ring has room (with a margin for the items an
+    // ending kernel leaves to republish and the tickets it skips).
+    mb_status publish() {
+        bool any = false;
+        while (sched_.has_runnable() && book_.outstanding() < 2 * sched_.slice_units() &&
+               book_.room() >= sched_.slice_units() + 4 * (int64_t)grid_) {
+            serve::Slice sl = sched_.next_slice();
+            if (sl.empty()) break;
+            for (const auto &rg : sl.ranges) {
+                Request &r = req(rg.id);
+                for (int64_t u = rg.u0; u < rg.u1; ++u) {
+                    ServeItem it;
+                    it.slot = rg.slot;
+                    r.um.decode(u, it.a, it.b, it.t);
+                    const int64_t k = book_.push(Entry{sl.seq, it});
+                    ring_[k % kRingCap] = it;
+                }
             }
-            ServeDesc &d = desc_table_[rg.slot];
-            d.x = r.dx;
-            d.phi = r.dphi;
-            d.tab = r.dtab;
-            d.n = (int32_t)r.n;
-            d.na = r.um.na;
-            d.scale = r.scale;
-            d.out_scale = r.out_scale;
+            {
+                std::lock_guard<std::mutex> g(mu_);
+                stats_.slices += 1;
+                if (sl.ranges.size() > 1) stats_.mixed_slices += 1;
+            }
+            const int64_t seq = sl.seq, units = sl.units;
+            live_[seq] = Live{std::move(sl), units};
+            any = true;
         }
-        const int nf = (int)fi.size();
-        const int nd = (int)di.size();
-        // the pinned copies of b were last read by slice seq - 2, which has finished
-        std::memcpy(b.h_desc, desc_table_.data(), sizeof(ServeDesc) * max_slots_);
-        std::memset(b.h_ring, 0, sizeof(unsigned) * (kHeaderWords + align_slots()));
-        std::copy(fi.begin(), fi.end(), h_items(b));
-        std::copy(di.begin(), di.end(), h_items(b) + nf);
-        const size_t bytes = sizeof(unsigned) * (kHeaderWords + align_slots()) +
-                             sizeof(ServeItem) * (size_t)(nf + nd);
-        MB_HIP(hipEventRecord(b.ev_start, cs_));
-        MB_HIP(hipMemcpyAsync(b.d_desc, b.h_desc, sizeof(ServeDesc) * max_slots_,
-                              hipMemcpyHostToDevice, cs_));
-        MB_HIP(hipMemcpyAsync(b.d_ring, b.h_ring, bytes, hipMemcpyHostToDevice, cs_));
-        if (nf)
-            serve_kernel<float><<<(unsigned)std::min(nf, grid_f_), DirectLds<float>::TPB, 0, cs_>>>(
-                b.d_desc, d_items(b), nf, d_header(b) + 0, d_counts(b));
-        if (nd)
-            serve_kernel<double><<<(unsigned)std::min(nd, grid_d_), DirectLds<double>::TPB, 0, cs_>>>(
-                b.d_desc, d_items(b) + nf, nd, d_header(b) + 1, d_counts(b));
-        MB_HIP(hipGetLastError());
-        MB_HIP(hipMemcpyAsync(b.h_counts, d_counts(b), sizeof(unsigned) * max_slots_,
-                              hipMemcpyDeviceToHost, cs_));
-        MB_HIP(hipEventRecord(b.ev_end, cs_));
+        return any ? send(t_sent_, book_.tail()) : MB_OK;
+    }
+
+    // Copy ring entries [from, to) to the device, then the new tail; one
+    // stream, so the entries land before the tail that publishes them.
+    mb_status send(int64_t from, int64_t to) {
+        for (int64_t k = from; k < to;) {
+            const int64_t e = k % kRingCap, len = std::min(to - k, kRingCap - e);
+            MB_HIP(hipMemcpyAsync(d_ring_ + e, ring_ + e, sizeof(ServeItem) * len,
+                                  hipMemcpyHostToDevice, ps_));
+            k += len;
+        }
+        const int q = (int)(tail_seq_++ % kTailSlots);
+        MB_HIP(hipEventSynchronize(tail_ev_[q]));  // its previous copy has long run
+        tail_src_[q] = (unsigned long long)to;
+        MB_HIP(hipMemcpyAsync(&ddev_->tail, tail_src_ + q, sizeof(unsigned long long),
+                              hipMemcpyHostToDevice, ps_));
+        MB_HIP(hipEventRecord(tail_ev_[q], ps_));
+        t_sent_ = to;
         return MB_OK;
     }
 
-    mb_status finish_slice(const serve::Slice &sl, const SliceBuf &b,
-                           std::vector<int64_t> &finished) {
-        MB_HIP(hipEventSynchronize(b.ev_end));
-        float ms = 0.f;
-        MB_HIP(hipEventElapsedTime(&ms, b.ev_start, b.ev_end));
-        std::vector<int64_t> expect(max_slots_, 0);
-        for (const auto &rg : sl.ranges) expect[rg.slot] += rg.u1 - rg.u0;
-        for (int s = 0; s < max_slots_; ++s)
-            if ((int64_t)b.h_counts[s] != expect[s])
-                return fail(MB_ERR_DEVICE, "drain kernel ran " + std::to_string(b.h_counts[s]) +
-                                               " items of slot " + std::to_string(s) + ", issued " +
-                                               std::to_string(expect[s]));
-        {
+    // Consume the done flags the kernel has set; slices whose units have all
+    // run finish their requests.
+    mb_status collect(std::vector<int64_t> &finished) {
+        int64_t n_done = 0;
+        bool refused = false;
+        auto flags = [&](int64_t e) {
+            const unsigned f = __atomic_load_n(&done_[e], __ATOMIC_ACQUIRE);
+            if (f == 0) return false;
+            refused = refused || f != kDoneRan;
+            __atomic_store_n(&done_[e], 0u, __ATOMIC_RELAXED);
+            return true;
+        };
+        auto on_done = [&](const Entry &en) {
+            ++n_done;
+            auto it = live_.find(en.seq);
+            if (it == live_.end()) return;
+            if (--it->second.left == 0) {
+                for (int64_t id : sched_.slice_done(it->second.sl)) finished.push_back(id);
+                live_.erase(it);
+            }
+        };
+        if (!book_.collect(flags, on_done))
+            return fail(MB_ERR_DEVICE, "the drain kernel flagged an item it was not given");
+        if (refused) return fail(MB_ERR_DEVICE, "the drain kernel refused an item out of range");
+        if (n_done) {
+            units_done_ += n_done;
             std::lock_guard<std::mutex> g(mu_);
-            stats_.slices += 1;
-            stats_.units += sl.units;
-            if (sl.ranges.size() > 1) stats_.mixed_slices += 1;
-            stats_.busy_ms += ms;
+            stats_.units += n_done;
         }
-        for (int64_t id : sched_.slice_done(sl)) finished.push_back(id);
+        return MB_OK;
+    }
+
+    // An ended kernel: republish what its exiting workgroups abandoned.
+    // Outstanding work and no kernel: launch one.
+    mb_status drain_lifecycle(std::vector<int64_t> &finished) {
+        mb_status st;
+        if (running_) {
+            const hipError_t q = hipEventQuery(ev_k1_);
+            if (q == hipErrorNotReady) return MB_OK;
+            MB_HIP(q);
+            running_ = false;
+            unsigned long long head = 0;
+            MB_HIP(hipMemcpyAsync(&head, &ddev_->head, sizeof head, hipMemcpyDeviceToHost, cs_));
+            MB_HIP(hipStreamSynchronize(cs_));
+            if ((st = collect(finished)) != MB_OK) return st;
+            // a kernel that ended with work published before its launch and
+            // ran none of it saw no items: after a run of such launches the
+            // server gives up rather than relaunch for ever
+            stalled_ = units_at_launch_ == units_done_ && out_at_launch_ > 0 ? stalled_ + 1 : 0;
+            if (stalled_ > kMaxStalled)
+                return fail(MB_ERR_DEVICE, "the drain kernel ran no published item in " +
+                                               std::to_string(stalled_) + " launches");
+            const int64_t again = book_.after_exit((int64_t)head);
+            for (int64_t k = book_.tail() - again; k < book_.tail(); ++k)
+                ring_[k % kRingCap] = book_.payload(k).item;
+            if ((st = send(book_.tail() - again, book_.tail())) != MB_OK) return st;
+        }
+        if (!running_ && book_.outstanding() > 0) {
+            // the ticket counter continues; the idle count and latch restart
+            MB_HIP(hipMemsetAsync(&ddev_->idle, 0, 2 * sizeof(unsigned), cs_));
+            DrainArgs a;
+            a.ctl = ctl_;
+            a.ring = d_ring_;
+            a.desc = d_desc_;
+            a.done = done_;
+            a.dev = ddev_;
+            a.cap = (unsigned)kRingCap;
+            a.grid = (unsigned)grid_;
+            a.n_slots = max_slots_;
+            a.pad = 0;
+            a.idle_ticks = idle_ticks_;
+            a.hard_ticks = hard_ticks_;
+            units_at_launch_ = units_done_;
+            out_at_launch_ = book_.outstanding();
+            MB_HIP(hipEventRecord(ev_k0_, cs_));
+            drain_kernel<<<(unsigned)grid_, 512, 0, cs_>>>(a);
+            MB_HIP(hipGetLastError());
+            MB_HIP(hipEventRecord(ev_k1_, cs_));
+            running_ = true;
+            std::lock_guard<std::mutex> g(mu_);
+            stats_.drain_launches += 1;
+        }
         return MB_OK;
     }
 
@@ -526,19 +823,14 @@ private:
     // Phi into the slot's pinned buffer.  No wait.
     mb_status finish_begin(Request &r, int slot) {
         SlotHost &h = slot_host_[slot];
-        if (h.phi_cap < r.n) {
-            if (h.phi) (void)hipHostFree(h.phi);
-            h.phi = nullptr;
-            h.phi_cap = 0;
-            MB_HIP(hipHostMalloc(&h.phi, sizeof(double) * (size_t)r.n, hipHostMallocDefault));
-            h.phi_cap = r.n;
-        }
+        r.pin_phi = static_cast<double *>(pinned_.get(sizeof(double) * (size_t)r.n));
+        if (!r.pin_phi) return fail(MB_ERR_OOM, "pinned host allocation failed");
         h.flagged = 0;
         if (r.prec == MB_FP32C) {
             const mb_status st = point_fp64_enqueue(r.dx, r.n, r.dmag, r.dphi, as_, &h.flagged);
             if (st != MB_OK) return st;
         }
-        MB_HIP(hipMemcpyAsync(h.phi, r.dphi, sizeof(double) * r.n, hipMemcpyDeviceToHost, as_));
+        MB_HIP(hipMemcpyAsync(r.pin_phi, r.dphi, sizeof(double) * r.n, hipMemcpyDeviceToHost, as_));
         MB_HIP(hipEventRecord(slot_ev_[slot], as_));
         return MB_OK;
     }
@@ -551,11 +843,15 @@ private:
         if (flagged > point_fix_cap(r.n)) {  // rare: redo the request in binary64
             mb_status st = point_fp64_redo_all(r.dx, r.n, r.dphi, as_);
             if (st != MB_OK) return st;
-            MB_HIP(hipMemcpyAsync(h.phi, r.dphi, sizeof(double) * r.n, hipMemcpyDeviceToHost, as_));
+            MB_HIP(hipMemcpyAsync(r.pin_phi, r.dphi, sizeof(double) * r.n, hipMemcpyDeviceToHost, as_));
             MB_HIP(hipStreamSynchronize(as_));
             flagged = r.n;
         }
-        r.phi.assign(h.phi, h.phi + r.n);
+        r.phi.assign(r.pin_phi, r.pin_phi + r.n);
+        pinned_.put(r.pin_phi);
+        r.pin_phi = nullptr;
+        pinned_.put(r.pin_x);  // the points' copy has long landed
+        r.pin_x = nullptr;
         if (flagged) {
             std::lock_guard<std::mutex> g(mu_);
             stats_.points_fp64 += flagged;
@@ -571,6 +867,8 @@ private:
         Request &r = req(id);
         if (r.chunk) (void)hipFreeAsync(r.chunk, as_);
         r.chunk = nullptr;
+        pinned_.put(r.pin_x);  // dropped before its copy was issued or after it landed
+        r.pin_x = nullptr;
         sched_.release(id);
         complete(r, st, msg);
     }
@@ -585,15 +883,18 @@ private:
             for (int64_t id : inbox_) sched_.enqueue(id, footprint(reqs_.at(id)->n));
             inbox_.clear();
         }
-        mb_status st;
-        // 1. keep up to two slices queued on the compute stream
-        if (inflight_.size() < 2) {
-            serve::Slice sl = sched_.next_slice();
-            if (!sl.empty()) {
-                if ((st = launch(sl, buf_[sl.seq & 1])) != MB_OK) return st;
-                inflight_.push_back(std::move(sl));
+        {  // wall time with units outstanding on the device
+            const double t = now_s();
+            if (book_.outstanding() > 0 && t_last_ > 0.0) {
+                std::lock_guard<std::mutex> g(mu_);
+                stats_.busy_ms += (t - t_last_) * 1e3;
             }
+            t_last_ = t;
         }
+        mb_status st;
+        // 1. units that have run; the kernel's end and (re)launch
+        if ((st = collect(finished)) != MB_OK) return st;
+        if ((st = drain_lifecycle(finished)) != MB_OK) return st;
         // 2. finished requests: enqueue their repairs and copies
         const double t0 = now_s();
         for (int64_t id : finished) {
@@ -627,8 +928,7 @@ private:
             if (st != MB_OK) return st;
             validating_.push_back(id);
         }
-        // 5. validations that have landed: finish staging, then the request runs
-        bool staged = false;
+        // 5. validations that have landed: enqueue the tables
         for (size_t q = 0; q < validating_.size();) {
             const int64_t id = validating_[q];
             const int slot = sched_.slot_of(id);
@@ -640,9 +940,8 @@ private:
             MB_HIP(e);
             validating_.erase(validating_.begin() + (long)q);
             Request &r = req(id);
-            int64_t units = 0, keep = 0;
             std::string why;
-            st = stage_end(r, slot, units, keep, why);
+            st = stage_end(r, slot, r.units, r.keep, why);
             if (st == MB_ERR_OOM) {
                 (void)hipGetLastError();
                 why = last_error_cstr();
@@ -652,41 +951,37 @@ private:
                 continue;
             }
             if (st != MB_OK) return st;
-            sched_.start(id, units, keep);
-            staged = true;
+            MB_HIP(hipEventRecord(slot_ev_[slot], as_));
+            staging_.push_back(id);
         }
-        if (staged) {
-            MB_HIP(hipEventRecord(ev_adm_, as_));
-            MB_HIP(hipStreamWaitEvent(cs_, ev_adm_, 0));
+        // 6. tables built: the request's units may be published
+        for (size_t q = 0; q < staging_.size();) {
+            const int64_t id = staging_[q];
+            const int slot = sched_.slot_of(id);
+            const hipError_t e = hipEventQuery(slot_ev_[slot]);
+            if (e == hipErrorNotReady) {
+                ++q;
+                continue;
+            }
+            MB_HIP(e);
+            staging_.erase(staging_.begin() + (long)q);
+            Request &r = req(id);
+            hdesc_[slot] = desc_host_[slot];  // copied ahead of the request's items
+            MB_HIP(hipMemcpyAsync(d_desc_ + slot, hdesc_ + slot, sizeof(ServeDesc),
+                                  hipMemcpyHostToDevice, ps_));
+            sched_.start(id, r.units, r.keep);
         }
         {
             std::lock_guard<std::mutex> g(mu_);
             stats_.finalize_ms += (t1 - t0) * 1e3;
             stats_.stage_ms += (now_s() - t1) * 1e3;
         }
-        // 6. collect the oldest slice when two are queued or nothing else can
-        // be queued, once its end event has passed (polled, so that arrivals
-        // keep being staged meanwhile); with no slice in flight, report
-        // whether anything is pending
-        idle = false;
-        if (!inflight_.empty() && (inflight_.size() == 2 || !sched_.has_runnable())) {
-            const serve::Slice &old = inflight_.front();
-            const hipError_t q = hipEventQuery(buf_[old.seq & 1].ev_end);
-            if (q == hipSuccess) {
-                if ((st = finish_slice(old, buf_[old.seq & 1], finished)) != MB_OK) return st;
-                inflight_.pop_front();
-            } else if (q == hipErrorNotReady) {
-                std::this_thread::sleep_for(std::chrono::microseconds(10));
-            } else {
-                return fail(MB_ERR_DEVICE, std::string("hipEventQuery: ") + hipGetErrorString(q));
-            }
-        } else if (inflight_.empty() && !sched_.has_runnable()) {
-            if (finishing_.empty() && validating_.empty() && finished.empty()) {
-                idle = true;
-            } else {
-                std::this_thread::sleep_for(std::chrono::microseconds(20));
-            }
-        }
+        // 7. publish, and launch a kernel if none is resident
+        if ((st = publish()) != MB_OK) return st;
+        if ((st = drain_lifecycle(finished)) != MB_OK) return st;
+        idle = book_.outstanding() == 0 && !sched_.has_runnable() && finishing_.empty() &&
+               validating_.empty() && staging_.empty() && finished.empty();
+        if (!idle) std::this_thread::sleep_for(std::chrono::microseconds(10));
         {
             std::lock_guard<std::mutex> g(mu_);
             stats_.peak_reserved = sched_.peak_reserved();
@@ -738,23 +1033,36 @@ private:
     serve::Scheduler sched_;  // scheduler thread only
     int max_slots_;
     hipStream_t user_stream_ = nullptr, own_cs_ = nullptr, cs_ = nullptr, as_ = nullptr;
-    hipEvent_t ev_adm_ = nullptr;
-    int dev_ = 0, grid_f_ = 1, grid_d_ = 1;
-    SliceBuf buf_[2];
-    // per slot: pinned validation record, repair count and result buffer, and
-    // an event marking when the staging or finishing copies have landed
+    int dev_ = 0, grid_ = 1;
+    // the drain ring (host memory shared with the kernel) and the kernel's state
+    DrainCtl *ctl_ = nullptr;
+    ServeItem *ring_ = nullptr, *d_ring_ = nullptr;
+    unsigned *done_ = nullptr;
+    ServeDesc *hdesc_ = nullptr, *d_desc_ = nullptr;
+    DrainDev *ddev_ = nullptr;
+    unsigned long long *tail_src_ = nullptr;
+    std::vector<hipEvent_t> tail_ev_;
+    int64_t tail_seq_ = 0, t_sent_ = 0;
+    hipStream_t ps_ = nullptr;  // copies that publish ring entries
+    int64_t units_done_ = 0, units_at_launch_ = 0, out_at_launch_ = 0;
+    int stalled_ = 0;
+    serve::RingBook<Entry> book_{kRingCap, 4096};
+    std::map<int64_t, Live> live_;  // published slices by sequence number
+    bool running_ = false;
+    hipEvent_t ev_k0_ = nullptr, ev_k1_ = nullptr;
+    unsigned long long idle_ticks_ = 0, hard_ticks_ = 0;
+    double t_last_ = 0.0;
+    // per slot: pinned validation record and repair count, and
+    // an event marking when the staging or finishing work has landed
     struct SlotHost {
         ValidateOut v;
         int32_t flagged;
-        double *phi;
-        int64_t phi_cap;
     };
     SlotHost *slot_host_ = nullptr;
     std::vector<hipEvent_t> slot_ev_;
-    std::vector<int64_t> validating_, finishing_;
-    std::vector<ServeDesc> desc_table_;   // per slot, host master copy
-    std::deque<serve::Slice> inflight_;   // slices queued on the compute stream
-    size_t ring_bytes_ = 0;
+    std::vector<int64_t> validating_, staging_, finishing_;
+    std::vector<ServeDesc> desc_host_;  // per slot, written at staging
+    PinnedPool pinned_;                 // scheduler thread only
     std::thread thread_;
 
     std::mutex mu_;  // guards everything below
