@@ -540,9 +540,6 @@ __device__ __forceinline__ void partners(const PartnerMap &m, uint64_t r, int64_
 }
 
 constexpr int kMcThreads = 256;
-#ifndef MB_MC_ABORT
-#define MB_MC_ABORT 0
-#endif
 #ifndef MB_MC_WAVES
 #define MB_MC_WAVES 4  // waves per SIMD the sampler's registers must allow
 #endif
@@ -628,13 +625,18 @@ constexpr int kMcBatch = 2 * kMcGroup;
 
 // Running statistics after sample count m (m >= 1) from the shifted sums
 // t1 = sum (f - f0), t2 = sum (f - f0)^2.
+//
+// The rule z s <= (eps C(mu - z s, mu + z s) + tau) / T_root, s = sigma_mu,
+// is tested without a square root or a division: every term of the credit
+// C is linear in z s with slope -T_i (`certified`), C = C0 - T_i z s, so the
+// rule reads z s <= R = (eps C0 + tau) / (T_root + eps T_i), i.e.
+// R >= 0 and z^2 s^2 <= R^2; den = 1 / (T_root + eps T_i) is set per point.
 struct McStat {
     bool ok, stop;
-    double mean, sig;
-    double need;  // samples the rule would need at this sigma: m (z sigma_mu / allowance)^2
+    double mean, var_mu;  // running mean and sigma_mu^2
 };
 __device__ __forceinline__ McStat mc_stat(double f0, double t1, double t2, int m, double t,
-                                          const NodeAllow &na, const MtConst &k) {
+                                          const NodeAllow &na, const MtConst &k, double den) {
     const double dm = (double)m;
     double im = __builtin_amdgcn_rcp(dm);  // 1/m: hardware estimate, one Newton step
     im = fma(fma(-dm, im, 1.0), im, im);
@@ -642,13 +644,12 @@ __device__ __forceinline__ McStat mc_stat(double f0, double t1, double t2, int m
     im1 = fma(fma(-(dm - 1.0), im1, 1.0), im1, im1);
     McStat r;
     r.mean = fma(t1, im, f0);
-    const double var = m >= 2 ? fmax(fma(-t1 * t1, im, t2), 0.0) * im1 : 0.0;
-    r.sig = sqrt(var * im);
-    const double credit = certified(k, na, t, r.mean - k.z * r.sig, r.mean + k.z * r.sig);
-    const double lim = (k.eps * credit + k.tau) / k.t_root;
-    const bool cond = m >= 2 && k.z * r.sig <= lim;
-    const double ratio = k.z * r.sig / lim;
-    r.need = lim > 0.0 ? dm * ratio * ratio : INFINITY;
+    r.var_mu = m >= 2 ? fmax(fma(-t1 * t1, im, t2), 0.0) * im1 * im : 0.0;
+    const double tm = t * r.mean;
+    double c0 = na.pos + tm;
+    if (k.two_sided) c0 = fmax(fmax(c0, na.neg - tm), na.mix - fabs(tm));
+    const double R = (k.eps * c0 + k.tau) * den;
+    const bool cond = m >= 2 && R >= 0.0 && k.z * k.z * r.var_mu <= R * R;
     r.ok = cond && m >= k.m_min;
     r.stop = r.ok || m == k.m_limit;
     return r;
@@ -660,14 +661,15 @@ struct McRun {
     PartnerMap pm;
     NodeAllow na;
     int32_t xr, bu, bv;
-    double x0, x1, x2, t;
+    double x0, x1, x2, t, den;
     double f0, s1, s2;
     int base;
 };
 
 __device__ __forceinline__ void mc_begin(McRun &r, const PartnerMap &pm, int64_t xr,
                                          const int64_t nb[3], const double *__restrict__ xs,
-                                         double t, const NodeStats &ns, int node) {
+                                         double t, const NodeStats &ns, int node,
+                                         const MtConst &k) {
     r.pm = pm;
     r.na = node_allow(ns, node);
     r.xr = (int32_t)xr;
@@ -677,6 +679,7 @@ __device__ __forceinline__ void mc_begin(McRun &r, const PartnerMap &pm, int64_t
     r.x1 = xs[3 * xr + 1];
     r.x2 = xs[3 * xr + 2];
     r.t = t;
+    r.den = 1.0 / (k.t_root + k.eps * t);
     r.f0 = r.s1 = r.s2 = 0.0;
     r.base = 0;
 }
@@ -711,8 +714,9 @@ __device__ __forceinline__ bool mc_batch(McRun &r, const Item &it, const double 
     const double ga = va ? fa - r.f0 : 0.0, gb = vb ? fb - r.f0 : 0.0;
     const double p1 = row16_incl_scan(ga + gb);
     const double p2 = row16_incl_scan(fma(ga, ga, gb * gb));
-    const McStat A = mc_stat(r.f0, r.s1 + (p1 - gb), r.s2 + fma(-gb, gb, p2), sa + 1, r.t, r.na, k);
-    const McStat B = mc_stat(r.f0, r.s1 + p1, r.s2 + p2, sa + 2, r.t, r.na, k);
+    const McStat A =
+        mc_stat(r.f0, r.s1 + (p1 - gb), r.s2 + fma(-gb, gb, p2), sa + 1, r.t, r.na, k, r.den);
+    const McStat B = mc_stat(r.f0, r.s1 + p1, r.s2 + p2, sa + 2, r.t, r.na, k, r.den);
     const bool stop_a = va && A.stop, stop_b = vb && B.stop;
     // this group's bits of the wave's ballot
     const unsigned long long bal = (__ballot(stop_a || stop_b) >> g0) & ((1ull << W) - 1ull);
@@ -722,20 +726,11 @@ __device__ __forceinline__ bool mc_batch(McRun &r, const Item &it, const double 
         const McStat &S = stop_a ? A : B;
         res.pass = __shfl((int)S.ok, L) != 0;
         res.mean = __shfl(S.mean, L);
-        res.sig = __shfl(S.sig, L);
+        res.sig = sqrt(__shfl(S.var_mu, L));
         res.drawn = drawn;
         return true;
     }
-    bool give_up = drawn >= k.m_limit;
-#if MB_MC_ABORT > 0
-    // A point whose sample variance, after at least m_min samples, asks for
-    // more than MB_MC_ABORT * m_limit samples is taken to fail now rather
-    // than at m_limit: failing only sends the triple on to its children, so
-    // the estimate's guarantee is unchanged.
-    give_up = give_up || (drawn >= k.m_min &&
-                          __shfl(B.need, g0 + W - 1) > (double)MB_MC_ABORT * (double)k.m_limit);
-#endif
-    if (give_up) {
+    if (drawn >= k.m_limit) {
         res.pass = false;
         res.mean = res.sig = 0.0;
         res.drawn = drawn;
@@ -754,7 +749,7 @@ __device__ McPoint mc_point_group(const Item &it, const PartnerMap &pm, int64_t 
                                   const NodeStats &ns, int node, const MtConst &k,
                                   const volatile int *failed, int gl, int g0) {
     McRun run;
-    mc_begin(run, pm, xr, nb, xs, t, ns, node);
+    mc_begin(run, pm, xr, nb, xs, t, ns, node, k);
     McPoint res;
     while (!mc_batch(run, it, xs, k, gl, g0, res)) {
         if (failed && *failed) {

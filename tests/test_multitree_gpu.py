@@ -173,6 +173,27 @@ def test_monte_carlo_guarantee(cuda):
     assert np.all(cov.cpu().numpy() == (n - 1) * (n - 2) // 2)
 
 
+def test_monte_carlo_limit_below_min(cuda):
+    # m_limit < m_min: no point can reach m_min samples, so every Monte Carlo
+    # attempt fails at m_limit and the node triples go on to their children;
+    # the result still meets the bound at every sampled point, with full
+    # coverage (Algorithm 4's two limits)
+    import paper_1105_2769_amd as mb
+
+    x = clustered(512, CENTERS8[:6], seed=40, spread=1.0)
+    n = x.shape[0]
+    idx = workloads.sample_indices(n, 128, seed=41)
+    ref = oracle_direct.phi(x, idx)
+    eps, alpha = 1e-2, 0.05
+    phi, st, cov = mb.eval_multitree(dev(x, cuda), eps=eps, alpha=alpha, leaf_size=32,
+                                     coverage=True, seed=7, zeta=4.0, m_limit=16)
+    rel = np.abs(phi.cpu().numpy()[idx] - ref) / np.abs(ref)
+    assert st["mc_prunes"] == 0 and st["mc_failed"] > 0
+    assert st["mc_samples"] <= 16 * n * st["mc_failed"]
+    assert float(np.mean(rel <= eps)) >= 1 - alpha
+    assert np.all(cov.cpu().numpy() == (n - 1) * (n - 2) // 2)
+
+
 def test_tree_reuse_same_result(cuda):
     import paper_1105_2769_amd as mb
 
