@@ -541,7 +541,7 @@ __device__ __forceinline__ void partners(const PartnerMap &m, uint64_t r, int64_
 
 constexpr int kMcThreads = 256;
 #ifndef MB_MC_WAVES
-#define MB_MC_WAVES 4  // waves per SIMD the sampler's registers must allow
+#define MB_MC_WAVES 3  // waves per SIMD the sampler's registers must allow
 #endif
 constexpr int kMcCache = 2048;  // points whose (mu, lower bound) stay in LDS between passes
 
@@ -564,12 +564,20 @@ __device__ __forceinline__ double row_shr(double v) {
                                             (unsigned)lo));
 }
 
-// Inclusive prefix sum over each row of 16 lanes.
-__device__ __forceinline__ double row16_incl_scan(double v) {
-    v += row_shr<1>(v);
-    v += row_shr<2>(v);
-    v += row_shr<4>(v);
-    v += row_shr<8>(v);
+// Inclusive prefix sum over each aligned group of W lanes (8 or 16; gl:
+// lane in group).  A row shift fills the first lanes of a 16-lane row with
+// 0; a group of 8 in the upper half of a row masks what it would take from
+// the lower half.
+template <int W>
+__device__ __forceinline__ double group_incl_scan(double v, int gl) {
+    static_assert(W == 8 || W == 16, "a DPP row or half a row");
+    double u = row_shr<1>(v);
+    v += (W == 16 || gl >= 1) ? u : 0.0;
+    u = row_shr<2>(v);
+    v += (W == 16 || gl >= 2) ? u : 0.0;
+    u = row_shr<4>(v);
+    v += (W == 16 || gl >= 4) ? u : 0.0;
+    if constexpr (W == 16) v += row_shr<8>(v);
     return v;
 }
 
@@ -608,10 +616,10 @@ __device__ __forceinline__ double phi_sample(double x0, double x1, double x2, co
     return __builtin_amdgcn_ldexp((double)f, -9 * e);
 }
 
-// Algorithm 4 for one point, by a group of kMcGroup lanes of a wave (four
-// points per wave): samples are drawn kMcBatch at a time, lane l of the group
-// taking samples 2l and 2l + 1 of the batch from the two halves of one
-// Philox block (sample s uses counter s / 2, half s mod 2); prefix sums give
+// Algorithm 4 for one point, by a group of kMcGroup lanes of a wave:
+// samples are drawn kMcBatch at a time, lane l of the group taking samples
+// kMcPer l .. kMcPer l + kMcPer - 1 of the batch, two from each Philox block
+// (sample s uses counter s / 2, half s mod 2); prefix sums give
 // the running mean and unbiased variance after every sample, and the first
 // sample count m at which the sequential loop would stop - the termination
 // rule holding with m >= m_min, or m = m_limit - is found with a ballot.
@@ -620,8 +628,12 @@ __device__ __forceinline__ double phi_sample(double x0, double x1, double x2, co
 // stops at m_min = 30 draws 32).  Every lane of the group returns the same
 // result.  `failed` (nullable) aborts between batches.  gl: lane in the
 // group, g0: the group's first lane in the wave.
-constexpr int kMcGroup = 16;  // one DPP row
-constexpr int kMcBatch = 2 * kMcGroup;
+#ifndef MB_MC_PER
+#define MB_MC_PER 4
+#endif
+constexpr int kMcPer = MB_MC_PER;        // samples per lane per batch (even)
+constexpr int kMcBatch = 32;              // samples per batch of a point
+constexpr int kMcGroup = kMcBatch / kMcPer;  // lanes per point
 
 // Running statistics after sample count m (m >= 1) from the shifted sums
 // t1 = sum (f - f0), t2 = sum (f - f0)^2.
@@ -688,45 +700,92 @@ __device__ __forceinline__ void mc_begin(McRun &r, const PartnerMap &pm, int64_t
 // test of the point has ended, with its result in res.
 __device__ __forceinline__ bool mc_batch(McRun &r, const Item &it, const double *__restrict__ xs,
                                          const MtConst &k, int gl, int g0, McPoint &res) {
-    constexpr int W = kMcGroup;
+    constexpr int W = kMcGroup, E = kMcPer;
     const int base = r.base;
-    const int sa = base + 2 * gl;  // this lane's samples sa, sa + 1
-    const bool va = sa < k.m_limit, vb = sa + 1 < k.m_limit;
-    double fa = 0.0, fb = 0.0;
-    if (va) {
-        uint32_t c[4] = {(uint32_t)r.xr, (uint32_t)(sa >> 1), (uint32_t)it.p1, (uint32_t)it.p2};
-        philox4x32_10(c, (uint32_t)it.p3, k.seed32);
-        // both samples' partners first, so that their four point loads are
-        // in flight together (the second tuple is a valid one even when
-        // sample sa + 1 lies past m_limit; its value is then unused)
-        int64_t ua, wa, ub, wb;
-        partners(r.pm, ((uint64_t)c[1] << 32) | c[0], ua, wa);
-        partners(r.pm, ((uint64_t)c[3] << 32) | c[2], ub, wb);
-        const double *pa = xs + 3 * (r.bu + ua), *qa = xs + 3 * (r.bv + wa);
-        const double *pb = xs + 3 * (r.bu + ub), *qb = xs + 3 * (r.bv + wb);
-        const double a0[3] = {pa[0], pa[1], pa[2]}, a1[3] = {qa[0], qa[1], qa[2]};
-        const double b0[3] = {pb[0], pb[1], pb[2]}, b1[3] = {qb[0], qb[1], qb[2]};
-        fa = phi_sample(r.x0, r.x1, r.x2, a0, a1);
-        const double fb_ = phi_sample(r.x0, r.x1, r.x2, b0, b1);
-        fb = vb ? fb_ : 0.0;
+    const int sa = base + E * gl;  // this lane's samples sa .. sa + E - 1
+    double f[E];
+    bool v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        v[e] = sa + e < k.m_limit;
+        f[e] = 0.0;
     }
-    if (base == 0) r.f0 = __shfl(fa, g0);  // shift for numerically stable sums
-    const double ga = va ? fa - r.f0 : 0.0, gb = vb ? fb - r.f0 : 0.0;
-    const double p1 = row16_incl_scan(ga + gb);
-    const double p2 = row16_incl_scan(fma(ga, ga, gb * gb));
-    const McStat A =
-        mc_stat(r.f0, r.s1 + (p1 - gb), r.s2 + fma(-gb, gb, p2), sa + 1, r.t, r.na, k, r.den);
-    const McStat B = mc_stat(r.f0, r.s1 + p1, r.s2 + p2, sa + 2, r.t, r.na, k, r.den);
-    const bool stop_a = va && A.stop, stop_b = vb && B.stop;
+    if (v[0]) {
+        // all the lane's partner tuples first, so that their point loads are
+        // in flight together (a tuple is valid even when its sample lies
+        // past m_limit; its value is then unused)
+        int64_t u[E], w[E];
+#pragma unroll
+        for (int h = 0; h < E / 2; ++h) {
+            uint32_t c[4] = {(uint32_t)r.xr, (uint32_t)((sa >> 1) + h), (uint32_t)it.p1,
+                             (uint32_t)it.p2};
+            philox4x32_10(c, (uint32_t)it.p3, k.seed32);
+            partners(r.pm, ((uint64_t)c[1] << 32) | c[0], u[2 * h], w[2 * h]);
+            partners(r.pm, ((uint64_t)c[3] << 32) | c[2], u[2 * h + 1], w[2 * h + 1]);
+        }
+        double pu[E][3], pw[E][3];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const double *a = xs + 3 * (r.bu + u[e]), *b = xs + 3 * (r.bv + w[e]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                pu[e][c] = a[c];
+                pw[e][c] = b[c];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const double fe = phi_sample(r.x0, r.x1, r.x2, pu[e], pw[e]);
+            f[e] = v[e] ? fe : 0.0;
+        }
+    }
+    if (base == 0) r.f0 = __shfl(f[0], g0);  // shift for numerically stable sums
+    double g[E], l1 = 0.0, l2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        g[e] = v[e] ? f[e] - r.f0 : 0.0;
+        l1 += g[e];
+        l2 = fma(g[e], g[e], l2);
+    }
+    const double p1 = group_incl_scan<W>(l1, gl), p2 = group_incl_scan<W>(l2, gl);
+    // sums through each of the lane's samples, from the last one down
+    McStat S[E];
+    bool stop[E];
+    {
+        double q1 = r.s1 + p1, q2 = r.s2 + p2;
+#pragma unroll
+        for (int e = E - 1; e >= 0; --e) {
+            S[e] = mc_stat(r.f0, q1, q2, sa + e + 1, r.t, r.na, k, r.den);
+            stop[e] = v[e] && S[e].stop;
+            q1 -= g[e];
+            q2 = fma(-g[e], g[e], q2);
+        }
+    }
+    bool any = false;
+    int first = E - 1;
+#pragma unroll
+    for (int e = E - 1; e >= 0; --e)
+        if (stop[e]) {
+            any = true;
+            first = e;
+        }
     // this group's bits of the wave's ballot
-    const unsigned long long bal = (__ballot(stop_a || stop_b) >> g0) & ((1ull << W) - 1ull);
+    const unsigned long long bal = (__ballot(any) >> g0) & ((1ull << W) - 1ull);
     const int drawn = min(base + kMcBatch, k.m_limit);
     if (bal) {
         const int L = g0 + __ffsll((long long)bal) - 1;
-        const McStat &S = stop_a ? A : B;
-        res.pass = __shfl((int)S.ok, L) != 0;
-        res.mean = __shfl(S.mean, L);
-        res.sig = sqrt(__shfl(S.var_mu, L));
+        bool ok = false;
+        double mean = 0.0, var_mu = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (e == first) {
+                ok = S[e].ok;
+                mean = S[e].mean;
+                var_mu = S[e].var_mu;
+            }
+        res.pass = __shfl((int)ok, L) != 0;
+        res.mean = __shfl(mean, L);
+        res.sig = sqrt(__shfl(var_mu, L));
         res.drawn = drawn;
         return true;
     }
