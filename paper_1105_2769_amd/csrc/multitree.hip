@@ -564,19 +564,20 @@ __device__ __forceinline__ double row_shr(double v) {
                                             (unsigned)lo));
 }
 
-// Inclusive prefix sum over each aligned group of W lanes (8 or 16; gl:
+// Inclusive prefix sum over each aligned group of W lanes (4, 8 or 16; gl:
 // lane in group).  A row shift fills the first lanes of a 16-lane row with
-// 0; a group of 8 in the upper half of a row masks what it would take from
-// the lower half.
+// 0; a smaller group masks what it would take from the group before it.
 template <int W>
 __device__ __forceinline__ double group_incl_scan(double v, int gl) {
-    static_assert(W == 8 || W == 16, "a DPP row or half a row");
+    static_assert(W == 4 || W == 8 || W == 16, "a DPP row or a part of one");
     double u = row_shr<1>(v);
     v += (W == 16 || gl >= 1) ? u : 0.0;
     u = row_shr<2>(v);
     v += (W == 16 || gl >= 2) ? u : 0.0;
-    u = row_shr<4>(v);
-    v += (W == 16 || gl >= 4) ? u : 0.0;
+    if constexpr (W >= 8) {
+        u = row_shr<4>(v);
+        v += (W == 16 || gl >= 4) ? u : 0.0;
+    }
     if constexpr (W == 16) v += row_shr<8>(v);
     return v;
 }
