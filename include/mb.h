@@ -89,6 +89,30 @@ int32_t mb_version(void);
 mb_status mb_eval_direct(const double *x, int64_t n, int32_t prec, double *phi, void *stream);
 
 /*
+ * The binary64 exhaustive sum of mb_eval_direct (prec MB_FP64; Section 1's
+ * definition) with every floating-point addition in an order fixed by N
+ * alone: the same points give the same bits on every call, whatever the
+ * scheduling of work on the GPU.  Within a work unit each wave keeps its
+ * own partial sums and the waves are combined in wave order; each unit then
+ * writes its sums to a row of device memory, and three passes add the rows
+ * into Phi point by point in a fixed order.  The result differs from
+ * mb_eval_direct's (whose FP64 atomics add in arrival order) only by
+ * rounding, and the two differ bitwise from each other in general.
+ *
+ *   scratch_bytes : device-memory bound for one stripe of the evaluation
+ *                   (pair-term table plus unit rows, 2 KiB per work unit of
+ *                   64 x 64 x 128 slots); <= 0 means MB_TABLE_BUDGET_MB.
+ *                   The J blocks are taken in stripes that fit it, at least
+ *                   one block of 64 per stripe; stripes run in order.
+ *
+ * Validation, errors and the N < 3 case are those of mb_eval_direct; waits
+ * on `stream` for the validation, then enqueues the sum.  MB_ERR_OOM if the
+ * scratch cannot be allocated.
+ */
+mb_status mb_eval_direct_deterministic(const double *x, int64_t n, double *phi,
+                                       int64_t scratch_bytes, void *stream);
+
+/*
  * mb_eval_direct without the validation step and without any wait: the
  * evaluation is only enqueued on `stream`.  For callers that have already
  * validated the same points (mb_validate) and must not block, e.g. a timing
@@ -107,7 +131,7 @@ mb_status mb_eval_direct_unchecked(const double *x, int64_t n, int32_t prec, dou
  * allocation.  Same arguments, preconditions and result; it calls no
  * hipMalloc, hipFree or allocating routine.  Its scratch - the unit offsets
  * and the (i, j) pair-term table - lives in one library-owned device array
- * of 24 MiB + 256 bytes per GPU, allocated when the library is loaded and
+ * of 16 MiB + 256 bytes per GPU, allocated when the library is loaded and
  * held until the process ends, so N is limited to 1024
  * (MB_ERR_UNSUPPORTED above).  Every call on a GPU uses that GPU's array:
  * calls that overlap on one GPU (several streams or threads) race and give

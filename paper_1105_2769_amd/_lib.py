@@ -90,6 +90,7 @@ SIGNATURES = {
     "mb_eval_direct": (_c_i32, [_c_vp, _c_i64, _c_i32, _c_vp, _c_vp]),
     "mb_eval_direct_unchecked": (_c_i32, [_c_vp, _c_i64, _c_i32, _c_vp, _c_vp]),
     "mb_eval_direct_noalloc": (_c_i32, [_c_vp, _c_i64, _c_i32, _c_vp, _c_vp]),
+    "mb_eval_direct_deterministic": (_c_i32, [_c_vp, _c_i64, _c_vp, _c_i64, _c_vp]),
     "mb_build_kdtree": (_c_i32, [_c_vp, _c_i64, _c_i32, _c_vp, ctypes.POINTER(_c_vp)]),
     "mb_free_kdtree": (_c_i32, [_c_vp]),
     "mb_kdtree_info": (_c_i32, [_c_vp, ctypes.POINTER(_c_i64), ctypes.POINTER(_c_i32),
@@ -176,6 +177,21 @@ def eval_direct(x, prec: str = "fp64", out=None, checked: bool = True):
         raise TypeError("out must be a contiguous float64 tensor of N elements")
     fn = lib().mb_eval_direct if checked else lib().mb_eval_direct_unchecked
     check(fn(_c_vp(x.data_ptr()), n, PREC[prec], _c_vp(phi.data_ptr()), stream_of(x)))
+    return phi
+
+
+def eval_direct_deterministic(x, out=None, scratch_bytes: int = 0):
+    """Binary64 exhaustive Phi with a fixed summation order
+    (mb_eval_direct_deterministic): bitwise the same on every call."""
+    import torch
+
+    x = _points(x)
+    n = x.shape[0]
+    phi = torch.empty(n, dtype=torch.float64, device=x.device) if out is None else out
+    if phi.dtype != torch.float64 or phi.numel() != n or not phi.is_contiguous():
+        raise TypeError("out must be a contiguous float64 tensor of N elements")
+    check(lib().mb_eval_direct_deterministic(_c_vp(x.data_ptr()), n, _c_vp(phi.data_ptr()),
+                                             int(scratch_bytes), stream_of(x)))
     return phi
 
 

@@ -147,6 +147,21 @@ mb_status mb_eval_direct(const double *x, int64_t n, int32_t prec, double *phi, 
     return direct_launch(x, n, p, scale, phi, s, r_fix);
 }
 
+mb_status mb_eval_direct_deterministic(const double *x, int64_t n, double *phi,
+                                       int64_t scratch_bytes, void *stream) {
+    clear_error();
+    if (n < 0) return fail(MB_ERR_INVALID, "n < 0");
+    if (n > 0 && (!x || !phi)) return fail(MB_ERR_INVALID, "null pointer");
+    if (n >= ((int64_t)1 << 31)) return fail(MB_ERR_UNSUPPORTED, "n must be < 2^31");
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) return MB_OK;
+    ValidateOut v{};
+    mb_status st = check_points(x, n, s, &v);
+    if (st != MB_OK) return st;
+    const size_t budget = scratch_bytes > 0 ? (size_t)scratch_bytes : table_budget_bytes();
+    return direct_launch_ordered(x, n, phi, budget, s);
+}
+
 mb_status mb_eval_direct_unchecked(const double *x, int64_t n, int32_t prec, double *phi,
                                    void *stream) {
     clear_error();

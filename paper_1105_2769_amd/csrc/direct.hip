@@ -28,6 +28,120 @@ __global__ __launch_bounds__(DirectLds<T>::TPB, DirectShape<T>::MINB) void direc
     }
 }
 
+// The exhaustive sum's units in the fixed-order mode: unit u writes its row
+// of IB + JB + KT sums (tile_unit) to rows[(u - u_begin) * W].
+template <typename T>
+__global__ __launch_bounds__(DirectLds<T>::TPB, DirectShape<T>::MINB) void direct_rows_kernel(
+    const double *__restrict__ x, int n, int na, int nb, int nt,
+    const int64_t *__restrict__ unit_off, int64_t u_begin, int64_t u_end, int b0,
+    const T *__restrict__ utab, double *__restrict__ rows) {
+    constexpr int IB = DirectLds<T>::IB;
+    constexpr int W = IB + kB + DirectLds<T>::KT;
+    __shared__ DirectLds<T> s;
+    for (int64_t u = u_begin + blockIdx.x; u < u_end; u += gridDim.x) {
+        int a, b, t;
+        decode_unit(u, unit_off, nb, nt, DirectLds<T>::KR, a, b, t);
+        direct_unit<T, const T *, true>(
+            s, x, n, a, b, t, utab + ((int64_t)(b - b0) * na + a) * (IB * kB * kPairVals), 1.0,
+            1.0, rows + (u - u_begin) * W);
+    }
+}
+
+// Sums of the unit rows of J blocks [b0, b1) (units [off[b0], off[b1]),
+// row r = u - off[b0]) into phi, one launch per role of a point: as i, as j,
+// as k.  A workgroup owns one block of points and adds, for each point, the
+// rows that hold it in a fixed order split into kRT / columns interleaved
+// streams; the streams are added in stream order and the total is added to
+// phi.  Launches on one stream run in order, so every point's result is the
+// same sequence of additions on every call.
+constexpr int kRT = 256;  // threads of the row-sum kernels
+
+// As i: block a, rows of units (a, b, t) in order of b, then t.
+template <int IB, int KR, int W>
+__global__ __launch_bounds__(kRT) void rows_i_kernel(const double *__restrict__ rows,
+                                                     const int64_t *__restrict__ off, int n, int na,
+                                                     int nt, int b0, int b1,
+                                                     double *__restrict__ phi) {
+    constexpr int S = kRT / IB;
+    static_assert(kRT % IB == 0, "whole streams");
+    __shared__ double part[S][IB];
+    const int a = blockIdx.x, c = threadIdx.x % IB, st = threadIdx.x / IB;
+    const int64_t r_first = off[b0];
+    double acc = 0.0;
+    for (int b = b0; b < b1; ++b) {
+        if (a >= units_a(b, IB, na)) continue;
+        const int tc = nt - b / KR;
+        const int64_t base = off[b] - r_first + (int64_t)a * tc;
+#pragma unroll 4
+        for (int q = st; q < tc; q += S) acc += rows[(base + q) * W + c];
+    }
+    part[st][c] = acc;
+    __syncthreads();
+    if (st == 0) {
+        double v = part[0][c];
+#pragma unroll
+        for (int k = 1; k < S; ++k) v += part[k][c];
+        const int64_t i = (int64_t)a * IB + c;
+        if (i < n) phi[i] += v;
+    }
+}
+
+// As j: J block b0 + blockIdx.x, its units in unit order.
+template <int IB, int JB, int W>
+__global__ __launch_bounds__(kRT) void rows_j_kernel(const double *__restrict__ rows,
+                                                     const int64_t *__restrict__ off, int n, int b0,
+                                                     double *__restrict__ phi) {
+    constexpr int S = kRT / JB;
+    static_assert(kRT % JB == 0, "whole streams");
+    __shared__ double part[S][JB];
+    const int b = b0 + blockIdx.x, c = threadIdx.x % JB, st = threadIdx.x / JB;
+    const int64_t r_first = off[b0];
+    const int64_t r0 = off[b] - r_first, r1 = off[b + 1] - r_first;
+    double acc = 0.0;
+#pragma unroll 4
+    for (int64_t r = r0 + st; r < r1; r += S) acc += rows[r * W + IB + c];
+    part[st][c] = acc;
+    __syncthreads();
+    if (st == 0) {
+        double v = part[0][c];
+#pragma unroll
+        for (int k = 1; k < S; ++k) v += part[k][c];
+        const int64_t j = (int64_t)b * JB + c;
+        if (j < n) phi[j] += v;
+    }
+}
+
+// As k: K tile t, rows of units (a, b, t) in order of b, then a.
+template <int IB, int JB, int KT, int KR, int W>
+__global__ __launch_bounds__(kRT) void rows_k_kernel(const double *__restrict__ rows,
+                                                     const int64_t *__restrict__ off, int n, int na,
+                                                     int nt, int b0, int b1,
+                                                     double *__restrict__ phi) {
+    constexpr int S = kRT / KT;
+    static_assert(kRT % KT == 0, "whole streams");
+    __shared__ double part[S][KT];
+    const int t = blockIdx.x, c = threadIdx.x % KT, st = threadIdx.x / KT;
+    const int64_t r_first = off[b0];
+    const int b_end = min(b1, KR * (t + 1));  // k > j needs b / KR <= t
+    double acc = 0.0;
+    for (int b = b0; b < b_end; ++b) {
+        const int tb = b / KR, tc = nt - tb;
+        const int n_a = units_a(b, IB, na);
+        const int64_t base = off[b] - r_first + (t - tb);
+#pragma unroll 4
+        for (int a = st; a < n_a; a += S) acc += rows[(base + (int64_t)a * tc) * W + IB + JB + c];
+    }
+    part[st][c] = acc;
+    __syncthreads();
+    if (st == 0) {
+        double v = part[0][c];
+#pragma unroll
+        for (int k = 1; k < S; ++k) v += part[k][c];
+        const int64_t kk = (int64_t)t * KT + c;
+        if (kk < n) phi[kk] += v;
+    }
+}
+
 // Near-field refinement of the binary32 tiles.  Each pair term is rounded to
 // binary32 once and reused by every triple through that pair, so its
 // rounding error does not average out over those triples; through the
@@ -647,6 +761,61 @@ mb_status direct_launch(const double *x, int64_t n, int prec, double scale, doub
     // too many strongly cancelling points for point-wise repair
     if (recomputed) *recomputed = n;
     return point_fp64_redo_all(x, n, phi, s);
+}
+
+// The binary64 exhaustive sum in the fixed-order mode: per stripe of J
+// blocks, the units write their rows, then the three row-sum kernels add
+// them into phi (zeroed here).  A stripe holds as many J blocks as keep its
+// (i, j) table plus its rows within `budget` bytes, at least one.
+mb_status direct_launch_ordered(const double *x, int64_t n, double *phi, size_t budget,
+                                hipStream_t s) {
+    using T = double;
+    constexpr int IB = DirectLds<T>::IB, KR = DirectLds<T>::KR, KT = DirectLds<T>::KT;
+    constexpr int W = IB + kB + KT;
+    mb_status st = zero_doubles(phi, n, s);
+    if (st != MB_OK || n < 3) return st;
+    const int na = (int)((n + IB - 1) / IB), nb = (int)((n + kB - 1) / kB);
+    const int nt = (int)((n + KT - 1) / KT);
+    std::vector<int64_t> off(nb + 1, 0);
+    for (int b = 0; b < nb; ++b)
+        off[b + 1] = off[b] + (int64_t)units_a(b, IB, na) * (nt - b / KR);
+    const size_t per_b = (size_t)na * IB * kB * kPairVals * sizeof(T);
+    const size_t row_bytes = (size_t)W * sizeof(double);
+    std::vector<int> cut{0};
+    size_t tab_max = 0, rows_max = 0;
+    for (int b0 = 0; b0 < nb;) {
+        auto need = [&](int e) { return per_b * (e - b0) + (size_t)(off[e] - off[b0]) * row_bytes; };
+        int b1 = b0 + 1;
+        while (b1 < nb && need(b1 + 1) <= budget) ++b1;
+        tab_max = std::max(tab_max, per_b * (b1 - b0));
+        rows_max = std::max(rows_max, (size_t)(off[b1] - off[b0]));
+        cut.push_back(b1);
+        b0 = b1;
+    }
+    Scratch unit_tab, pair_tab, rows;
+    if ((st = unit_tab.alloc(sizeof(int64_t) * (nb + 1), s)) != MB_OK) return st;
+    if ((st = pair_tab.alloc(tab_max, s)) != MB_OK) return st;
+    if ((st = rows.alloc(rows_max * row_bytes, s)) != MB_OK) return st;
+    const int64_t *doff = unit_tab.as<int64_t>();
+    unit_offsets_kernel<<<1, 1, 0, s>>>(nb, nt, KR, IB, na, unit_tab.as<int64_t>());
+    MB_HIP(hipGetLastError());
+    for (size_t c = 0; c + 1 < cut.size(); ++c) {
+        const int b0 = cut[c], b1 = cut[c + 1];
+        const int64_t u0 = off[b0], u1 = off[b1];
+        pair_table_kernel<T><<<dim3((unsigned)na, (unsigned)(b1 - b0)), 256, 0, s>>>(
+            x, (int)n, na, b0, 1.0, pair_tab.as<T>());
+        const unsigned grid = (unsigned)std::min<int64_t>(u1 - u0, (int64_t)1 << 30);
+        direct_rows_kernel<T><<<grid, DirectLds<T>::TPB, 0, s>>>(
+            x, (int)n, na, nb, nt, doff, u0, u1, b0, pair_tab.as<T>(), rows.as<double>());
+        rows_i_kernel<IB, KR, W><<<(unsigned)na, kRT, 0, s>>>(rows.as<double>(), doff, (int)n, na,
+                                                              nt, b0, b1, phi);
+        rows_j_kernel<IB, kB, W><<<(unsigned)(b1 - b0), kRT, 0, s>>>(rows.as<double>(), doff,
+                                                                     (int)n, b0, phi);
+        rows_k_kernel<IB, kB, KT, KR, W><<<(unsigned)nt, kRT, 0, s>>>(rows.as<double>(), doff,
+                                                                      (int)n, na, nt, b0, b1, phi);
+        MB_HIP(hipGetLastError());
+    }
+    return MB_OK;
 }
 
 }  // namespace mb

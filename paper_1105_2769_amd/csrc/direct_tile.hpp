@@ -114,10 +114,21 @@ struct DirectLds {
     static constexpr int KR = Shape::KR;
     static constexpr int KT = 64 * KR;                   // points per K tile
     static constexpr int XS = IB + JB + KT;
+    // the fixed-order mode's per-wave sums fit in the space they share
+    static constexpr bool kOrderedFits = Shape::NW * 8 <= kJC * (int)sizeof(T) &&
+                                         Shape::NW * JB <= kJC * 64;
+    static constexpr int kOW = kOrderedFits ? Shape::NW : 1;
     double xs[3][XS];                              // coordinates of the I, J blocks and K tile
-    T cb[kJC][KT], cq[kJC][KT], co[kJC][KT];       // (j, k) terms of the chunk
+    union {
+        T cb[kJC][KT];                             // (j, k) terms of the chunk
+        double kw[kOW][KT];                        // fixed order: Phi_k per wave, after the chunks
+    };
+    T cq[kJC][KT], co[kJC][KT];
     T cbb[Shape::kLdsBB ? kJC : 1][KT];            // their b^2 (kLdsBB)
-    double pj[kJC][64];                            // Phi_j partials per (j, lane), all waves
+    union {
+        double pj[kJC][64];                        // Phi_j partials per (j, lane), all waves
+        double pjw[kOW][JB];                       // fixed order: Phi_j per (wave, j)
+    };
     double pjacc[JB];                              // Phi_j of the unit
     double kacc[KT];                               // Phi_k of the unit
 };
@@ -241,10 +252,19 @@ __device__ __forceinline__ T tile_psi(T a, T g, T wg, T b, T bb, T ob) {
 // the table is unchanged during the kernel).  x holds the coordinates the
 // ranks index; sums go to phi[rank] (times out_scale).  Every thread of the
 // workgroup calls it.
-template <typename T, int JB, typename Shape, typename Ix, typename TabPtr>
+//
+// kOrdered: every sum of the unit is formed in an order fixed by the code
+// alone (per-wave partials, lane reductions by a fixed butterfly, waves
+// combined in wave order), and phi is instead the unit's own row of
+// IB + JB + KT values: the I block's sums, then the J block's, then the K
+// tile's, times out_scale (empty slots get 0).  Adding the rows of all
+// units in a fixed order then gives a result independent of scheduling.
+template <typename T, int JB, typename Shape, typename Ix, typename TabPtr, bool kOrdered = false>
 __device__ __forceinline__ void tile_unit(DirectLds<T, JB, Shape> &s, const double *__restrict__ x,
                                           const Ix &ix, TabPtr ublk, double scale,
                                           double out_scale, double *__restrict__ phi) {
+    static_assert(!kOrdered || DirectLds<T, JB, Shape>::kOrderedFits,
+                  "per-wave sums of the fixed-order mode fit in the LDS they reuse");
     constexpr int IPW = Shape::IPW;
     constexpr int IB = DirectLds<T, JB, Shape>::IB;
     constexpr int TPB = DirectLds<T, JB, Shape>::TPB;
@@ -266,7 +286,8 @@ __device__ __forceinline__ void tile_unit(DirectLds<T, JB, Shape> &s, const doub
         s.xs[1][p] = ok ? x[3 * (int64_t)g + 1] * scale : 0.0;
         s.xs[2][p] = ok ? x[3 * (int64_t)g + 2] * scale : 0.0;
     }
-    for (int e = tid; e < kKT; e += TPB) s.kacc[e] = 0.0;
+    if constexpr (!kOrdered)
+        for (int e = tid; e < kKT; e += TPB) s.kacc[e] = 0.0;
     __syncthreads();
 
     // (i, k) pair terms of this wave, in registers for the whole unit
@@ -333,7 +354,8 @@ __device__ __forceinline__ void tile_unit(DirectLds<T, JB, Shape> &s, const doub
                 if constexpr (Shape::kLdsBB) s.cbb[jj][kl] = b * b;
             }
         }
-        for (int e = tid; e < kJC * 64; e += TPB) s.pj[e / 64][e % 64] = 0.0;
+        if constexpr (!kOrdered)
+            for (int e = tid; e < kJC * 64; e += TPB) s.pj[e / 64][e % 64] = 0.0;
         __syncthreads();
 
         const TabPtr uc = up + (jc * kJC) * (IB * kPairVals);
@@ -388,7 +410,12 @@ __device__ __forceinline__ void tile_unit(DirectLds<T, JB, Shape> &s, const doub
                 else
                     acck[kk] = fma((double)o.cq[kk], (double)sk[kk], acck[kk]);
             }
-            atomicAdd(&s.pj[jj][lane], (double)pj32);
+            if constexpr (kOrdered) {
+                const double v = wave_sum((double)pj32);
+                if (lane == 0) s.pjw[wave][jc * kJC + jj] = v;
+            } else {
+                atomicAdd(&s.pj[jj][lane], (double)pj32);
+            }
         };
         // Two operand sets: everything step jj + 1 reads is loaded while
         // step jj computes, so one wait per step covers loads issued a
@@ -436,20 +463,47 @@ __device__ __forceinline__ void tile_unit(DirectLds<T, JB, Shape> &s, const doub
         }
         __syncthreads();
         // Phi_j of the chunk: 16 rows of 64 slots, 32 threads per row
+        if constexpr (!kOrdered) {
 #pragma unroll
-        for (int r0 = 0; r0 < kJC; r0 += TPB / 32) {
-            const int row = r0 + (tid >> 5), c = tid & 31;
-            // whole 32-lane groups drop out together, so the shuffles stay
-            // inside groups that are all active
-            if (row < kJC) {
-                double v = s.pj[row][c] + s.pj[row][c + 32];
+            for (int r0 = 0; r0 < kJC; r0 += TPB / 32) {
+                const int row = r0 + (tid >> 5), c = tid & 31;
+                // whole 32-lane groups drop out together, so the shuffles
+                // stay inside groups that are all active
+                if (row < kJC) {
+                    double v = s.pj[row][c] + s.pj[row][c + 32];
 #pragma unroll
-                for (int m = 16; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-                if (c == 0) s.pjacc[jc * kJC + row] = v;
+                    for (int m = 16; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+                    if (c == 0) s.pjacc[jc * kJC + row] = v;
+                }
             }
         }
     }
 
+    if constexpr (kOrdered) {
+        constexpr int NW = Shape::NW;
+#pragma unroll
+        for (int ii = 0; ii < IPW; ++ii) {
+            const double v = wave_sum(sizeof(T) == 4 ? acc_i64[ii] : (double)acc_i[ii]);
+            if (lane == 0) phi[wave * IPW + ii] = ix.ri(wave * IPW + ii) >= 0 ? v * out_scale : 0.0;
+        }
+        // the last chunk's barrier has passed: every wave is done with cb
+#pragma unroll
+        for (int kk = 0; kk < kKR; ++kk) s.kw[wave][lane + 64 * kk] = acck[kk];
+        __syncthreads();
+        for (int e = tid; e < kKT + JB; e += TPB) {
+            double v = 0.0;
+            if (e < kKT) {
+#pragma unroll
+                for (int w = 0; w < NW; ++w) v += s.kw[w][e];
+                phi[IB + JB + e] = ix.rk(e) >= 0 ? v * out_scale : 0.0;
+            } else {
+#pragma unroll
+                for (int w = 0; w < NW; ++w) v += s.pjw[w][e - kKT];
+                phi[IB + e - kKT] = ix.rj(e - kKT) >= 0 ? v * out_scale : 0.0;
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int ii = 0; ii < IPW; ++ii) {
         const double v = wave_sum(sizeof(T) == 4 ? acc_i64[ii] : (double)acc_i[ii]);
@@ -471,13 +525,15 @@ __device__ __forceinline__ void tile_unit(DirectLds<T, JB, Shape> &s, const doub
 }
 
 // One unit (I block a, J block b, K tile t) of the exhaustive sum over the
-// input order; ublk is the (i, j) table block of (a, b).
-template <typename T, typename TabPtr = const T *>
+// input order; ublk is the (i, j) table block of (a, b).  kOrdered: phi is
+// the unit's row (tile_unit).
+template <typename T, typename TabPtr = const T *, bool kOrdered = false>
 __device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__restrict__ x, int n,
                                             int a, int b, int t, TabPtr ublk, double scale,
                                             double out_scale, double *__restrict__ phi) {
     const BlockIndex<DirectLds<T>::IB, kB, DirectLds<T>::KT> ix(n, a, b, t);
-    tile_unit<T, kB, DirectShape<T>>(s, x, ix, ublk, scale, out_scale, phi);
+    tile_unit<T, kB, DirectShape<T>, BlockIndex<DirectLds<T>::IB, kB, DirectLds<T>::KT>, TabPtr,
+              kOrdered>(s, x, ix, ublk, scale, out_scale, phi);
 }
 
 }  // namespace

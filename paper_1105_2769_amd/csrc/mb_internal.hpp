@@ -93,6 +93,13 @@ size_t table_budget_bytes();
 mb_status direct_launch(const double *x, int64_t n, int prec, double scale, double *phi,
                         hipStream_t s, double r_fix = 0.0, int64_t *recomputed = nullptr);
 
+// The binary64 exhaustive sum with every addition in a fixed order
+// (mb_eval_direct_deterministic); phi is zeroed first.  Scratch per stripe
+// of J blocks (pair table and unit rows) stays within `budget` bytes where
+// one J block allows.
+mb_status direct_launch_ordered(const double *x, int64_t n, double *phi, size_t budget,
+                                hipStream_t s);
+
 // The exhaustive sum as mb_eval_direct_unchecked, with its scratch in the
 // library's static device array (no allocation); n <= kNoAllocMaxN.
 constexpr int64_t kNoAllocMaxN = 1024;

@@ -40,6 +40,9 @@ def test_invalid_arguments_no_device():
     assert lib.mb_eval_direct(None, 5, 7, None, None) == 1
     assert b"precision" in lib.mb_last_error() or b"null" in lib.mb_last_error()
     assert lib.mb_eval_direct(None, 0, 0, None, None) == 0
+    assert lib.mb_eval_direct_deterministic(None, -1, None, 0, None) == 1
+    assert lib.mb_eval_direct_deterministic(None, 5, None, 0, None) == 1
+    assert lib.mb_eval_direct_deterministic(None, 0, None, 0, None) == 0
     assert lib.mb_version() >= 100
 
 
