@@ -39,7 +39,8 @@ typedef enum {
     MB_ERR_DEGENERATE = 2,  /* two coincident points: phi is undefined          */
     MB_ERR_OOM = 3,         /* device allocation failed or budget exceeded      */
     MB_ERR_DEVICE = 4,      /* a HIP call failed; see mb_last_error()           */
-    MB_ERR_UNSUPPORTED = 5  /* request outside what the library implements      */
+    MB_ERR_UNSUPPORTED = 5, /* request outside what the library implements      */
+    MB_ERR_CANCELLED = 6    /* serving: request cancelled or timed out          */
 } mb_status;
 
 /* Arithmetic of the exhaustive (direct) sum and of the tree's base cases. */
@@ -54,6 +55,23 @@ const char *mb_last_error(void);
 
 /* Library version as major * 10000 + minor * 100 + patch. */
 int32_t mb_version(void);
+
+/*
+ * Return cached device memory to the device.  Every evaluation takes its
+ * scratch (pair-term tables, work lists, unit rows) from the current
+ * device's default memory pool by stream-ordered allocation, and the pool
+ * keeps the freed blocks for later calls (its release threshold is set to
+ * unlimited on first use), so repeated calls do not allocate again.
+ * mb_trim waits for `stream` (the work of this library enqueued there,
+ * frees included, has then run), then releases every block of that pool
+ * that no allocation holds.  Memory held by live trees (mb_build_kdtree),
+ * servers (mb_server_create) and the static array of
+ * mb_eval_direct_noalloc is not touched.
+ *   released : host pointer or NULL; receives the pool's reserved bytes
+ *              before the trim minus those after it.
+ * MB_ERR_DEVICE if a HIP call fails.
+ */
+mb_status mb_trim(void *stream, int64_t *released);
 
 /*
  * Exhaustive Phi(x_i) for all N points (the naive O(N^3) algorithm that the
@@ -397,6 +415,7 @@ typedef struct {
     double triples;                        /* sum of C(N, 3) of completed ones   */
     double busy_ms;                        /* wall time with units outstanding on the device */
     double stage_ms, finalize_ms;          /* host time staging / finishing requests */
+    int64_t cancelled;                     /* cancelled or timed out (also in failed) */
 } mb_server_stats;
 
 /*
@@ -439,6 +458,26 @@ mb_status mb_server_wait(void *srv, int64_t req_id, int32_t timeout_ms, int32_t 
 
 /* Seconds from submission to completion of a finished request. */
 mb_status mb_server_latency(void *srv, int64_t req_id, double *seconds);
+
+/*
+ * Stop a request.  One that has not finished ends with MB_ERR_CANCELLED
+ * (poll and wait report it like any other error): a queued request leaves
+ * the queue; one being staged is dropped when its staging work has landed;
+ * a running one hands out no more work units, and its device memory and
+ * slot return once the units already published have run.  A request whose
+ * last unit has run (its result is being copied back) completes normally.
+ * The server's thread carries the cancellation out shortly after the call.
+ * MB_OK for any known id, finished or not; unknown id: MB_ERR_INVALID.
+ */
+mb_status mb_server_cancel(void *srv, int64_t req_id);
+
+/*
+ * Time limit for requests submitted after the call: a request not finished
+ * timeout_ms milliseconds after its submission is cancelled as by
+ * mb_server_cancel (MB_ERR_CANCELLED, message "timed out after ... ms").
+ * timeout_ms <= 0: no limit (the default).
+ */
+mb_status mb_server_set_timeout(void *srv, int32_t timeout_ms);
 
 /* Counters of the server so far (host struct). */
 mb_status mb_server_stats_get(void *srv, mb_server_stats *out);

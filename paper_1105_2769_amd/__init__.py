@@ -6,8 +6,8 @@ memory and streams only.
 """
 from ._lib import (KdTree, MBError, Server, eval_direct, eval_direct_deterministic,  # noqa: F401
                    eval_factorized, eval_multitree, farfield_eval, lib, mt_params,
-                   normal_quantile, validate)
+                   normal_quantile, trim, validate)
 
 __all__ = ["MBError", "KdTree", "Server", "eval_direct", "eval_direct_deterministic",
            "eval_factorized", "eval_multitree", "farfield_eval", "mt_params", "normal_quantile",
-           "validate", "lib"]
+           "trim", "validate", "lib"]

@@ -21,6 +21,7 @@ STATUS_NAMES = {
     3: "MB_ERR_OOM",
     4: "MB_ERR_DEVICE",
     5: "MB_ERR_UNSUPPORTED",
+    6: "MB_ERR_CANCELLED",
 }
 PREC = {"fp64": 0, "fp32c": 1}
 BOUND = {"signed": 0, "two_sided": 1}
@@ -75,7 +76,8 @@ class ServerStats(ctypes.Structure):
                  "mixed_slices", "points_fp64", "peak_reserved")] + \
                [("peak_active", ctypes.c_int32), ("drain_launches", ctypes.c_int32),
                 ("triples", ctypes.c_double), ("busy_ms", ctypes.c_double),
-                ("stage_ms", ctypes.c_double), ("finalize_ms", ctypes.c_double)]
+                ("stage_ms", ctypes.c_double), ("finalize_ms", ctypes.c_double),
+                ("cancelled", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "pad"}
@@ -91,6 +93,7 @@ SIGNATURES = {
     "mb_eval_direct_unchecked": (_c_i32, [_c_vp, _c_i64, _c_i32, _c_vp, _c_vp]),
     "mb_eval_direct_noalloc": (_c_i32, [_c_vp, _c_i64, _c_i32, _c_vp, _c_vp]),
     "mb_eval_direct_deterministic": (_c_i32, [_c_vp, _c_i64, _c_vp, _c_i64, _c_vp]),
+    "mb_trim": (_c_i32, [_c_vp, ctypes.POINTER(_c_i64)]),
     "mb_build_kdtree": (_c_i32, [_c_vp, _c_i64, _c_i32, _c_vp, ctypes.POINTER(_c_vp)]),
     "mb_free_kdtree": (_c_i32, [_c_vp]),
     "mb_kdtree_info": (_c_i32, [_c_vp, ctypes.POINTER(_c_i64), ctypes.POINTER(_c_i32),
@@ -111,6 +114,8 @@ SIGNATURES = {
     "mb_server_latency": (_c_i32, [_c_vp, _c_i64, ctypes.POINTER(_c_dbl)]),
     "mb_server_stats_get": (_c_i32, [_c_vp, ctypes.POINTER(ServerStats)]),
     "mb_server_set_slice_units": (_c_i32, [_c_vp, _c_i64]),
+    "mb_server_cancel": (_c_i32, [_c_vp, _c_i64]),
+    "mb_server_set_timeout": (_c_i32, [_c_vp, _c_i32]),
     "mb_server_destroy": (_c_i32, [_c_vp]),
     "mb_struct_size": (_c_i64, [ctypes.c_char_p]),
 }
@@ -150,6 +155,17 @@ def _points(x):
     if x.dtype != torch.float64 or x.dim() != 2 or x.shape[1] != 3:
         raise TypeError("x must be float64 with shape (N, 3)")
     return x.contiguous()
+
+
+def trim(device=None) -> int:
+    """Release the library's cached device memory on the current device
+    after the current stream's work (mb_trim); returns the bytes released."""
+    import torch
+
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+    released = _c_i64()
+    check(lib().mb_trim(_c_vp(torch.cuda.current_stream(dev).cuda_stream), ctypes.byref(released)))
+    return released.value
 
 
 def validate(x) -> tuple[float, bool, tuple]:
@@ -363,6 +379,12 @@ class Server:
 
     def set_slice_units(self, units: int) -> None:
         check(lib().mb_server_set_slice_units(self._srv, int(units)))
+
+    def cancel(self, rid: int) -> None:
+        check(lib().mb_server_cancel(self._srv, int(rid)))
+
+    def set_timeout(self, timeout_ms: int) -> None:
+        check(lib().mb_server_set_timeout(self._srv, int(timeout_ms)))
 
     def close(self) -> None:
         if self._srv:

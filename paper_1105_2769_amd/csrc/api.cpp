@@ -102,6 +102,22 @@ const char *mb_last_error(void) { return last_error_cstr(); }
 
 int32_t mb_version(void) { return 100; }
 
+mb_status mb_trim(void *stream, int64_t *released) {
+    clear_error();
+    if (released) *released = 0;
+    MB_HIP(hipStreamSynchronize((hipStream_t)stream));
+    int dev = 0;
+    MB_HIP(hipGetDevice(&dev));
+    hipMemPool_t pool;
+    MB_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+    uint64_t before = 0, after = 0;
+    MB_HIP(hipMemPoolGetAttribute(pool, hipMemPoolAttrReservedMemCurrent, &before));
+    MB_HIP(hipMemPoolTrimTo(pool, 0));
+    MB_HIP(hipMemPoolGetAttribute(pool, hipMemPoolAttrReservedMemCurrent, &after));
+    if (released) *released = before > after ? (int64_t)(before - after) : 0;
+    return MB_OK;
+}
+
 mb_status mb_validate(const double *x, int64_t n, double *min_d2, int32_t *finite, double *bbox,
                       void *stream) {
     clear_error();

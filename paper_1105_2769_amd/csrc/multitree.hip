@@ -939,24 +939,6 @@ __global__ __launch_bounds__(kMcThreads, MB_MC_WAVES) void mc_kernel(
     }
 }
 
-#ifdef MB_MC_DEBUG
-__global__ void mc_debug_kernel(const Item *__restrict__ mc_list, NodeView nv,
-                                const MtCounters *__restrict__ ctr, unsigned long long *out) {
-    const unsigned long long n = ctr->n_mc;
-    for (unsigned long long w = blockIdx.x * 256ull + threadIdx.x; w < n; w += gridDim.x * 256ull) {
-        const Item it = mc_list[w];
-        const int64_t n1 = nv.end[it.p1] - nv.begin[it.p1], n2 = nv.end[it.p2] - nv.begin[it.p2],
-                      n3 = nv.end[it.p3] - nv.begin[it.p3];
-        const Roles r = roles_of(it.p1, it.p2, it.p3, n1, n2, n3);
-        unsigned long long tot = 0;
-        for (int q = 0; q < r.n_roles; ++q) tot += nv.end[r.node[q]] - nv.begin[r.node[q]];
-        atomicAdd(&out[0], tot);
-        atomicMax(&out[1], tot);
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[2] = n;
-}
-#endif
-
 // 3. Exhaustive base cases (MTPotentialBase) through the tile code of the
 // exhaustive sum.  A leaf triple (P1, P2, P3) holds the particle triples
 // i in P1, j in P2, k in P3 with depth-first ranks i < j < k, so it is a
@@ -1697,19 +1679,6 @@ mb_status multitree_run(const DeviceTree *t, const MtParams &prm, double *phi, i
         phase_ms[0] += ms[0];
         phase_ms[1] += ms[1];
         phase_ms[2] += ms[2];
-#ifdef MB_MC_DEBUG
-        {
-            static unsigned long long *dbg = nullptr;
-            if (!dbg) (void)hipMalloc(&dbg, 64);
-            (void)hipMemsetAsync(dbg, 0, 64, s);
-            mc_debug_kernel<<<1024, 256, 0, s>>>(mc_list, nv, ctr, dbg);
-            unsigned long long h[3];
-            (void)hipMemcpy(h, dbg, sizeof h, hipMemcpyDeviceToHost);
-            if (ms[1] > 0.5)
-                fprintf(stderr, "mcdbg B=%d n_mc=%llu P=%llu maxP=%llu mc_ms=%.3f\n", B, h[2], h[0],
-                        h[1], ms[1]);
-        }
-#endif
         // units beyond the first batch (their credits reach the statistics
         // one round later, which only delays prunes)
         const unsigned long long n_units_max = std::max(n_units[0], n_units[1]);

@@ -355,6 +355,8 @@ struct Request {
     UnitMap um;
     int64_t units = 0, keep = 0;  // from staging, applied once the tables are built
     double *pin_x = nullptr, *pin_phi = nullptr;  // pinned copies of the points and Phi
+    bool cancel = false;     // cancelled; dropped when its device work has landed
+    std::string cancel_msg;
 };
 
 class Server {
@@ -534,6 +536,24 @@ public:
         *out = stats_;
     }
 
+    // The scheduler thread carries the cancellation out (cancel_one).
+    mb_status cancel(int64_t id) {
+        std::lock_guard<std::mutex> g(mu_);
+        auto it = reqs_.find(id);
+        if (it == reqs_.end()) return fail(MB_ERR_INVALID, "unknown request id");
+        if (!it->second->done) {
+            cancels_.emplace_back(id, "cancelled");
+            cv_work_.notify_all();
+        }
+        return MB_OK;
+    }
+
+    mb_status set_timeout(int32_t ms) {
+        std::lock_guard<std::mutex> g(mu_);
+        timeout_ms_ = ms > 0 ? ms : 0;
+        return MB_OK;
+    }
+
     mb_status set_slice_units(int64_t u) {
         if (u < 1) return fail(MB_ERR_INVALID, "slice_units < 1");
         std::lock_guard<std::mutex> g(mu_);
@@ -582,6 +602,7 @@ private:
             stats_.triples += n * (n - 1) * (n - 2) / 6.0;
         } else {
             stats_.failed += 1;
+            if (st == MB_ERR_CANCELLED) stats_.cancelled += 1;
         }
         std::vector<double>().swap(r.x);
         cv_done_.notify_all();
@@ -863,6 +884,26 @@ private:
         return MB_OK;
     }
 
+    // A cancellation or time-out, in whatever state the request is.
+    void cancel_one(int64_t id, const std::string &msg) {
+        Request &r = req(id);
+        if (r.done || r.cancel) return;
+        switch (sched_.cancel(id)) {
+        case serve::Cancel::Removed:  // still queued: holds nothing
+            complete(r, MB_ERR_CANCELLED, msg);
+            break;
+        case serve::Cancel::Finished:  // none of its units is on the device
+            drop(id, MB_ERR_CANCELLED, msg);
+            break;
+        case serve::Cancel::Later:  // staging, or units still to run
+            r.cancel = true;
+            r.cancel_msg = msg;
+            break;
+        case serve::Cancel::Ignored:  // its result is being copied back
+            break;
+        }
+    }
+
     void drop(int64_t id, mb_status st, const std::string &msg) {
         Request &r = req(id);
         if (r.chunk) (void)hipFreeAsync(r.chunk, as_);
@@ -880,9 +921,25 @@ private:
                 sched_.set_slice_units(slice_request_);
                 slice_request_ = 0;
             }
-            for (int64_t id : inbox_) sched_.enqueue(id, footprint(reqs_.at(id)->n));
+            for (int64_t id : inbox_) {
+                sched_.enqueue(id, footprint(reqs_.at(id)->n));
+                if (timeout_ms_ > 0)
+                    deadlines_.push_back(Deadline{reqs_.at(id)->t_submit + 1e-3 * timeout_ms_, id,
+                                                  timeout_ms_});
+            }
             inbox_.clear();
+            cancel_work_.swap(cancels_);
         }
+        // time-outs (one limit at a time, so deadlines come in submission
+        // order), then cancellations
+        for (const double t = now_s(); !deadlines_.empty() && deadlines_.front().t <= t;) {
+            cancel_work_.emplace_back(deadlines_.front().id, "timed out after " +
+                                                            std::to_string(deadlines_.front().ms) +
+                                                            " ms");
+            deadlines_.pop_front();
+        }
+        for (const auto &c : cancel_work_) cancel_one(c.first, c.second);
+        cancel_work_.clear();
         {  // wall time with units outstanding on the device
             const double t = now_s();
             if (book_.outstanding() > 0 && t_last_ > 0.0) {
@@ -898,8 +955,13 @@ private:
         // 2. finished requests: enqueue their repairs and copies
         const double t0 = now_s();
         for (int64_t id : finished) {
+            Request &r = req(id);
+            if (r.cancel) {  // its handed-out units have run
+                drop(id, MB_ERR_CANCELLED, r.cancel_msg);
+                continue;
+            }
             const int slot = sched_.slot_of(id);
-            if ((st = finish_begin(req(id), slot)) != MB_OK) return st;
+            if ((st = finish_begin(r, slot)) != MB_OK) return st;
             finishing_.push_back(id);
         }
         finished.clear();
@@ -940,6 +1002,10 @@ private:
             MB_HIP(e);
             validating_.erase(validating_.begin() + (long)q);
             Request &r = req(id);
+            if (r.cancel) {
+                drop(id, MB_ERR_CANCELLED, r.cancel_msg);
+                continue;
+            }
             std::string why;
             st = stage_end(r, slot, r.units, r.keep, why);
             if (st == MB_ERR_OOM) {
@@ -966,6 +1032,10 @@ private:
             MB_HIP(e);
             staging_.erase(staging_.begin() + (long)q);
             Request &r = req(id);
+            if (r.cancel) {
+                drop(id, MB_ERR_CANCELLED, r.cancel_msg);
+                continue;
+            }
             hdesc_[slot] = desc_host_[slot];  // copied ahead of the request's items
             MB_HIP(hipMemcpyAsync(d_desc_ + slot, hdesc_ + slot, sizeof(ServeDesc),
                                   hipMemcpyHostToDevice, ps_));
@@ -1061,6 +1131,13 @@ private:
     SlotHost *slot_host_ = nullptr;
     std::vector<hipEvent_t> slot_ev_;
     std::vector<int64_t> validating_, staging_, finishing_;
+    struct Deadline {
+        double t;
+        int64_t id;
+        int32_t ms;
+    };
+    std::deque<Deadline> deadlines_;                             // scheduler thread only
+    std::vector<std::pair<int64_t, std::string>> cancel_work_;  // scheduler thread only
     std::vector<ServeDesc> desc_host_;  // per slot, written at staging
     PinnedPool pinned_;                 // scheduler thread only
     std::thread thread_;
@@ -1069,6 +1146,8 @@ private:
     std::condition_variable cv_work_, cv_done_;
     std::map<int64_t, std::unique_ptr<Request>> reqs_;
     std::vector<int64_t> inbox_;
+    std::vector<std::pair<int64_t, std::string>> cancels_;
+    int32_t timeout_ms_ = 0;
     int64_t next_id_ = 0;
     int64_t slice_request_ = 0;
     bool stop_ = false, broken_ = false;
@@ -1126,6 +1205,18 @@ mb_status mb_server_stats_get(void *srv, mb_server_stats *out) {
     if (!srv || !out) return fail(MB_ERR_INVALID, "null argument");
     static_cast<Server *>(srv)->get_stats(out);
     return MB_OK;
+}
+
+mb_status mb_server_cancel(void *srv, int64_t req_id) {
+    clear_error();
+    if (!srv) return fail(MB_ERR_INVALID, "null server");
+    return static_cast<Server *>(srv)->cancel(req_id);
+}
+
+mb_status mb_server_set_timeout(void *srv, int32_t timeout_ms) {
+    clear_error();
+    if (!srv) return fail(MB_ERR_INVALID, "null server");
+    return static_cast<Server *>(srv)->set_timeout(timeout_ms);
 }
 
 mb_status mb_server_set_slice_units(void *srv, int64_t units) {

@@ -13,6 +13,11 @@
 //   Finished  every unit's slice has finished: the executor copies the result
 //             back and calls release(), which frees the slot and the bytes.
 //
+// Cancellation (cancel()) takes a Pending request out of the queue, and makes
+// a Running one Draining with the units handed out so far as its whole work,
+// so it reaches Finished once those have run; the executor then releases it
+// without a result.
+//
 // Slices.  A slice is one launch of the drain kernel over at most
 // `slice_units` units.  Requests fill it in order of least remaining work
 // (fewest units left to hand out), so a short request that arrives while a
@@ -29,6 +34,13 @@ namespace mb {
 namespace serve {
 
 enum class State { Pending, Admitted, Running, Draining, Finished };
+
+// What cancel() did: Removed - a Pending request left the queue and the
+// scheduler (it holds nothing); Finished - a Running request has no unit left
+// on the device: release it now; Later - it finishes (Admitted: the executor
+// drops it when its staging lands; Running or Draining: slice_done reports it
+// once its handed-out units have run); Ignored - unknown, or already Finished.
+enum class Cancel { Removed, Finished, Later, Ignored };
 
 struct Range {
     int64_t id;
@@ -112,6 +124,32 @@ public:
 
     // The request needs no device work (an error, or n < 3).
     void finish_now(int64_t id) { reqs_.at(id).state = State::Finished; }
+
+    Cancel cancel(int64_t id) {
+        auto it = reqs_.find(id);
+        if (it == reqs_.end()) return Cancel::Ignored;
+        Req &r = it->second;
+        switch (r.state) {
+        case State::Pending:
+            fifo_.erase(std::find(fifo_.begin(), fifo_.end(), id));
+            reqs_.erase(it);
+            return Cancel::Removed;
+        case State::Running:
+            r.units = r.issued;
+            if (r.in_flight == 0) {  // every handed-out unit has run
+                r.state = State::Finished;
+                return Cancel::Finished;
+            }
+            r.state = State::Draining;
+            return Cancel::Later;
+        case State::Admitted:
+        case State::Draining:
+            return Cancel::Later;
+        case State::Finished:
+            break;
+        }
+        return Cancel::Ignored;
+    }
 
     Slice next_slice() {
         Slice sl;

@@ -1,10 +1,12 @@
 // CPU check of the serving scheduler with a fake executor: random arrivals,
-// sizes and slice limits; every step checks the invariants the device side
-// relies on.  Built and run by test_serve_sched.py (host compiler only).
+// sizes, slice limits, slices that stay in flight for a while, and
+// cancellations in every state; every step checks the invariants the device
+// side relies on.  Built and run by test_serve_sched.py (host compiler only).
 #include "serve_sched.hpp"
 
 #include <cstdio>
 #include <cstdlib>
+#include <deque>
 #include <random>
 #include <set>
 
@@ -28,14 +30,24 @@ int main(int argc, char **argv) {
         int64_t reserve, keep, units;
         std::vector<char> seen;  // each unit issued once
         bool admitted = false, started = false, finished = false, released = false;
+        bool cancel_marked = false, cancelled = false;
     };
     std::vector<Rec> recs;
     std::set<int> used_slots;
     std::vector<int64_t> admit_order, finish_order;
-    int64_t next_id = 0, ticks = 0, degenerate = 0;
+    int64_t next_id = 0, ticks = 0, degenerate = 0, cancelled = 0;
     const int n_req = 300;
     std::vector<int64_t> admitted_not_started;
-    while ((int64_t)finish_order.size() + degenerate < n_req || next_id < n_req) {
+    std::deque<Slice> inflight;
+    // the executor releases a request exactly once
+    auto release = [&](int64_t id) {
+        Rec &r = recs[id];
+        CHECK(!r.released);
+        used_slots.erase(s.slot_of(id));
+        s.release(id);
+        r.released = true;
+    };
+    while ((int64_t)finish_order.size() + degenerate + cancelled < n_req || next_id < n_req) {
         CHECK(++ticks < 1000000);
         // arrivals
         const int arrive = (int)(g() % 3);
@@ -55,7 +67,10 @@ int main(int argc, char **argv) {
         for (int64_t id : s.admit()) {
             CHECK(!recs[id].admitted);
             recs[id].admitted = true;
-            CHECK(admit_order.empty() || id == admit_order.back() + 1);
+            // arrival order: the requests skipped left the queue by cancellation
+            for (int64_t q = admit_order.empty() ? 0 : admit_order.back() + 1; q < id; ++q)
+                CHECK(recs[q].cancelled && !recs[q].admitted);
+            CHECK(admit_order.empty() || id > admit_order.back());
             admit_order.push_back(id);
             const int slot = s.slot_of(id);
             CHECK(slot >= 0 && slot < slots);
@@ -73,11 +88,13 @@ int main(int argc, char **argv) {
                 continue;
             }
             Rec &r = recs[id];
-            if (r.units == 0) {
+            if (r.cancel_marked) {  // cancelled while staging: dropped
+                release(id);
+                r.cancelled = true;
+                ++cancelled;
+            } else if (r.units == 0) {
                 s.finish_now(id);
-                used_slots.erase(s.slot_of(id));
-                s.release(id);
-                r.released = true;
+                release(id);
                 ++degenerate;
             } else {
                 s.start(id, r.units, r.keep);
@@ -96,7 +113,7 @@ int main(int argc, char **argv) {
             for (int64_t other : ids_in_slice) CHECK(other != rg.id);
             ids_in_slice.push_back(rg.id);
             Rec &r = recs[rg.id];
-            CHECK(r.started && !r.finished);
+            CHECK(r.started && !r.finished && !r.cancel_marked);
             CHECK(rg.slot == s.slot_of(rg.id));
             CHECK(rg.u0 < rg.u1 && rg.u1 <= r.units);
             for (int64_t u = rg.u0; u < rg.u1; ++u) {
@@ -105,26 +122,66 @@ int main(int argc, char **argv) {
             }
             (void)prev_left;
         }
-        for (int64_t id : s.slice_done(sl)) {
+        if (!sl.empty()) inflight.push_back(sl);
+        // slices finish in order, up to three in flight
+        while (!inflight.empty() && (inflight.size() > 3 || g() % 2)) {
+            for (int64_t id : s.slice_done(inflight.front())) {
+                Rec &r = recs[id];
+                CHECK(!r.finished);
+                r.finished = true;
+                if (r.cancel_marked) {  // its handed-out units have run
+                    r.cancelled = true;
+                    ++cancelled;
+                } else {
+                    for (char c : r.seen) CHECK(c);
+                    finish_order.push_back(id);
+                }
+                release(id);
+            }
+            inflight.pop_front();
+        }
+        // a cancellation of a random request, in whatever state it is
+        if (next_id > 0 && g() % 6 == 0) {
+            const int64_t id = (int64_t)(g() % (uint64_t)next_id);
             Rec &r = recs[id];
-            for (char c : r.seen) CHECK(c);
-            CHECK(!r.finished);
-            r.finished = true;
-            finish_order.push_back(id);
-            used_slots.erase(s.slot_of(id));
-            s.release(id);
-            r.released = true;
+            const Cancel c = s.cancel(id);
+            switch (c) {
+            case Cancel::Removed:
+                CHECK(!r.admitted && !r.released);
+                CHECK(!s.known(id));
+                r.released = r.cancelled = true;
+                ++cancelled;
+                break;
+            case Cancel::Finished:
+                CHECK(r.started && !r.finished && !r.cancel_marked);
+                for (const Slice &q : inflight)
+                    for (const Range &rg : q.ranges) CHECK(rg.id != id);
+                r.finished = r.cancelled = true;
+                ++cancelled;
+                release(id);
+                break;
+            case Cancel::Later:
+                CHECK(r.admitted && !r.released);
+                r.cancel_marked = true;
+                break;
+            case Cancel::Ignored:
+                CHECK(r.released);
+                break;
+            }
         }
     }
+    CHECK(inflight.empty());
     for (const Rec &r : recs) {
         CHECK(r.released);
-        for (char c : r.seen) CHECK(c);
+        if (!r.cancelled)
+            for (char c : r.seen) CHECK(c);
     }
     CHECK(s.idle());
     CHECK(s.reserved() == 0);
     CHECK(s.peak_reserved() <= budget);
-    std::printf("OK seed=%u slots=%d finished=%zu degenerate=%lld ticks=%lld peak=%lld\n", seed, slots,
-                finish_order.size(), (long long)degenerate, (long long)ticks,
-                (long long)s.peak_reserved());
+    CHECK(cancelled > 0);
+    std::printf("OK seed=%u slots=%d finished=%zu degenerate=%lld cancelled=%lld ticks=%lld peak=%lld\n",
+                seed, slots, finish_order.size(), (long long)degenerate, (long long)cancelled,
+                (long long)ticks, (long long)s.peak_reserved());
     return 0;
 }

@@ -91,6 +91,8 @@ def test_server_bad_arguments_no_device():
     assert lib.mb_server_poll(None, 0, None, ctypes.byref(done)) == 1
     assert lib.mb_server_wait(None, 0, 0, None) == 1
     assert lib.mb_server_set_slice_units(None, 4) == 1
+    assert lib.mb_server_cancel(None, 0) == 1
+    assert lib.mb_server_set_timeout(None, 10) == 1
     assert lib.mb_server_destroy(None) == 0
 
 
