@@ -391,10 +391,13 @@ double mb_normal_quantile(double alpha_half);
  *     until it is released, whichever table validation selects;
  *   - continuous batching: the work units (block triples) of all admitted
  *     requests are drained together by one persistent kernel whose
- *     workgroups take (request, unit) items from a ring in pinned host
- *     memory; the server thread publishes them in slices of a bounded
- *     number of units, requests with the fewest units left first.  The
- *     kernel stays resident while work arrives and exits after all its
+ *     workgroups take (request, unit) items from a ring in coherent pinned
+ *     host memory, which the server thread writes directly, in slices of a
+ *     bounded number of units, requests with the fewest units left first
+ *     (MB_SERVE_TRACE in the environment: a progress line every 2 s on
+ *     stderr).  The kernel is launched cooperatively (all its
+ *     workgroups resident at once, on a hardware queue no other stream
+ *     shares), stays resident while work arrives and exits after all its
  *     workgroups have been idle for 20 ms at once (it is launched again
  *     when work arrives); it leaves 32 CUs free for the staging and
  *     finishing kernels of requests;

@@ -27,6 +27,8 @@
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -48,9 +50,16 @@ struct ServeDesc {
     int32_t f64, pad;  // tile type: binary64 if nonzero
 };
 
+// A work item: the slot word (slot in the low kSlotBits bits, the slot's
+// generation above them, bumped for each request the slot holds) and the
+// unit's I block, J block and K tile.
 struct ServeItem {
     int32_t slot, a, b, t;
 };
+static_assert(sizeof(ServeItem) == 16 && sizeof(ServeDesc) == 56, "8-byte words for system_load");
+constexpr int kSlotBits = 12;  // max_slots <= 4096
+constexpr int32_t kSlotMask = (1 << kSlotBits) - 1;
+constexpr uint32_t kGenMask = (1u << (31 - kSlotBits)) - 1;  // slot words stay >= 0
 
 // Load a small struct at a wave-uniform address and mark every word uniform,
 // so that pointers and sizes read from it live in SGPRs (the loop's atomics
@@ -68,18 +77,23 @@ __device__ __forceinline__ S uniform_load(const S *p) {
     return out;
 }
 
-// Control word of the drain ring in fine-grained pinned host memory: the
-// host writes it, the kernel reads it at system scope while it waits.
+// Control words of the drain ring.  They, the ring entries and the request
+// descriptors live in fine-grained (coherent) pinned host memory: the host
+// writes them with plain stores (the tail last, with release order), and the
+// kernel reads them at system scope over the host link while it runs.  Device
+// memory from hipMalloc is coarse-grained: a running kernel is guaranteed to
+// see what a copy wrote there only at a dispatch boundary, and a polled line
+// can keep being served stale from a cache.
 struct DrainCtl {
-    unsigned int stop;  // set at shutdown
-    unsigned int pad[15];
+    unsigned long long tail;  // items [0, tail) are published
+    unsigned int stop;        // set at shutdown
+    unsigned int pad[13];
 };
 
-// The drain ring's device side.  The host writes tail (and the ring entries
-// and descriptors before it) by copies on its own stream; the kernel reads
-// them with system-scope loads, which do not hit stale cache lines.
+// The drain ring's device side: the ticket counter and the idle count,
+// device-scope atomics among the workgroups; the host reads head after the
+// kernel has ended.
 struct DrainDev {
-    unsigned long long tail;  // items [0, tail) are published
     unsigned long long head;  // next ticket; continues across launches
     unsigned int idle;        // workgroups waiting past the idle limit
     unsigned int closing;     // they all were at once: every workgroup exits
@@ -87,8 +101,8 @@ struct DrainDev {
 
 struct DrainArgs {
     const DrainCtl *ctl;
-    const ServeItem *ring;  // device memory, cap entries
-    const ServeDesc *desc;  // device memory, one per slot
+    const ServeItem *ring;  // coherent host memory, cap entries
+    const ServeDesc *desc;  // coherent host memory, one per slot
     unsigned int *done;     // host memory, cap flags
     DrainDev *dev;
     unsigned int cap, grid;
@@ -122,21 +136,24 @@ __device__ __forceinline__ unsigned long long uniform64(unsigned long long v) {
     return ((unsigned long long)hi << 32) | lo;
 }
 
-// A word-sized struct from host memory at system scope, made wave-uniform.
-// All its words are requested before the first is used, so the struct
-// costs one round trip over the host link, not one per word.
+// A struct of 8-byte words from host memory at system scope, made
+// wave-uniform: lane l of the wave loads word l, so the whole struct is one
+// vector load and one round trip over the host link.
 template <typename S>
-__device__ __forceinline__ S system_load(const S *p) {
-    static_assert(sizeof(S) % 4 == 0, "word-sized struct");
-    constexpr int W = sizeof(S) / 4;
-    const unsigned *w = reinterpret_cast<const unsigned *>(p);
-    unsigned v[W];
+__device__ __forceinline__ S system_load(const S *p, int lane) {
+    static_assert(sizeof(S) % 8 == 0 && sizeof(S) / 8 <= 64, "8-byte words, one per lane");
+    constexpr int W = sizeof(S) / 8;
+    const unsigned long long *w = reinterpret_cast<const unsigned long long *>(p);
+    unsigned long long v = 0;
+    if (lane < W) v = __hip_atomic_load(w + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    unsigned u[2 * W];
 #pragma unroll
-    for (int e = 0; e < W; ++e) v[e] = __hip_atomic_load(w + e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-#pragma unroll
-    for (int e = 0; e < W; ++e) v[e] = __builtin_amdgcn_readfirstlane(v[e]);
+    for (int e = 0; e < W; ++e) {
+        u[2 * e] = __builtin_amdgcn_readlane((unsigned)v, e);
+        u[2 * e + 1] = __builtin_amdgcn_readlane((unsigned)(v >> 32), e);
+    }
     S out;
-    __builtin_memcpy(&out, v, sizeof(S));
+    __builtin_memcpy(&out, u, sizeof(S));
     return out;
 }
 
@@ -181,6 +198,12 @@ __global__ __launch_bounds__(512, 1) void drain_kernel(DrainArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     constexpr unsigned long long kExit = ~0ull;
+    // wave 0: the largest tail read so far (the tail only grows), so that the
+    // host word is read over the link only when the ticket is past it; and
+    // the descriptor of the last item's slot word
+    unsigned long long seen = 0;
+    int32_t dkey = -1;
+    ServeDesc dcache{};
     for (;;) {
         if (wave == 0) {
             const unsigned long long tk =
@@ -188,10 +211,12 @@ __global__ __launch_bounds__(512, 1) void drain_kernel(DrainArgs a) {
             unsigned long long res = tk;
             const unsigned long long t0 = wall_clock64();
             bool counted = false;
+            int polls = 0;
             for (;;) {
-                const unsigned long long tail = uniform64(
-                    __hip_atomic_load(&a.dev->tail, kPollOrder, __HIP_MEMORY_SCOPE_SYSTEM));
-                if (tk < tail) {
+                if (tk >= seen)
+                    seen = uniform64(
+                        __hip_atomic_load(&a.ctl->tail, kPollOrder, __HIP_MEMORY_SCOPE_SYSTEM));
+                if (tk < seen) {
                     if (counted) atomicSub(&a.dev->idle, lane == 0 ? 1u : 0u);
                     break;
                 }
@@ -216,14 +241,27 @@ __global__ __launch_bounds__(512, 1) void drain_kernel(DrainArgs a) {
                     res = kExit;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(63);
+                // short pauses first, then about 25 us between reads of the
+                // host word, so that idle workgroups load the link little
+                if (polls < 16) {
+                    ++polls;
+                    __builtin_amdgcn_s_sleep(63);
+                } else {
+#pragma unroll
+                    for (int z = 0; z < 8; ++z) __builtin_amdgcn_s_sleep(127);
+                }
             }
             if (res != kExit) {
-                ServeItem it = system_load(a.ring + res % a.cap);
-                ServeDesc d{};
-                if (it.slot >= 0 && it.slot < a.n_slots) d = system_load(a.desc + it.slot);
+                ServeItem it = system_load(a.ring + res % a.cap, lane);
+                // the descriptor is read again only when the slot or its
+                // generation changes (a slot's next request has a new one)
+                const int slot = it.slot & kSlotMask;
+                if (it.slot >= 0 && slot < a.n_slots && it.slot != dkey) {
+                    dcache = system_load(a.desc + slot, lane);
+                    dkey = it.slot;
+                }
                 s_it = it;  // every lane of the wave writes the same value
-                s_d = d;
+                s_d = it.slot == dkey ? dcache : ServeDesc{};
             }
             s_tk = res;
         }
@@ -233,7 +271,7 @@ __global__ __launch_bounds__(512, 1) void drain_kernel(DrainArgs a) {
         const ServeItem it = uniform_load(&s_it);
         const ServeDesc d = uniform_load(&s_d);
         // an item outside its request's units is refused, not run
-        const bool ok = it.slot >= 0 && it.slot < a.n_slots &&
+        const bool ok = it.slot >= 0 && (it.slot & kSlotMask) < a.n_slots &&
                         (d.f64 ? item_in_range<double>(it, d) : item_in_range<float>(it, d));
         if (ok) {
             if (d.f64)
@@ -319,6 +357,7 @@ public:
         size_of_[p] = c;
         return p;
     }
+    size_t blocks() const { return blocks_.size(); }
     void put(void *p) {
         if (!p) return;
         auto it = size_of_.find(p);
@@ -372,7 +411,8 @@ public:
         int occ = 0;
         MB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, drain_kernel, 512, 0));
         // every workgroup must be resident at once (the idle rule counts all
-        // of them); kReserveCus CUs stay free for staging and finishing
+        // of them; the cooperative launch checks it); kReserveCus CUs stay
+        // free for staging and finishing
         grid_ = std::max(1, std::max(1, occ) * (cus - std::min(cus / 2, kReserveCus)));
         sched_.set_slice_units(std::min<int64_t>(8 * (int64_t)grid_, kMaxSliceUnits));
         int rate_khz = 0;
@@ -389,28 +429,22 @@ public:
         MB_HIP(hipStreamCreateWithFlags(&as_, hipStreamNonBlocking));
         MB_HIP(hipEventCreateWithFlags(&ev_k0_, hipEventDefault));
         MB_HIP(hipEventCreateWithFlags(&ev_k1_, hipEventDefault));
-        MB_HIP(hipStreamCreateWithFlags(&ps_, hipStreamNonBlocking));
-        // stop flag and done flags: fine-grained pinned host memory, written
-        // and read while the kernel runs; the ring's entries, descriptors and
-        // tail values: pinned sources of the copies to the device side
+        // control words, ring entries, descriptors and done flags:
+        // fine-grained pinned host memory, written and read while the kernel
+        // runs (see DrainCtl)
         MB_HIP(hipHostMalloc((void **)&ctl_, sizeof(DrainCtl), hipHostMallocCoherent));
         MB_HIP(hipHostMalloc((void **)&done_, sizeof(unsigned) * kRingCap, hipHostMallocCoherent));
-        MB_HIP(hipHostMalloc((void **)&ring_, sizeof(ServeItem) * kRingCap, hipHostMallocDefault));
-        MB_HIP(hipHostMalloc((void **)&hdesc_, sizeof(ServeDesc) * max_slots_, hipHostMallocDefault));
-        MB_HIP(hipHostMalloc((void **)&tail_src_, sizeof(unsigned long long) * kTailSlots,
-                             hipHostMallocDefault));
+        MB_HIP(hipHostMalloc((void **)&ring_, sizeof(ServeItem) * kRingCap, hipHostMallocCoherent));
+        MB_HIP(hipHostMalloc((void **)&hdesc_, sizeof(ServeDesc) * max_slots_,
+                             hipHostMallocCoherent));
         std::memset((void *)ctl_, 0, sizeof(DrainCtl));
         std::memset((void *)done_, 0, sizeof(unsigned) * kRingCap);
         std::memset((void *)hdesc_, 0, sizeof(ServeDesc) * max_slots_);
         MB_HIP(hipMalloc((void **)&ddev_, sizeof(DrainDev)));
         MB_HIP(hipMemset(ddev_, 0, sizeof(DrainDev)));
-        MB_HIP(hipMalloc((void **)&d_ring_, sizeof(ServeItem) * kRingCap));
-        MB_HIP(hipMalloc((void **)&d_desc_, sizeof(ServeDesc) * max_slots_));
-        MB_HIP(hipMemset(d_desc_, 0, sizeof(ServeDesc) * max_slots_));
-        tail_ev_.assign(kTailSlots, nullptr);
-        for (hipEvent_t &e : tail_ev_) MB_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         MB_HIP(hipDeviceSynchronize());
         desc_host_.assign(max_slots_, ServeDesc{});
+        gen_.assign(max_slots_, 0);
         MB_HIP(hipHostMalloc(&slot_host_, sizeof(SlotHost) * max_slots_, hipHostMallocDefault));
         std::memset(slot_host_, 0, sizeof(SlotHost) * max_slots_);
         slot_ev_.assign(max_slots_, nullptr);
@@ -432,18 +466,11 @@ public:
         }
         if (ev_k0_) (void)hipEventDestroy(ev_k0_);
         if (ev_k1_) (void)hipEventDestroy(ev_k1_);
-        if (ps_) (void)hipStreamSynchronize(ps_);
-        for (hipEvent_t e : tail_ev_)
-            if (e) (void)hipEventDestroy(e);
         if (ddev_) (void)hipFree(ddev_);
-        if (d_ring_) (void)hipFree(d_ring_);
-        if (d_desc_) (void)hipFree(d_desc_);
         if (ctl_) (void)hipHostFree((void *)ctl_);
         if (ring_) (void)hipHostFree((void *)ring_);
         if (done_) (void)hipHostFree((void *)done_);
         if (hdesc_) (void)hipHostFree((void *)hdesc_);
-        if (tail_src_) (void)hipHostFree((void *)tail_src_);
-        if (ps_) (void)hipStreamDestroy(ps_);
         for (hipEvent_t e : slot_ev_)
             if (e) (void)hipEventDestroy(e);
         if (slot_host_) (void)hipHostFree(slot_host_);
@@ -570,7 +597,6 @@ private:
     static constexpr int kReserveCus = MB_RESERVE_CUS;  // CUs the drain kernel leaves free
     static constexpr unsigned long long kIdleMs = 20;   // idle time before the kernel exits
     static constexpr unsigned long long kHardMs = 500;  // longest single wait
-    static constexpr int kTailSlots = 64;              // tail values in flight to the device
     static constexpr int kMaxStalled = 50;             // launches in a row that ran nothing
 
     // A slice published to the ring: its ranges and how many of its units
@@ -613,7 +639,10 @@ private:
     mb_status stage_begin(Request &r, int slot) {
         const int64_t n = r.n;
         const serve::ChunkLayout lay = serve::chunk_layout(n, kTab32, kTab64);
-        if (hipMallocAsync(&r.chunk, lay.total, as_) != hipSuccess) {
+        const double tm0 = now_s();
+        const hipError_t me = hipMallocAsync(&r.chunk, lay.total, as_);
+        tr_.malloc_ms += (now_s() - tm0) * 1e3;
+        if (me != hipSuccess) {
             r.chunk = nullptr;
             (void)hipGetLastError();
             return fail(MB_ERR_OOM,
@@ -625,7 +654,9 @@ private:
         r.dmag = reinterpret_cast<double *>(base + lay.mag);
         r.dtab = base + lay.tab;
         r.tab_bytes = lay.tab_bytes;
+        const double tp0 = now_s();
         r.pin_x = static_cast<double *>(pinned_.get(sizeof(double) * 3 * n));
+        tr_.pin_ms += (now_s() - tp0) * 1e3;
         if (!r.pin_x) return fail(MB_ERR_OOM, "pinned host allocation failed");
         std::memcpy(r.pin_x, r.x.data(), sizeof(double) * 3 * n);
         MB_HIP(hipMemcpyAsync(r.dx, r.pin_x, sizeof(double) * 3 * n, hipMemcpyHostToDevice, as_));
@@ -718,7 +749,7 @@ private:
                 Request &r = req(rg.id);
                 for (int64_t u = rg.u0; u < rg.u1; ++u) {
                     ServeItem it;
-                    it.slot = rg.slot;
+                    it.slot = rg.slot | (int32_t)(gen_[rg.slot] << kSlotBits);
                     r.um.decode(u, it.a, it.b, it.t);
                     const int64_t k = book_.push(Entry{sl.seq, it});
                     ring_[k % kRingCap] = it;
@@ -733,26 +764,15 @@ private:
             live_[seq] = Live{std::move(sl), units};
             any = true;
         }
-        return any ? send(t_sent_, book_.tail()) : MB_OK;
+        if (any) publish_tail();
+        return MB_OK;
     }
 
-    // Copy ring entries [from, to) to the device, then the new tail; one
-    // stream, so the entries land before the tail that publishes them.
-    mb_status send(int64_t from, int64_t to) {
-        for (int64_t k = from; k < to;) {
-            const int64_t e = k % kRingCap, len = std::min(to - k, kRingCap - e);
-            MB_HIP(hipMemcpyAsync(d_ring_ + e, ring_ + e, sizeof(ServeItem) * len,
-                                  hipMemcpyHostToDevice, ps_));
-            k += len;
-        }
-        const int q = (int)(tail_seq_++ % kTailSlots);
-        MB_HIP(hipEventSynchronize(tail_ev_[q]));  // its previous copy has long run
-        tail_src_[q] = (unsigned long long)to;
-        MB_HIP(hipMemcpyAsync(&ddev_->tail, tail_src_ + q, sizeof(unsigned long long),
-                              hipMemcpyHostToDevice, ps_));
-        MB_HIP(hipEventRecord(tail_ev_[q], ps_));
-        t_sent_ = to;
-        return MB_OK;
+    // Release the ring entries written so far to the kernel: a release store
+    // of the tail, after the entries (and the descriptors of their requests)
+    // in program order.
+    void publish_tail() {
+        __atomic_store_n(&ctl_->tail, (unsigned long long)book_.tail(), __ATOMIC_RELEASE);
     }
 
     // Consume the done flags the kernel has set; slices whose units have all
@@ -798,7 +818,9 @@ private:
             running_ = false;
             unsigned long long head = 0;
             MB_HIP(hipMemcpyAsync(&head, &ddev_->head, sizeof head, hipMemcpyDeviceToHost, cs_));
+            const double ts0 = now_s();
             MB_HIP(hipStreamSynchronize(cs_));
+            tr_.sync_ms += (now_s() - ts0) * 1e3;
             if ((st = collect(finished)) != MB_OK) return st;
             // a kernel that ended with work published before its launch and
             // ran none of it saw no items: after a run of such launches the
@@ -810,15 +832,15 @@ private:
             const int64_t again = book_.after_exit((int64_t)head);
             for (int64_t k = book_.tail() - again; k < book_.tail(); ++k)
                 ring_[k % kRingCap] = book_.payload(k).item;
-            if ((st = send(book_.tail() - again, book_.tail())) != MB_OK) return st;
+            publish_tail();
         }
         if (!running_ && book_.outstanding() > 0) {
             // the ticket counter continues; the idle count and latch restart
             MB_HIP(hipMemsetAsync(&ddev_->idle, 0, 2 * sizeof(unsigned), cs_));
             DrainArgs a;
             a.ctl = ctl_;
-            a.ring = d_ring_;
-            a.desc = d_desc_;
+            a.ring = ring_;
+            a.desc = hdesc_;
             a.done = done_;
             a.dev = ddev_;
             a.cap = (unsigned)kRingCap;
@@ -830,8 +852,14 @@ private:
             units_at_launch_ = units_done_;
             out_at_launch_ = book_.outstanding();
             MB_HIP(hipEventRecord(ev_k0_, cs_));
-            drain_kernel<<<(unsigned)grid_, 512, 0, cs_>>>(a);
-            MB_HIP(hipGetLastError());
+            // A cooperative launch: every workgroup is resident at once (the
+            // idle rule counts all of them), and the kernel runs from a
+            // hardware queue of its own.  Streams share hardware queues, and
+            // work on a stream whose queue a plain launch of the resident
+            // kernel held would wait until the kernel went idle.
+            void *args[] = {(void *)&a};
+            MB_HIP(hipLaunchCooperativeKernel((const void *)drain_kernel, dim3((unsigned)grid_),
+                                              dim3(512), args, 0, cs_));
             MB_HIP(hipEventRecord(ev_k1_, cs_));
             running_ = true;
             std::lock_guard<std::mutex> g(mu_);
@@ -844,7 +872,9 @@ private:
     // Phi into the slot's pinned buffer.  No wait.
     mb_status finish_begin(Request &r, int slot) {
         SlotHost &h = slot_host_[slot];
+        const double tp0 = now_s();
         r.pin_phi = static_cast<double *>(pinned_.get(sizeof(double) * (size_t)r.n));
+        tr_.pin_ms += (now_s() - tp0) * 1e3;
         if (!r.pin_phi) return fail(MB_ERR_OOM, "pinned host allocation failed");
         h.flagged = 0;
         if (r.prec == MB_FP32C) {
@@ -1036,9 +1066,8 @@ private:
                 drop(id, MB_ERR_CANCELLED, r.cancel_msg);
                 continue;
             }
-            hdesc_[slot] = desc_host_[slot];  // copied ahead of the request's items
-            MB_HIP(hipMemcpyAsync(d_desc_ + slot, hdesc_ + slot, sizeof(ServeDesc),
-                                  hipMemcpyHostToDevice, ps_));
+            gen_[slot] = (gen_[slot] + 1) & kGenMask;  // items carry the slot's new word
+            hdesc_[slot] = desc_host_[slot];          // written before the request's items
             sched_.start(id, r.units, r.keep);
         }
         {
@@ -1051,6 +1080,7 @@ private:
         if ((st = drain_lifecycle(finished)) != MB_OK) return st;
         idle = book_.outstanding() == 0 && !sched_.has_runnable() && finishing_.empty() &&
                validating_.empty() && staging_.empty() && finished.empty();
+        if (tr_.on) trace_line(idle);
         if (!idle) std::this_thread::sleep_for(std::chrono::microseconds(10));
         {
             std::lock_guard<std::mutex> g(mu_);
@@ -1058,6 +1088,32 @@ private:
             stats_.peak_active = sched_.peak_active();
         }
         return MB_OK;
+    }
+
+    // MB_SERVE_TRACE set: a line every 2 s on stderr with the queue depths and
+    // the host time spent in the calls that can wait for the device.
+    struct Trace {
+        bool on = std::getenv("MB_SERVE_TRACE") != nullptr;
+        double t0 = 0.0, last = 0.0;
+        double malloc_ms = 0.0, pin_ms = 0.0, sync_ms = 0.0;
+    } tr_;
+    void trace_line(bool idle) {
+        const double t = now_s();
+        if (tr_.t0 == 0.0) tr_.t0 = tr_.last = t;
+        if (t - tr_.last < 2.0) return;
+        tr_.last = t;
+        mb_server_stats st;
+        get_stats(&st);
+        std::fprintf(stderr,
+                     "[mb serve] %.1f s: submitted %lld done %lld failed %lld units %lld "
+                     "outstanding %lld launches %d running %d idle %d | validating %zu staging %zu "
+                     "finishing %zu slices %zu pinned blocks %zu | ms in malloc %.0f pinned %.0f "
+                     "kernel-end sync %.0f\n",
+                     t - tr_.t0, (long long)st.submitted, (long long)st.completed,
+                     (long long)st.failed, (long long)st.units, (long long)book_.outstanding(),
+                     st.drain_launches, (int)running_, (int)idle, validating_.size(),
+                     staging_.size(), finishing_.size(), live_.size(), pinned_.blocks(),
+                     tr_.malloc_ms, tr_.pin_ms, tr_.sync_ms);
     }
 
     void loop() {
@@ -1106,14 +1162,10 @@ private:
     int dev_ = 0, grid_ = 1;
     // the drain ring (host memory shared with the kernel) and the kernel's state
     DrainCtl *ctl_ = nullptr;
-    ServeItem *ring_ = nullptr, *d_ring_ = nullptr;
+    ServeItem *ring_ = nullptr;
     unsigned *done_ = nullptr;
-    ServeDesc *hdesc_ = nullptr, *d_desc_ = nullptr;
+    ServeDesc *hdesc_ = nullptr;
     DrainDev *ddev_ = nullptr;
-    unsigned long long *tail_src_ = nullptr;
-    std::vector<hipEvent_t> tail_ev_;
-    int64_t tail_seq_ = 0, t_sent_ = 0;
-    hipStream_t ps_ = nullptr;  // copies that publish ring entries
     int64_t units_done_ = 0, units_at_launch_ = 0, out_at_launch_ = 0;
     int stalled_ = 0;
     serve::RingBook<Entry> book_{kRingCap, 4096};
@@ -1139,6 +1191,7 @@ private:
     std::deque<Deadline> deadlines_;                             // scheduler thread only
     std::vector<std::pair<int64_t, std::string>> cancel_work_;  // scheduler thread only
     std::vector<ServeDesc> desc_host_;  // per slot, written at staging
+    std::vector<uint32_t> gen_;         // per slot: generation of its current request
     PinnedPool pinned_;                 // scheduler thread only
     std::thread thread_;
 
