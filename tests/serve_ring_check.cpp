@@ -4,8 +4,13 @@
 // idle rule ends the kernel, run the item, set its done flag - while the
 // main thread publishes the units of many requests in slices, consumes done
 // flags, and after each "kernel" ends republishes abandoned items and
-// launches the next one.  Checks: every unit runs exactly once, no flag
-// appears on an unpublished entry, and the book is empty at the end.
+// launches the next one.  Requests hold one of a few slots while they run;
+// a slot's descriptor is rewritten, and its generation bumped, for each
+// request it takes, and a workgroup re-reads a descriptor only when an
+// item's slot word (slot and generation) differs from the last one it read.
+// Checks: every unit runs exactly once and with its own request's
+// descriptor, no flag appears on an unpublished entry, and the book is empty
+// at the end.
 // Built and run by test_serve_ring.py under ThreadSanitizer and under
 // AddressSanitizer + UndefinedBehaviorSanitizer.
 #include "serve_ring.hpp"
@@ -23,7 +28,11 @@ using namespace mb::serve;
 struct Item {
     int req, unit;
     int64_t slice;
+    int32_t slot_word;  // slot | generation << kSlotBits
 };
+
+constexpr int kSlotBits = 12;
+constexpr int kMaxSlots = 5;
 
 struct Shared {
     // host-written, kernel-read
@@ -36,12 +45,18 @@ struct Shared {
     std::atomic<int> idle{0}, closing{0};
     // what ran
     std::vector<std::unique_ptr<std::atomic<int>[]>> runs;
+    // per slot: the descriptor (here the request it holds), written by the
+    // host before the request's first item is published
+    int desc[kMaxSlots] = {};
+    std::atomic<int> wrong_desc{0};
 };
 
 // One workgroup of the drain kernel.
 static void workgroup(Shared &sh, int grid, int64_t cap, int idle_spins, int hard_spins,
                       unsigned seed) {
     std::mt19937 rng(seed);
+    int32_t dkey = -1;  // slot word of the cached descriptor
+    int dcache = -1;
     for (;;) {
         const int64_t t = sh.head.fetch_add(1);
         int spins = 0;
@@ -63,13 +78,20 @@ static void workgroup(Shared &sh, int grid, int64_t cap, int idle_spins, int har
         }
         if (!run) return;  // exits holding ticket t
         const Item it = sh.ring[t % cap];
+        if (it.slot_word != dkey) {
+            dcache = sh.desc[it.slot_word & ((1 << kSlotBits) - 1)];
+            dkey = it.slot_word;
+        }
+        if (dcache != it.req) sh.wrong_desc.fetch_add(1);
         sh.runs[it.req][it.unit].fetch_add(1);
         if (rng() % 8 == 0) std::this_thread::sleep_for(std::chrono::microseconds(rng() % 50));
         sh.done[t % cap].store(1, std::memory_order_release);
     }
 }
 
-int main() {
+// One run of the model with n_slots slots (1: consecutive requests share the
+// slot, so only the generation tells their descriptors apart).
+static int run(int n_slots) {
     const int64_t cap = 4096;
     const int grid = 6;
     std::mt19937 rng(12345);
@@ -87,7 +109,10 @@ int main() {
     }
 
     RingBook<Item> book(cap);
-    std::vector<int> issued(n_req, 0), finished_units(n_req, 0);
+    std::vector<int> issued(n_req, 0), finished_units(n_req, 0), slot_of(n_req, -1);
+    std::vector<int> free_slots;
+    for (int q = n_slots - 1; q >= 0; --q) free_slots.push_back(q);
+    uint32_t gen[kMaxSlots] = {};
     int next_req = 0, launches = 0;
     int64_t republished = 0;
     int64_t slice_seq = 0;
@@ -113,7 +138,9 @@ int main() {
         }
         return false;
     };
-    auto on_done = [&](const Item &it) { finished_units[it.req] += 1; };
+    auto on_done = [&](const Item &it) {
+        if (++finished_units[it.req] == units[it.req]) free_slots.push_back(slot_of[it.req]);
+    };
     int active_from = 0;
     for (int step = 0;; ++step) {
         // publish a slice of up to 64 units from the admitted requests
@@ -121,8 +148,17 @@ int main() {
         const int64_t before = book.tail();
         int64_t room = std::min<int64_t>(64, book.room() - 2 * grid);
         for (int r = active_from; r < next_req && room > 0; ++r) {
+            if (slot_of[r] < 0) {  // admit into a free slot: new generation, new descriptor
+                if (free_slots.empty()) continue;
+                const int q = free_slots.back();
+                free_slots.pop_back();
+                gen[q] = (gen[q] + 1) & 0x7FFFF;
+                sh.desc[q] = r;
+                slot_of[r] = q;
+            }
+            const int32_t word = slot_of[r] | (int32_t)(gen[slot_of[r]] << kSlotBits);
             while (issued[r] < units[r] && room > 0) {
-                const int64_t k = book.push(Item{r, issued[r]++, slice_seq});
+                const int64_t k = book.push(Item{r, issued[r]++, slice_seq, word});
                 sh.ring[k % cap] = book.payload(k);
                 --room;
             }
@@ -178,11 +214,21 @@ int main() {
         std::printf("FAIL: book not empty\n");
         return 1;
     }
+    if (sh.wrong_desc.load() != 0) {
+        std::printf("FAIL: %d units ran with another request's descriptor\n", sh.wrong_desc.load());
+        return 1;
+    }
     if (launches < 5) {
         std::printf("FAIL: only %d kernel launches: the relaunch path was not exercised\n", launches);
         return 1;
     }
-    std::printf("OK %ld units, %d launches, %ld items republished\n", checked, launches,
-                (long)republished);
+    std::printf("OK %d slots: %ld units, %d launches, %ld items republished\n", n_slots, checked,
+                launches, (long)republished);
+    return 0;
+}
+
+int main() {
+    for (int n_slots : {1, kMaxSlots})
+        if (run(n_slots) != 0) return 1;
     return 0;
 }

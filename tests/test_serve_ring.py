@@ -4,9 +4,12 @@ tests/serve_ring_check.cpp models the persistent drain kernel with host
 threads (tickets from a shared counter, bounded idle waits, a collective
 exit) against the host bookkeeping of csrc/serve_ring.hpp (publication,
 consumption of done flags, republication of abandoned items after a kernel
-ends, relaunch).  It checks that every unit of every request runs exactly
-once.  Built with the host compiler under ThreadSanitizer, then under
-AddressSanitizer and UndefinedBehaviorSanitizer.
+ends, relaunch), with requests in reused slots whose descriptors the workgroups
+cache by slot word (slot and generation).  It checks that every unit of
+every request runs exactly once and with its own request's descriptor, with
+one slot (consecutive requests share it) and with five.  Built with the host
+compiler under ThreadSanitizer, then under AddressSanitizer and
+UndefinedBehaviorSanitizer.
 """
 import os
 import shutil
