@@ -38,12 +38,13 @@ __global__ __launch_bounds__(DirectLds<T>::TPB, DirectShape<T>::MINB) void direc
     constexpr int IB = DirectLds<T>::IB;
     constexpr int W = IB + kB + DirectLds<T>::KT;
     __shared__ DirectLds<T> s;
+    __shared__ double pjl[DirectShape<T>::NW * DirectShape<T>::JC * 64];
     for (int64_t u = u_begin + blockIdx.x; u < u_end; u += gridDim.x) {
         int a, b, t;
         decode_unit(u, unit_off, nb, nt, DirectLds<T>::KR, a, b, t);
         direct_unit<T, const T *, true>(
             s, x, n, a, b, t, utab + ((int64_t)(b - b0) * na + a) * (IB * kB * kPairVals), 1.0,
-            1.0, rows + (u - u_begin) * W);
+            1.0, rows + (u - u_begin) * W, pjl);
     }
 }
 

@@ -114,9 +114,8 @@ struct DirectLds {
     static constexpr int KR = Shape::KR;
     static constexpr int KT = 64 * KR;                   // points per K tile
     static constexpr int XS = IB + JB + KT;
-    // the fixed-order mode's per-wave sums fit in the space they share
-    static constexpr bool kOrderedFits = Shape::NW * 8 <= kJC * (int)sizeof(T) &&
-                                         Shape::NW * JB <= kJC * 64;
+    // the fixed-order mode's per-wave Phi_k sums fit in the space they share
+    static constexpr bool kOrderedFits = Shape::NW * 8 <= kJC * (int)sizeof(T);
     static constexpr int kOW = kOrderedFits ? Shape::NW : 1;
     double xs[3][XS];                              // coordinates of the I, J blocks and K tile
     union {
@@ -125,10 +124,7 @@ struct DirectLds {
     };
     T cq[kJC][KT], co[kJC][KT];
     T cbb[Shape::kLdsBB ? kJC : 1][KT];            // their b^2 (kLdsBB)
-    union {
-        double pj[kJC][64];                        // Phi_j partials per (j, lane), all waves
-        double pjw[kOW][JB];                       // fixed order: Phi_j per (wave, j)
-    };
+    double pj[kJC][64];                            // Phi_j partials per (j, lane), all waves
     double pjacc[JB];                              // Phi_j of the unit
     double kacc[KT];                               // Phi_k of the unit
 };
@@ -259,10 +255,13 @@ __device__ __forceinline__ T tile_psi(T a, T g, T wg, T b, T bb, T ob) {
 // IB + JB + KT values: the I block's sums, then the J block's, then the K
 // tile's, times out_scale (empty slots get 0).  Adding the rows of all
 // units in a fixed order then gives a result independent of scheduling.
+// pjl (kOrdered only) is LDS for NW * JC * 64 Phi_j partials, one slot per
+// (wave, j, lane), in place of the atomic mode's shared adds.
 template <typename T, int JB, typename Shape, typename Ix, typename TabPtr, bool kOrdered = false>
 __device__ __forceinline__ void tile_unit(DirectLds<T, JB, Shape> &s, const double *__restrict__ x,
                                           const Ix &ix, TabPtr ublk, double scale,
-                                          double out_scale, double *__restrict__ phi) {
+                                          double out_scale, double *__restrict__ phi,
+                                          double *__restrict__ pjl = nullptr) {
     static_assert(!kOrdered || DirectLds<T, JB, Shape>::kOrderedFits,
                   "per-wave sums of the fixed-order mode fit in the LDS they reuse");
     constexpr int IPW = Shape::IPW;
@@ -411,8 +410,7 @@ __device__ __forceinline__ void tile_unit(DirectLds<T, JB, Shape> &s, const doub
                     acck[kk] = fma((double)o.cq[kk], (double)sk[kk], acck[kk]);
             }
             if constexpr (kOrdered) {
-                const double v = wave_sum((double)pj32);
-                if (lane == 0) s.pjw[wave][jc * kJC + jj] = v;
+                pjl[(wave * kJC + jj) * 64 + lane] = (double)pj32;
             } else {
                 atomicAdd(&s.pj[jj][lane], (double)pj32);
             }
@@ -462,19 +460,28 @@ __device__ __forceinline__ void tile_unit(DirectLds<T, JB, Shape> &s, const doub
             }
         }
         __syncthreads();
-        // Phi_j of the chunk: 16 rows of 64 slots, 32 threads per row
-        if constexpr (!kOrdered) {
+        if constexpr (kOrdered) {
+            // the waves' partials of each (j, lane), added in wave order
+            for (int e = tid; e < kJC * 64; e += TPB) {
+                double v = 0.0;
 #pragma unroll
-            for (int r0 = 0; r0 < kJC; r0 += TPB / 32) {
-                const int row = r0 + (tid >> 5), c = tid & 31;
-                // whole 32-lane groups drop out together, so the shuffles
-                // stay inside groups that are all active
-                if (row < kJC) {
-                    double v = s.pj[row][c] + s.pj[row][c + 32];
+                for (int w = 0; w < Shape::NW; ++w) v += pjl[w * kJC * 64 + e];
+                s.pj[e / 64][e % 64] = v;
+            }
+            __syncthreads();
+        }
+        // Phi_j of the chunk: 16 rows of 64 slots, 32 threads per row (a
+        // fixed order: the two halves of a row, then a butterfly)
 #pragma unroll
-                    for (int m = 16; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-                    if (c == 0) s.pjacc[jc * kJC + row] = v;
-                }
+        for (int r0 = 0; r0 < kJC; r0 += TPB / 32) {
+            const int row = r0 + (tid >> 5), c = tid & 31;
+            // whole 32-lane groups drop out together, so the shuffles stay
+            // inside groups that are all active
+            if (row < kJC) {
+                double v = s.pj[row][c] + s.pj[row][c + 32];
+#pragma unroll
+                for (int m = 16; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+                if (c == 0) s.pjacc[jc * kJC + row] = v;
             }
         }
     }
@@ -497,8 +504,7 @@ __device__ __forceinline__ void tile_unit(DirectLds<T, JB, Shape> &s, const doub
                 for (int w = 0; w < NW; ++w) v += s.kw[w][e];
                 phi[IB + JB + e] = ix.rk(e) >= 0 ? v * out_scale : 0.0;
             } else {
-#pragma unroll
-                for (int w = 0; w < NW; ++w) v += s.pjw[w][e - kKT];
+                v = s.pjacc[e - kKT];
                 phi[IB + e - kKT] = ix.rj(e - kKT) >= 0 ? v * out_scale : 0.0;
             }
         }
@@ -526,14 +532,15 @@ __device__ __forceinline__ void tile_unit(DirectLds<T, JB, Shape> &s, const doub
 
 // One unit (I block a, J block b, K tile t) of the exhaustive sum over the
 // input order; ublk is the (i, j) table block of (a, b).  kOrdered: phi is
-// the unit's row (tile_unit).
+// the unit's row and pjl the per-wave LDS slots (tile_unit).
 template <typename T, typename TabPtr = const T *, bool kOrdered = false>
 __device__ __forceinline__ void direct_unit(DirectLds<T> &s, const double *__restrict__ x, int n,
                                             int a, int b, int t, TabPtr ublk, double scale,
-                                            double out_scale, double *__restrict__ phi) {
+                                            double out_scale, double *__restrict__ phi,
+                                            double *__restrict__ pjl = nullptr) {
     const BlockIndex<DirectLds<T>::IB, kB, DirectLds<T>::KT> ix(n, a, b, t);
     tile_unit<T, kB, DirectShape<T>, BlockIndex<DirectLds<T>::IB, kB, DirectLds<T>::KT>, TabPtr,
-              kOrdered>(s, x, ix, ublk, scale, out_scale, phi);
+              kOrdered>(s, x, ix, ublk, scale, out_scale, phi, pjl);
 }
 
 }  // namespace
