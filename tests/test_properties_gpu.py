@@ -1,7 +1,10 @@
-"""Property tests of the exhaustive sum on random small point sets
-(hypothesis, N from 3 to 64): every path against the binary64 oracle, and the
+"""Property tests on random small point sets (hypothesis): the exhaustive
+sum (N from 3 to 64) on every path against the binary64 oracle, and the
 symmetries of Phi - permutation equivariance, invariance under rotation and
-translation, and homogeneity of degree -9 under scaling by 2^k.
+translation, and homogeneity of degree -9 under scaling by 2^k; the
+triple-tree traversal (N up to 300, any leaf size) exact at eps = 0 and
+within its deterministic bound (alpha = 0, Theorem 5.1) at every point for
+eps > 0, with every triple covered exactly once.
 
 Error scale: a particle's bar is relative to M_i = sum over its triangles of
 |phi| (the size of the terms being summed; Phi_i itself may cancel):
@@ -99,3 +102,25 @@ def test_symmetries(case, k, data, cuda):
         # Phi(2^k x) = 2^(-9k) Phi(x): every pair term scales by a power of two
         s = 2.0 ** k
         assert np.all(np.abs(gpu(x * s, path, cuda) * s ** 9 - base) <= 1e-14 * mag)
+
+
+@SETTINGS
+@given(kind=st.sampled_from(["lattice", "cube", "ball"]), n=st.integers(3, 300),
+       seed=st.integers(0, 2 ** 31 - 1), leaf=st.sampled_from([1, 2, 5, 16, 32]),
+       eps=st.sampled_from([0.0, 1e-2, 0.1]))
+def test_traversal_properties(kind, n, seed, leaf, eps, cuda):
+    import torch
+
+    import paper_1105_2769_amd as mb
+
+    x = points(kind, n, seed)
+    print(f"properties: traversal {kind} N={n} seed={seed} leaf={leaf} eps={eps}", flush=True)
+    ref = oracle.phi(x)
+    mag = magnitude(x)
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to(cuda)
+    phi, st_, cov = mb.eval_multitree(xt, eps=eps, alpha=0.0, leaf_size=leaf, coverage=True,
+                                      base_prec="fp64")
+    bar = eps * np.abs(ref) + 1e-12 * mag
+    ratio = np.abs(phi.cpu().numpy() - ref) / bar
+    assert np.all(cov.cpu().numpy() == (n - 1) * (n - 2) // 2)
+    assert np.all(ratio <= 1.0), float(ratio.max())
