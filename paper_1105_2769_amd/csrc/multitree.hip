@@ -330,18 +330,44 @@ __device__ __forceinline__ void emit_children(const NodeView &nv, const Item &it
     }
 }
 
-// 1. classification of the popped triples
-__global__ __launch_bounds__(256) void classify_kernel(
-    const Item *__restrict__ items, int n_items, NodeView nv, NodeStats ns,
-    double *__restrict__ node_acc, double *__restrict__ node_lo, double *__restrict__ node_hi,
-    unsigned long long *__restrict__ node_cov, MtConst k, MtCounters *__restrict__ ctr,
-    Item *__restrict__ mc_list, Item *__restrict__ base_list, Item *__restrict__ child_buf,
+// A slot of a list for every lane of the wave with `want`, by one atomic
+// per wave: the lanes that ask are numbered in lane order from the count the
+// first of them takes.  Every lane of the wave calls it (convergent); the
+// result is meaningful only where want is true.
+__device__ __forceinline__ unsigned long long wave_append(unsigned long long *counter, bool want) {
+    const unsigned long long mask = __ballot(want);
+    if (mask == 0) return 0;
+    const int lane = threadIdx.x & 63;
+    const int first = __ffsll((long long)mask) - 1;
+    unsigned long long base = 0;
+    if (lane == first) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)base, first);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(base >> 32), first);
+    base = ((unsigned long long)hi << 32) | lo;
+    return base + (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull));
+}
+
+// counter += the sum of v over the lanes of the wave, by one atomic per
+// wave (every lane calls it)
+__device__ __forceinline__ void wave_add(unsigned long long *counter, unsigned long long v) {
+    const unsigned long long mask = __ballot(v != 0);
+    if (mask == 0) return;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    if ((threadIdx.x & 63) == __ffsll((long long)mask) - 1) atomicAdd(counter, v);
+}
+
+// What classification decided for a triple; the list appends are made by
+// the caller, a wave at a time.
+enum Outcome : int { kNone, kSplit, kDeferred, kFar, kPruned, kToMc, kToBase };
+
+// 1. classification of one popped triple (slot `slot` of the round)
+__device__ __forceinline__ int classify_one(
+    Item &it, int slot, const NodeView &nv, const NodeStats &ns, double *__restrict__ node_acc,
+    double *__restrict__ node_lo, double *__restrict__ node_hi,
+    unsigned long long *__restrict__ node_cov, const MtConst &k, Item *__restrict__ child_buf,
     uint8_t *__restrict__ child_flag, double spread_limit, Item *__restrict__ defer_buf,
-    uint8_t *__restrict__ defer_flag, FarItem *__restrict__ far_list) {
-    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot >= n_items) return;
-    Item it = items[slot];
-    it.slot = slot;
+    uint8_t *__restrict__ defer_flag, double &far_lo, double &far_hi) {
     for (int q = 0; q < 8; ++q) child_flag[8 * slot + q] = 0;
     defer_flag[slot] = 0;
     const int p1 = it.p1, p2 = it.p2, p3 = it.p3;
@@ -365,7 +391,7 @@ __global__ __launch_bounds__(256) void classify_kernel(
     if (fmax(d12, fmax(d13, d23)) > spread_limit) {
         defer_buf[slot] = it;
         defer_flag[slot] = 1;
-        return;
+        return kDeferred;
     }
 
     // bounds on phi over the triple: no two points are closer than r_min, so
@@ -389,10 +415,11 @@ __global__ __launch_bounds__(256) void classify_kernel(
         for (int q = 0; q < 3; ++q)
             allow = fmin(allow, certified(k, ns, r.node[q], (double)r.t[q], phi_lo, phi_hi));
         if (phi_hi - phi_lo <= (k.eps * allow + k.tau) / k.t_root) {
-            if (k.order >= 1 && well_separated(nv, p1, p2, p3)) {
+            const bool far = k.order >= 1 && well_separated(nv, p1, p2, p3);
+            if (far) {
                 // the far-field expansion at each point (far_kernel)
-                const unsigned long long pos = atomicAdd(&ctr->n_far, 1ull);
-                far_list[pos] = FarItem{p1, p2, p3, 0, phi_lo, phi_hi};
+                far_lo = phi_lo;
+                far_hi = phi_hi;
             } else {
                 // monopole estimate at the centroids, kept inside the bound interval
                 double phic =
@@ -406,8 +433,7 @@ __global__ __launch_bounds__(256) void classify_kernel(
                 atomicAdd(&node_hi[r.node[q]], (double)r.t[q] * phi_hi);
                 if (k.want_cov) atomicAdd(&node_cov[r.node[q]], (unsigned long long)r.t[q]);
             }
-            atomicAdd(&ctr->det_prunes, 1ull);
-            return;
+            return far ? kFar : kPruned;
         }
     }
     // Monte Carlo candidate.  A point can pass the stop rule only if its
@@ -426,19 +452,40 @@ __global__ __launch_bounds__(256) void classify_kernel(
             if (k.two_sided) best = fmax(fmax(best, ns.neg[v] - t * phi_lo), ns.mix[v]);
             can_pass = k.eps * best + k.tau >= 0.0;
         }
-        if (can_pass) {
-            const unsigned long long pos = atomicAdd(&ctr->n_mc, 1ull);
-            mc_list[pos] = it;
-            return;
-        }
+        if (can_pass) return kToMc;
     }
     const bool all_leaves = nv.left[p1] < 0 && nv.left[p2] < 0 && nv.left[p3] < 0;
-    if (all_leaves) {
-        const unsigned long long pos = atomicAdd(&ctr->n_base, 1ull);
-        base_list[pos] = it;
-        return;
-    }
+    if (all_leaves) return kToBase;
     emit_children(nv, it, slot, child_buf, child_flag);
+    return kSplit;
+}
+
+__global__ __launch_bounds__(256) void classify_kernel(
+    const Item *__restrict__ items, int n_items, NodeView nv, NodeStats ns,
+    double *__restrict__ node_acc, double *__restrict__ node_lo, double *__restrict__ node_hi,
+    unsigned long long *__restrict__ node_cov, MtConst k, MtCounters *__restrict__ ctr,
+    Item *__restrict__ mc_list, Item *__restrict__ base_list, Item *__restrict__ child_buf,
+    uint8_t *__restrict__ child_flag, double spread_limit, Item *__restrict__ defer_buf,
+    uint8_t *__restrict__ defer_flag, FarItem *__restrict__ far_list) {
+    const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+    int outcome = kNone;
+    Item it{};
+    double far_lo = 0.0, far_hi = 0.0;
+    if (slot < n_items) {
+        it = items[slot];
+        it.slot = slot;
+        outcome = classify_one(it, slot, nv, ns, node_acc, node_lo, node_hi, node_cov, k,
+                               child_buf, child_flag, spread_limit, defer_buf, defer_flag, far_lo,
+                               far_hi);
+    }
+    // list appends and the prune count, one atomic per wave each
+    const unsigned long long pf = wave_append(&ctr->n_far, outcome == kFar);
+    if (outcome == kFar) far_list[pf] = FarItem{it.p1, it.p2, it.p3, 0, far_lo, far_hi};
+    const unsigned long long pm = wave_append(&ctr->n_mc, outcome == kToMc);
+    if (outcome == kToMc) mc_list[pm] = it;
+    const unsigned long long pb = wave_append(&ctr->n_base, outcome == kToBase);
+    if (outcome == kToBase) base_list[pb] = it;
+    wave_add(&ctr->det_prunes, outcome == kPruned || outcome == kFar ? 1ull : 0ull);
 }
 
 // Philox4x32-10 (Salmon et al., SC'11): 10 rounds of two 32x32 -> 64-bit
@@ -995,31 +1042,33 @@ __global__ void leaf_keys_kernel(const Item *__restrict__ base_list, int cap, No
                                  unsigned long long *__restrict__ node_cov,
                                  unsigned long long *__restrict__ keys, int *__restrict__ vals) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= cap) return;
     const int n_base = (int)ctr->n_base;
-    if (e >= n_base) {
+    unsigned long long tri = 0;
+    if (e < cap && e >= n_base) {
         keys[e] = ~0ull;
         vals[e] = -1;
-        return;
+    } else if (e < cap) {
+        const Item it = base_list[e];
+        keys[e] = (unsigned long long)it.p1 * (unsigned long long)M + (unsigned long long)it.p2;
+        vals[e] = it.p3;
+        const int64_t n1 = nv.end[it.p1] - nv.begin[it.p1],
+                      n2 = nv.end[it.p2] - nv.begin[it.p2],
+                      n3 = nv.end[it.p3] - nv.begin[it.p3];
+        const char cs = canonical_case(it.p1, it.p2, it.p3);
+        if (cs == 'a') tri = (unsigned long long)(n1 * (n1 - 1) * (n1 - 2) / 6);
+        else if (cs == 'b') tri = (unsigned long long)(comb2(n1) * n3);
+        else if (cs == 'c') tri = (unsigned long long)(n1 * comb2(n2));
+        else tri = (unsigned long long)(n1 * n2 * n3);
+        if (k.want_cov) {
+            const Roles r = roles_of(it.p1, it.p2, it.p3, n1, n2, n3);
+            for (int q = 0; q < r.n_roles; ++q)
+                atomicAdd(&node_cov[r.node[q]], (unsigned long long)r.t[q]);
+        }
     }
-    const Item it = base_list[e];
-    keys[e] = (unsigned long long)it.p1 * (unsigned long long)M + (unsigned long long)it.p2;
-    vals[e] = it.p3;
-    const int64_t n1 = nv.end[it.p1] - nv.begin[it.p1], n2 = nv.end[it.p2] - nv.begin[it.p2],
-                  n3 = nv.end[it.p3] - nv.begin[it.p3];
-    const char cs = canonical_case(it.p1, it.p2, it.p3);
-    unsigned long long tri;
-    if (cs == 'a') tri = (unsigned long long)(n1 * (n1 - 1) * (n1 - 2) / 6);
-    else if (cs == 'b') tri = (unsigned long long)(comb2(n1) * n3);
-    else if (cs == 'c') tri = (unsigned long long)(n1 * comb2(n2));
-    else tri = (unsigned long long)(n1 * n2 * n3);
-    atomicAdd(&ctr->base_cases, 1ull);
-    atomicAdd(&ctr->base_triples, tri);
-    if (k.want_cov) {
-        const Roles r = roles_of(it.p1, it.p2, it.p3, n1, n2, n3);
-        for (int q = 0; q < r.n_roles; ++q)
-            atomicAdd(&node_cov[r.node[q]], (unsigned long long)r.t[q]);
-    }
+    // the base-case statistics, one atomic per wave each (every lane here)
+    const bool real = e < cap && e < n_base;
+    wave_add(&ctr->base_cases, real ? 1ull : 0ull);
+    wave_add(&ctr->base_triples, tri);
 }
 
 // Units from the sorted keys: each run of equal (P1, P2) is cut into full
