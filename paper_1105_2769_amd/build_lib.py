@@ -3,7 +3,9 @@
 Every translation unit is compiled with hipcc for gfx950 only.  Packed FP32
 instructions are disabled for device code (``-packed-fp32-ops``); FP64
 atomics are emitted as hardware instructions (``-munsafe-fp-atomics``, the
-library only uses them on coarse-grained device memory).
+library only uses them on coarse-grained device memory).  Clang's
+thread-safety analysis is on and its findings are errors: members of the
+serving code marked as guarded by a mutex are only touched with it held.
 """
 from __future__ import annotations
 
@@ -28,6 +30,10 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
     "-Wno-unused-result",
+    # lock discipline of the server's shared state (annotations in
+    # csrc/lock_check.hpp), checked at compile time
+    "-Wthread-safety",
+    "-Werror=thread-safety",
 ]
 
 

@@ -18,6 +18,7 @@
 // scheduler thread enqueues those and polls per-slot events, so it never
 // blocks on the device.
 #include "direct_tile.hpp"
+#include "lock_check.hpp"
 #include "mb_internal.hpp"
 #include "serve_ring.hpp"
 #include "serve_sched.hpp"
@@ -455,7 +456,7 @@ public:
 
     ~Server() {
         {
-            std::lock_guard<std::mutex> g(mu_);
+            Lock g(mu_);
             stop_ = true;
         }
         cv_work_.notify_all();
@@ -492,7 +493,7 @@ public:
         r->n = n;
         r->prec_req = r->prec = prec;
         r->t_submit = now_s();
-        std::lock_guard<std::mutex> g(mu_);
+        Lock g(mu_);
         if (broken_) return fail(MB_ERR_DEVICE, "server stopped after a device error: " + broken_msg_);
         r->id = next_id_++;
         *id = r->id;
@@ -514,7 +515,7 @@ public:
     }
 
     mb_status poll(int64_t id, double *out, int32_t *done) {
-        std::lock_guard<std::mutex> g(mu_);
+        Lock g(mu_);
         auto it = reqs_.find(id);
         if (it == reqs_.end()) return fail(MB_ERR_INVALID, "unknown request id");
         Request &r = *it->second;
@@ -531,8 +532,8 @@ public:
     }
 
     mb_status wait(int64_t id, int32_t timeout_ms, int32_t *done) {
-        std::unique_lock<std::mutex> g(mu_);
-        auto ready = [&] {
+        Lock g(mu_);
+        auto ready = [&]() MB_REQUIRES(mu_) {
             if (id < 0) return stats_.completed + stats_.failed == stats_.submitted;
             auto it = reqs_.find(id);
             return it == reqs_.end() || it->second->done;
@@ -540,17 +541,17 @@ public:
         if (id >= 0 && reqs_.find(id) == reqs_.end()) return fail(MB_ERR_INVALID, "unknown request id");
         bool ok;
         if (timeout_ms < 0) {
-            cv_done_.wait(g, ready);
+            cv_done_.wait(g.native(), ready);
             ok = true;
         } else {
-            ok = cv_done_.wait_for(g, std::chrono::milliseconds(timeout_ms), ready);
+            ok = cv_done_.wait_for(g.native(), std::chrono::milliseconds(timeout_ms), ready);
         }
         if (done) *done = ok ? 1 : 0;
         return MB_OK;
     }
 
     mb_status latency(int64_t id, double *sec) {
-        std::lock_guard<std::mutex> g(mu_);
+        Lock g(mu_);
         auto it = reqs_.find(id);
         if (it == reqs_.end()) return fail(MB_ERR_INVALID, "unknown request id");
         if (!it->second->done) return fail(MB_ERR_INVALID, "request not finished");
@@ -559,13 +560,13 @@ public:
     }
 
     void get_stats(mb_server_stats *out) {
-        std::lock_guard<std::mutex> g(mu_);
+        Lock g(mu_);
         *out = stats_;
     }
 
     // The scheduler thread carries the cancellation out (cancel_one).
     mb_status cancel(int64_t id) {
-        std::lock_guard<std::mutex> g(mu_);
+        Lock g(mu_);
         auto it = reqs_.find(id);
         if (it == reqs_.end()) return fail(MB_ERR_INVALID, "unknown request id");
         if (!it->second->done) {
@@ -576,14 +577,14 @@ public:
     }
 
     mb_status set_timeout(int32_t ms) {
-        std::lock_guard<std::mutex> g(mu_);
+        Lock g(mu_);
         timeout_ms_ = ms > 0 ? ms : 0;
         return MB_OK;
     }
 
     mb_status set_slice_units(int64_t u) {
         if (u < 1) return fail(MB_ERR_INVALID, "slice_units < 1");
-        std::lock_guard<std::mutex> g(mu_);
+        Lock g(mu_);
         slice_request_ = std::min<int64_t>(u, kMaxSliceUnits);
         return MB_OK;
     }
@@ -611,13 +612,13 @@ private:
     };
 
     Request &req(int64_t id) {
-        std::lock_guard<std::mutex> g(mu_);
+        Lock g(mu_);
         return *reqs_.at(id);
     }
 
     // Mark a request finished (result or error) and wake waiters.
     void complete(Request &r, mb_status st, const std::string &msg) {
-        std::lock_guard<std::mutex> g(mu_);
+        Lock g(mu_);
         r.status = st;
         r.msg = msg;
         r.t_done = now_s();
@@ -692,7 +693,7 @@ private:
         if (r.prec == MB_FP32C) {
             if (!fp32c_suitable(v, n)) {
                 r.prec = MB_FP64;
-                std::lock_guard<std::mutex> g(mu_);
+                Lock g(mu_);
                 stats_.fp64_fallbacks += 1;
             } else {
                 r.scale = unit_scale(md2);
@@ -756,7 +757,7 @@ private:
                 }
             }
             {
-                std::lock_guard<std::mutex> g(mu_);
+                Lock g(mu_);
                 stats_.slices += 1;
                 if (sl.ranges.size() > 1) stats_.mixed_slices += 1;
             }
@@ -801,7 +802,7 @@ private:
         if (refused) return fail(MB_ERR_DEVICE, "the drain kernel refused an item out of range");
         if (n_done) {
             units_done_ += n_done;
-            std::lock_guard<std::mutex> g(mu_);
+            Lock g(mu_);
             stats_.units += n_done;
         }
         return MB_OK;
@@ -862,7 +863,7 @@ private:
                                               dim3(512), args, 0, cs_));
             MB_HIP(hipEventRecord(ev_k1_, cs_));
             running_ = true;
-            std::lock_guard<std::mutex> g(mu_);
+            Lock g(mu_);
             stats_.drain_launches += 1;
         }
         return MB_OK;
@@ -904,7 +905,7 @@ private:
         pinned_.put(r.pin_x);  // the points' copy has long landed
         r.pin_x = nullptr;
         if (flagged) {
-            std::lock_guard<std::mutex> g(mu_);
+            Lock g(mu_);
             stats_.points_fp64 += flagged;
         }
         MB_HIP(hipFreeAsync(r.chunk, as_));
@@ -946,7 +947,7 @@ private:
 
     mb_status step(std::vector<int64_t> &finished, bool &idle) {
         {
-            std::lock_guard<std::mutex> g(mu_);
+            Lock g(mu_);
             if (slice_request_ > 0) {
                 sched_.set_slice_units(slice_request_);
                 slice_request_ = 0;
@@ -973,7 +974,7 @@ private:
         {  // wall time with units outstanding on the device
             const double t = now_s();
             if (book_.outstanding() > 0 && t_last_ > 0.0) {
-                std::lock_guard<std::mutex> g(mu_);
+                Lock g(mu_);
                 stats_.busy_ms += (t - t_last_) * 1e3;
             }
             t_last_ = t;
@@ -1071,7 +1072,7 @@ private:
             sched_.start(id, r.units, r.keep);
         }
         {
-            std::lock_guard<std::mutex> g(mu_);
+            Lock g(mu_);
             stats_.finalize_ms += (t1 - t0) * 1e3;
             stats_.stage_ms += (now_s() - t1) * 1e3;
         }
@@ -1083,7 +1084,7 @@ private:
         if (tr_.on) trace_line(idle);
         if (!idle) std::this_thread::sleep_for(std::chrono::microseconds(10));
         {
-            std::lock_guard<std::mutex> g(mu_);
+            Lock g(mu_);
             stats_.peak_reserved = sched_.peak_reserved();
             stats_.peak_active = sched_.peak_active();
         }
@@ -1130,10 +1131,10 @@ private:
                 return;
             }
             if (idle) {
-                std::unique_lock<std::mutex> g(mu_);
+                Lock g(mu_);
                 if (inbox_.empty()) {
                     if (stop_ && sched_.idle()) return;
-                    cv_work_.wait_for(g, std::chrono::milliseconds(2));
+                    cv_work_.wait_for(g.native(), std::chrono::milliseconds(2));
                 }
             }
         }
@@ -1141,7 +1142,7 @@ private:
 
     // A device error ends the server: every unfinished request fails.
     void break_all(const std::string &msg) {
-        std::lock_guard<std::mutex> g(mu_);
+        Lock g(mu_);
         broken_ = true;
         broken_msg_ = msg;
         for (auto &kv : reqs_) {
@@ -1195,17 +1196,20 @@ private:
     PinnedPool pinned_;                 // scheduler thread only
     std::thread thread_;
 
-    std::mutex mu_;  // guards everything below
+    // Shared between the callers' threads and the scheduler thread: only
+    // with mu_ held (checked by the compiler's thread-safety analysis).
+    Mutex mu_;
     std::condition_variable cv_work_, cv_done_;
-    std::map<int64_t, std::unique_ptr<Request>> reqs_;
-    std::vector<int64_t> inbox_;
-    std::vector<std::pair<int64_t, std::string>> cancels_;
-    int32_t timeout_ms_ = 0;
-    int64_t next_id_ = 0;
-    int64_t slice_request_ = 0;
-    bool stop_ = false, broken_ = false;
-    std::string broken_msg_;
-    mb_server_stats stats_{};
+    std::map<int64_t, std::unique_ptr<Request>> reqs_ MB_GUARDED_BY(mu_);
+    std::vector<int64_t> inbox_ MB_GUARDED_BY(mu_);
+    std::vector<std::pair<int64_t, std::string>> cancels_ MB_GUARDED_BY(mu_);
+    int32_t timeout_ms_ MB_GUARDED_BY(mu_) = 0;
+    int64_t next_id_ MB_GUARDED_BY(mu_) = 0;
+    int64_t slice_request_ MB_GUARDED_BY(mu_) = 0;
+    bool stop_ MB_GUARDED_BY(mu_) = false;
+    bool broken_ MB_GUARDED_BY(mu_) = false;
+    std::string broken_msg_ MB_GUARDED_BY(mu_);
+    mb_server_stats stats_ MB_GUARDED_BY(mu_){};
 };
 
 }  // namespace
