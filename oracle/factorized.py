@@ -81,11 +81,3 @@ def phi(x: np.ndarray, r_near: float = 0.0) -> np.ndarray:
     if r_near <= 0.0:
         return far
     return far + direct.phi_split(x, r_near, far=False)
-
-
-def cancellation(x: np.ndarray, r_near: float = 0.0) -> np.ndarray:
-    """kappa_i = sum_t |c_t T_t(i)| / |sum_t c_t T_t(i)| of the product form."""
-    t = term_sums(x, r_near)
-    num = sum(abs(c) * np.abs(ti) for ((_, c), ti) in zip(TERMS, t))
-    den = np.abs(sum(c * ti for ((_, c), ti) in zip(TERMS, t)))
-    return num / den
