@@ -504,7 +504,7 @@ __global__ __launch_bounds__(256) void near_triples_kernel(
             if (lane == 0) atomicAdd(&pair_sum[q], s);
         }
         __syncthreads();
-        if (threadIdx.x < cnt) {
+        if ((int)threadIdx.x < cnt) {
             const int2 pr = pairs[pbase + threadIdx.x];
             const double s = pair_sum[threadIdx.x];
             if (s != 0.0) {
