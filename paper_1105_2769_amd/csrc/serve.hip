@@ -31,7 +31,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <deque>
+#include <queue>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -385,6 +385,7 @@ struct Request {
     mb_status status = MB_OK;
     std::string msg;
     double t_submit = 0.0, t_done = 0.0;
+    int32_t timeout_ms = 0;  // the server's time limit when it was submitted (0: none)
     bool done = false, fetched = false;
     // device side, owned by the scheduler thread
     void *chunk = nullptr;
@@ -496,6 +497,7 @@ public:
         Lock g(mu_);
         if (broken_) return fail(MB_ERR_DEVICE, "server stopped after a device error: " + broken_msg_);
         r->id = next_id_++;
+        r->timeout_ms = timeout_ms_;
         *id = r->id;
         stats_.submitted += 1;
         if (n < 3) {  // the empty sum
@@ -953,21 +955,22 @@ private:
                 slice_request_ = 0;
             }
             for (int64_t id : inbox_) {
-                sched_.enqueue(id, footprint(reqs_.at(id)->n));
-                if (timeout_ms_ > 0)
-                    deadlines_.push_back(Deadline{reqs_.at(id)->t_submit + 1e-3 * timeout_ms_, id,
-                                                  timeout_ms_});
+                const Request &r = *reqs_.at(id);
+                sched_.enqueue(id, footprint(r.n));
+                if (r.timeout_ms > 0)
+                    deadlines_.push(Deadline{r.t_submit + 1e-3 * r.timeout_ms, id, r.timeout_ms});
             }
             inbox_.clear();
             cancel_work_.swap(cancels_);
         }
-        // time-outs (one limit at a time, so deadlines come in submission
-        // order), then cancellations
-        for (const double t = now_s(); !deadlines_.empty() && deadlines_.front().t <= t;) {
-            cancel_work_.emplace_back(deadlines_.front().id, "timed out after " +
-                                                            std::to_string(deadlines_.front().ms) +
-                                                            " ms");
-            deadlines_.pop_front();
+        // time-outs (earliest deadline first; requests submitted under
+        // different limits reach theirs out of submission order), then
+        // cancellations
+        for (const double t = now_s(); !deadlines_.empty() && deadlines_.top().t <= t;) {
+            cancel_work_.emplace_back(deadlines_.top().id, "timed out after " +
+                                                              std::to_string(deadlines_.top().ms) +
+                                                              " ms");
+            deadlines_.pop();
         }
         for (const auto &c : cancel_work_) cancel_one(c.first, c.second);
         cancel_work_.clear();
@@ -1189,7 +1192,11 @@ private:
         int64_t id;
         int32_t ms;
     };
-    std::deque<Deadline> deadlines_;                             // scheduler thread only
+    struct LaterDeadline {
+        bool operator()(const Deadline &a, const Deadline &b) const { return a.t > b.t; }
+    };
+    // earliest deadline on top; scheduler thread only
+    std::priority_queue<Deadline, std::vector<Deadline>, LaterDeadline> deadlines_;
     std::vector<std::pair<int64_t, std::string>> cancel_work_;  // scheduler thread only
     std::vector<ServeDesc> desc_host_;  // per slot, written at staging
     std::vector<uint32_t> gen_;         // per slot: generation of its current request

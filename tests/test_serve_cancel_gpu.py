@@ -93,6 +93,31 @@ def test_timeout(cuda):
     assert st["cancelled"] == 1 and st["completed"] == 1
 
 
+def test_limit_is_the_one_at_submission(cuda):
+    # a request keeps the limit in force when it was submitted, whatever the
+    # server's limit is by the time its scheduler thread takes it in; and a
+    # short limit set after a long one ends its request at its own deadline,
+    # not behind the earlier request's later one
+    import paper_1105_2769_amd as mb
+
+    big = workloads.jittered_lattice(20000, seed=73)
+    print("serving: limits fixed at submission", flush=True)
+    with server() as srv:
+        srv.set_timeout(60_000)
+        a = srv.submit(big)
+        srv.set_timeout(20)
+        b = srv.submit(big)
+        srv.set_timeout(0)
+        assert srv.wait(-1, 120_000)
+        np.testing.assert_allclose(srv.result(a), one_shot(big, cuda), rtol=1e-12)
+        with pytest.raises(mb.MBError) as e:
+            srv.result(b)
+        assert e.value.status == CANCELLED and "timed out after 20 ms" in e.value.msg
+        assert srv.latency(b) < srv.latency(a)
+        st = srv.stats()
+    assert st["cancelled"] == 1 and st["completed"] == 1
+
+
 def test_random_cancels_rest_correct(cuda):
     import paper_1105_2769_amd as mb
 
