@@ -121,7 +121,11 @@ mb_status mb_eval_direct(const double *x, int64_t n, int32_t prec, double *phi, 
  *                   (pair-term table plus unit rows, 2 KiB per work unit of
  *                   64 x 64 x 128 slots); <= 0 means MB_TABLE_BUDGET_MB.
  *                   The J blocks are taken in stripes that fit it, at least
- *                   one block of 64 per stripe; stripes run in order.
+ *                   one block of 64 per stripe; stripes run in order.  A
+ *                   one-block stripe still holds up to about N^2 / 32768
+ *                   units (N^2 / 16 bytes of rows, 62.5 GB at N = 10^6),
+ *                   which bounds this mode by device memory, not by
+ *                   scratch_bytes.
  *
  * Validation, errors and the N < 3 case are those of mb_eval_direct; waits
  * on `stream` for the validation, then enqueues the sum.  MB_ERR_OOM if the
