@@ -22,6 +22,10 @@ Extra fields:
   cpu_baseline - the CPU oracle timed on the host's cores on a bounded
                  sample of the same workload (a few particles' full sums);
                  its values also give the accuracy check above.
+  fixed_order  - the fixed-order binary64 sum (mb_eval_direct_deterministic)
+                 on the same points: time per call against the atomic
+                 binary64 step, bitwise repeatability of two calls, and the
+                 largest relative difference from the atomic result.
   latency      - the serving loop on a Poisson trace: 4096 requests at
                  200 requests/s (trace seed 5), N log-uniform in [64, 8192],
                  request r the jittered lattice of N points with seed
@@ -107,6 +111,8 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=4096,
                     help="requests of the serving trace (0: skip the serving leg)")
     ap.add_argument("--no-factorized", action="store_true")
+    ap.add_argument("--no-fixed-order", action="store_true",
+                    help="skip the fixed-order (bitwise-reproducible) binary64 sum")
     ap.add_argument("--no-paper", action="store_true",
                     help="skip the paper's own workloads (Tables 1-3 settings) on the traversal")
     ap.add_argument("--multitree-n", type=int, default=262144,
@@ -222,6 +228,8 @@ def main() -> int:
             results[prec]["rel_all"] = float(r_all.max())
             results[prec]["frac_above_1e6"] = float(np.mean(r_all > 1e-6))
 
+    fixed_order = fixed_order_leg(x, results["fp64"]["phi"], results["fp64"]["step_s"]) \
+        if "fp64" in results and not args.no_fixed_order else None
     latency = serve_leg(args.serve_requests, dev) if args.serve_requests else None
     multitree = multitree_leg(args.multitree_n, dev, not args.no_multitree_extra) \
         if args.multitree_n else None
@@ -261,6 +269,7 @@ def main() -> int:
                      "kernel": "direct_kernel", "kernel_ms": r["kern_s"] * 1e3},
         "cpu_baseline": cpu,
         "latency": latency,
+        "fixed_order": fixed_order,
         "multitree": multitree,
         "factorized": factorized,
         "paper_workloads": paper,
@@ -550,6 +559,35 @@ def paper_leg(dev) -> dict:
                       f"{r['exhaustive_fraction']:.3f}, within {r['within_pct']:.1f} %", flush=True)
         out["speedups"][name] = sp
     return out
+
+
+def fixed_order_leg(x, phi_atomic, atomic_step_s: float, steps: int = 2) -> dict:
+    """The fixed-order binary64 sum (mb_eval_direct_deterministic) on the
+    headline points: whole-call time (validation included, as the atomic
+    path's step), bitwise repeatability, and its distance from the atomic
+    path's result of the same run."""
+    import numpy as np
+    import torch
+
+    import paper_1105_2769_amd as mb
+
+    print("fixed order: warmup", flush=True)
+    first = mb.eval_direct_deterministic(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        again = mb.eval_direct_deterministic(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    a = first.cpu().numpy()
+    b = again.cpu().numpy()
+    same = bool(np.array_equal(a.view(np.uint64), b.view(np.uint64)))
+    rel = float(np.max(np.abs(a - phi_atomic) / np.abs(phi_atomic)))
+    print(f"fixed order: {dt * 1e3:.1f} ms per call (atomic fp64 step "
+          f"{atomic_step_s * 1e3:.1f} ms), bitwise repeat {same}, max rel diff vs atomic "
+          f"{rel:.2e}", flush=True)
+    return {"ms": dt * 1e3, "atomic_fp64_step_ms": atomic_step_s * 1e3,
+            "bitwise_repeat": same, "max_rel_diff_vs_atomic": rel}
 
 
 def factorized_leg(dev, n: int = 16384, steps: int = 3) -> dict:
